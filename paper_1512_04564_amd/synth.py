@@ -1,0 +1,242 @@
+"""Seeded synthetic fan-beam CT scans: random-ellipse phantoms, analytic sinograms, noise and weights.
+
+This module is the only code shared by the HIP path's callers and the CPU oracle's tests. It simulates
+the *scanner*, not the reconstruction method: it holds no projector, regularizer or update arithmetic.
+Its sinograms are exact line integrals through ellipses (averaged over sub-rays per detector bin), so
+they carry no discretisation of the reconstruction grid ("no inverse crime").
+
+Geometry conventions (shared by every consumer; the reconstruction grid only matters for `truth`):
+
+* Image ``[ny][nx]`` row-major; pixel ``(i, j)`` is centred at
+  ``x_j = (j - (nx-1)/2) dx``, ``y_i = (i - (ny-1)/2) dy`` (mm).
+* View ``v`` has angle ``beta_v = beta0 + span * v / nviews``; central direction ``d = (cos b, sin b)``,
+  detector axis ``e = (-sin b, cos b)``; the source sits at ``S = -dso d``.
+* Detector bin boundaries ``u_k = (k - nb/2 + u_offset) du`` for ``k = 0..nb``. Flat detector: the point
+  at coordinate ``u`` is ``(dsd - dso) d + u e``. Arc detector: angle ``u/dsd`` about the source at radius
+  ``dsd``.
+
+The workload recipe follows the paper's XCAT acquisition (888 channels, 984 views, 541/949 mm source
+distances, 1e5 incident photons; Section "XCAT phantom") reduced to a 2-D fan beam, with seeded ellipses
+standing in for the XCAT phantom and the clinical scans, which are not available.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+__all__ = [
+    "ScanGeometry", "CFG1", "CFG2", "BATCH_CLASSES", "fov_radius", "random_ellipses", "phantom_image",
+    "ray_points", "analytic_sinogram", "noisy_scan", "Scan", "MU_WATER",
+]
+
+MU_WATER = 0.02  # mm^-1; 1000 HU.  The HU scale puts air at 0.
+
+
+@dataclasses.dataclass(frozen=True)
+class ScanGeometry:
+    nx: int
+    ny: int
+    dx: float
+    dy: float
+    nb: int
+    du: float
+    u_offset: float
+    det: str            # "flat" or "arc"
+    nviews: int
+    beta0: float
+    span: float
+    dso: float
+    dsd: float
+    nsubsets: int
+
+    def replace(self, **kw) -> "ScanGeometry":
+        return dataclasses.replace(self, **kw)
+
+
+#: 128x128 at 1 mm, flat 256 x 1 mm detector, 220 views over 360 deg, 10 subsets.
+CFG1 = ScanGeometry(128, 128, 1.0, 1.0, 256, 1.0, 0.0, "flat", 220, 0.0, 2 * math.pi, 541.0, 949.0, 10)
+#: 512x512 at 0.98 mm, flat 888 x 1.0239 mm detector, 984 views over 360 deg, 41 subsets.
+CFG2 = ScanGeometry(512, 512, 0.98, 0.98, 888, 1.0239, 0.0, "flat", 984, 0.0, 2 * math.pi, 541.0, 949.0, 41)
+
+
+def _batch_class(n: int, nv: int, nb: int) -> ScanGeometry:
+    # Constant ~500 mm field: pixel and bin sizes scale from the 512^2 / 0.98 mm / 888-bin class.
+    scale = 512.0 / n
+    return ScanGeometry(n, n, 0.98 * scale, 0.98 * scale, nb, 1.0239 * 888.0 / nb, 0.0, "flat", nv, 0.0,
+                        2 * math.pi, 541.0, 949.0, 41)
+
+
+#: The three slice classes of the uneven batch: 256^2/492 views/444 bins, 384^2/738/666, 512^2/984/888.
+BATCH_CLASSES = (_batch_class(256, 492, 444), _batch_class(384, 738, 666), _batch_class(512, 984, 888))
+
+
+def fov_radius(g: ScanGeometry) -> float:
+    """Radius (mm) of the disk seen by every view: the fan's half-angle seen from the source."""
+    half = 0.5 * g.nb * g.du
+    gam = math.atan(half / g.dsd) if g.det == "flat" else half / g.dsd
+    return g.dso * math.sin(gam)
+
+
+def _view_frame(g: ScanGeometry, v):
+    beta = g.beta0 + g.span * np.asarray(v, dtype=np.float64) / g.nviews
+    c, s = np.cos(beta), np.sin(beta)
+    return c, s
+
+
+def ray_points(g: ScanGeometry, v, u):
+    """Source point and detector point (both ``[..., 2]``, mm) for views ``v`` and detector coords ``u``.
+
+    ``v`` and ``u`` broadcast against each other.
+    """
+    c, s = _view_frame(g, v)
+    u = np.asarray(u, dtype=np.float64)
+    c, s, u = np.broadcast_arrays(c, s, u)
+    src = np.stack([-g.dso * c, -g.dso * s], axis=-1)
+    if g.det == "flat":
+        off = g.dsd - g.dso
+        det = np.stack([off * c - u * s, off * s + u * c], axis=-1)
+    elif g.det == "arc":
+        gam = u / g.dsd
+        dirx = np.cos(gam) * c - np.sin(gam) * s
+        diry = np.cos(gam) * s + np.sin(gam) * c
+        det = src + g.dsd * np.stack([dirx, diry], axis=-1)
+    else:
+        raise ValueError(f"unknown detector shape {g.det!r}")
+    return src, det
+
+
+@dataclasses.dataclass
+class Ellipse:
+    cx: float
+    cy: float
+    a: float
+    b: float
+    phi: float
+    mu: float       # additive value (mm^-1)
+
+
+def random_ellipses(g: ScanGeometry, seed: int, n: int = 8, *, rng: np.random.Generator | None = None):
+    """Body ellipse plus ``n-1`` disjoint inserts, all inside the field of view.
+
+    Every object pixel ends up in [0.01, 0.04] mm^-1 (inserts are stored as contrast to the body).
+    """
+    rng = rng if rng is not None else np.random.Generator(np.random.PCG64(seed))
+    rf = fov_radius(g)
+    ell = []
+    cx, cy = rng.uniform(-0.05, 0.05, 2) * rf
+    a, b = rng.uniform(0.55, 0.80, 2) * rf
+    phi = rng.uniform(0.0, math.pi)
+    mu_body = rng.uniform(0.015, 0.025)
+    body = Ellipse(cx, cy, a, b, phi, mu_body)
+    ell.append(body)
+    shrink = 2.0 * max(g.dx, g.dy)
+    circles = []
+    tries = 0
+    while len(ell) < n:
+        tries += 1
+        if tries > 20000:
+            raise RuntimeError("could not place ellipses")
+        ea, eb = rng.uniform(0.04, 0.20, 2) * rf
+        ephi = rng.uniform(0.0, math.pi)
+        mu = rng.uniform(0.01, 0.04)
+        # candidate centre uniformly inside the body's bounding box
+        ecx = cx + rng.uniform(-1, 1) * max(a, b)
+        ecy = cy + rng.uniform(-1, 1) * max(a, b)
+        rad = max(ea, eb)
+        t = np.linspace(0, 2 * math.pi, 72, endpoint=False)
+        px, py = ecx + rad * np.cos(t), ecy + rad * np.sin(t)
+        if not np.all(_inside(px, py, cx, cy, a - shrink, b - shrink, phi)):
+            continue
+        if any(math.hypot(ecx - ox, ecy - oy) < rad + orad for ox, oy, orad in circles):
+            continue
+        circles.append((ecx, ecy, rad))
+        ell.append(Ellipse(ecx, ecy, ea, eb, ephi, mu - mu_body))
+    return ell
+
+
+def _inside(px, py, cx, cy, a, b, phi):
+    c, s = math.cos(phi), math.sin(phi)
+    dx, dy = px - cx, py - cy
+    xr = c * dx + s * dy
+    yr = -s * dx + c * dy
+    return (xr / a) ** 2 + (yr / b) ** 2 <= 1.0
+
+
+def phantom_image(g: ScanGeometry, ellipses, supersample: int = 4) -> np.ndarray:
+    """Pixel-averaged phantom on the reconstruction grid (``[ny][nx]`` float64, mm^-1)."""
+    ss = supersample
+    off = (np.arange(ss) + 0.5) / ss - 0.5
+    xs = ((np.arange(g.nx) - (g.nx - 1) / 2.0)[:, None] * g.dx + off[None, :] * g.dx).reshape(-1)
+    ys = ((np.arange(g.ny) - (g.ny - 1) / 2.0)[:, None] * g.dy + off[None, :] * g.dy).reshape(-1)
+    X, Y = np.meshgrid(xs, ys)
+    img = np.zeros_like(X)
+    for e in ellipses:
+        img += e.mu * _inside(X, Y, e.cx, e.cy, e.a, e.b, e.phi)
+    return img.reshape(g.ny, ss, g.nx, ss).mean(axis=(1, 3))
+
+
+def _chords(src, det, ellipses):
+    """Sum over ellipses of mu * (length of the line src->det inside the ellipse)."""
+    d = det - src
+    d = d / np.linalg.norm(d, axis=-1, keepdims=True)
+    total = np.zeros(src.shape[:-1])
+    for e in ellipses:
+        c, s = math.cos(e.phi), math.sin(e.phi)
+        px, py = src[..., 0] - e.cx, src[..., 1] - e.cy
+        qx = (c * px + s * py) / e.a
+        qy = (-s * px + c * py) / e.b
+        rx = (c * d[..., 0] + s * d[..., 1]) / e.a
+        ry = (-s * d[..., 0] + c * d[..., 1]) / e.b
+        A = rx * rx + ry * ry
+        B = 2.0 * (qx * rx + qy * ry)
+        C = qx * qx + qy * qy - 1.0
+        disc = B * B - 4.0 * A * C
+        total += e.mu * np.sqrt(np.maximum(disc, 0.0)) / A
+    return total
+
+
+def analytic_sinogram(g: ScanGeometry, ellipses, subrays: int = 4, views=None) -> np.ndarray:
+    """Exact ellipse line integrals, averaged over ``subrays`` equally spaced rays per bin.
+
+    Returns ``[nviews][nb]`` float64 (dimensionless) for all views, or for the listed ``views``.
+    """
+    v = np.arange(g.nviews) if views is None else np.asarray(views)
+    k = np.arange(g.nb)
+    sub = (np.arange(subrays) + 0.5) / subrays
+    u = ((k[:, None] + sub[None, :]) - g.nb / 2.0 + g.u_offset) * g.du      # [nb][subrays]
+    out = np.empty((len(v), g.nb))
+    for a in range(0, len(v), 64):
+        vv = v[a:a + 64]
+        src, det = ray_points(g, vv[:, None, None], u[None, :, :])
+        out[a:a + 64] = _chords(src, det, ellipses).mean(axis=-1)
+    return out
+
+
+@dataclasses.dataclass
+class Scan:
+    geom: ScanGeometry
+    seed: int
+    y: np.ndarray        # [nviews][nb] float32 post-log sinogram
+    w: np.ndarray        # [nviews][nb] float32 statistical weights
+    truth: np.ndarray    # [ny][nx] float64 supersampled phantom (mm^-1)
+    line_integrals: np.ndarray  # [nviews][nb] float64 noise-free sinogram
+    ellipses: list
+
+
+def noisy_scan(g: ScanGeometry, seed: int, *, i0: float = 1e5, sigma: float = 5.0, n_ellipses: int = 8,
+               truth: bool = True) -> Scan:
+    """One seeded scan: Poisson(I0 e^-l) + N(0, sigma^2) counts, clamped at 1, log, weights Y^2/(Y+25).
+
+    ``y`` and ``w`` are rounded to float32; every consumer (GPU path and oracle) reads the same values.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ell = random_ellipses(g, seed, n_ellipses, rng=rng)
+    li = analytic_sinogram(g, ell)
+    counts = rng.poisson(i0 * np.exp(-li)).astype(np.float64) + rng.normal(0.0, sigma, li.shape)
+    counts = np.maximum(counts, 1.0)
+    y = np.log(i0 / counts).astype(np.float32)
+    w = (counts * counts / (counts + sigma * sigma)).astype(np.float32)
+    img = phantom_image(g, ell) if truth else None
+    return Scan(g, seed, y, w, img, li, ell)
