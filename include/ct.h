@@ -1,0 +1,162 @@
+/*
+ * ct.h -- C ABI of libctrlalm: relaxed OS-LALM (OS-RLALM) for 2-D fan-beam PWLS X-ray CT on AMD gfx950.
+ *
+ * The library solves the penalized weighted-least-squares problem of Nien & Fessler, "Relaxed linearized
+ * algorithms for faster X-ray CT image reconstruction" (Section III, eq. ct_problem):
+ *
+ *     x_hat = argmin_{x in Omega}  1/2 || y - A x ||_W^2 + R(x),       Omega = { x >= 0 }
+ *
+ * with the edge-preserving regularizer of eq. def_reg (four directions, eight neighbours), by
+ * Algorithm 1 ("proposed (over-)relaxed OS-LALM", Section III-A) with the alpha-dependent continuation
+ * rho_k(alpha) of eq. dec_rho (Section III-B). A is a matched distance-driven fan-beam projector (the
+ * paper cites but does not define its projector); A' is its exact transpose up to summation order.
+ *
+ * Conventions shared by every entry point:
+ *   - Images are float32, [ny][nx] row-major. Pixel (i, j) is centred at
+ *     x_j = (j - (nx-1)/2) dx, y_i = (i - (ny-1)/2) dy  (mm); values are attenuation in mm^-1.
+ *   - Sinograms are [view][bin], acquisition order. View v has angle beta0 + span * v / nviews, the
+ *     source sits at -dso (cos b, sin b); bin k spans detector coordinates
+ *     [(k - nb/2 + u_offset) du, (k + 1 - nb/2 + u_offset) du] along (-sin b, cos b).
+ *   - Subset m of M is the interleaved view set { v : v mod M == m } (nviews % M == 0 is required);
+ *     its sinogram block is [nviews/M][nb] in ascending view order. subset = -1 means all views.
+ *   - Every data pointer is a DEVICE pointer owned by the caller (e.g. a torch tensor's data_ptr()).
+ *     `stream` is a hipStream_t (NULL = the null stream). Calls are stream-ordered and asynchronous
+ *     unless stated otherwise.
+ *   - Every call returns a ct_status; no exception crosses the ABI. On an argument error nothing is
+ *     launched and outputs are untouched. ct_last_error() returns a thread-local message for the last
+ *     non-OK status.
+ */
+#ifndef CTRLALM_CT_H
+#define CTRLALM_CT_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CT_OK = 0,
+    CT_ERR_INVALID_ARG = 1,
+    CT_ERR_OOM = 2,
+    CT_ERR_HIP = 3,
+    CT_ERR_UNSUPPORTED = 4,
+    CT_ERR_DIVERGED = 5
+} ct_status;
+
+typedef enum { CT_DET_FLAT = 0, CT_DET_ARC = 1 } ct_detector;
+
+/* Storage type of the sinogram inputs y and w (the image state is always float32). */
+typedef enum { CT_F32 = 0, CT_F16 = 1, CT_BF16 = 2 } ct_dtype;
+
+typedef struct {
+    int nx, ny;          /* image size (pixels), each in [1, 4096]                                  */
+    double dx, dy;       /* pixel size (mm), > 0                                                     */
+    int nb;              /* detector bins, in [1, 8192]                                              */
+    double du;           /* bin width at the detector (mm), > 0                                      */
+    double u_offset;     /* detector offset in bins (0 = centred)                                    */
+    int det;             /* ct_detector: flat, or arc centred on the source                          */
+    int nviews;          /* projection views, >= 1                                                   */
+    double beta0, span;  /* first view angle and angular span (rad); views at beta0 + span v / nviews */
+    double dso, dsd;     /* source-isocentre and source-detector distances (mm), dsd > dso > 0      */
+    int nsubsets;        /* M >= 1, nviews % M == 0                                                  */
+    int storage;         /* ct_dtype of y and w passed to the solver                                 */
+} ct_geom_desc;
+
+typedef struct ct_geom ct_geom; /* opaque: device geometry tables + solver workspace */
+
+/*
+ * Build the per-view geometry tables (FP64 on the host, stored FP32 on the current device) and the
+ * subset tables. The handle owns them until ct_geom_destroy. The solver workspace inside the handle
+ * is allocated on first use; solves on one handle must not overlap in time.
+ * Errors: CT_ERR_INVALID_ARG for an inconsistent descriptor (sizes, distances, nviews % M), CT_ERR_OOM,
+ * CT_ERR_HIP.
+ */
+ct_status ct_geom_create(const ct_geom_desc *desc, ct_geom **out);
+void ct_geom_destroy(ct_geom *g);
+
+/*
+ * p = A_m x : distance-driven forward projection of the float32 image x ([ny][nx]) for subset m
+ * (p is [nviews/M][nb]) or for all views when subset == -1 (p is [nviews][nb]). p is overwritten.
+ * Projection is the operation inside the subset gradient of Algorithm 1 (Section III-A).
+ */
+ct_status ct_forward(const ct_geom *g, int subset, const float *x, float *p, void *stream);
+
+/*
+ * x = A_m' r : matched distance-driven back-projection (gather form, no atomics) of the float32
+ * sinogram block r for subset m ([nviews/M][nb]) or all views (subset == -1, [nviews][nb]).
+ * x ([ny][nx]) is overwritten.
+ */
+ct_status ct_back(const ct_geom *g, int subset, const float *r, float *x, void *stream);
+
+/* Subset processing order (the paper leaves it open). */
+typedef enum { CT_ORDER_SEQUENTIAL = 0, CT_ORDER_BITREV = 1 } ct_subset_order;
+
+typedef struct {
+    double alpha;        /* relaxation, 1 <= alpha < 2; alpha = 1 is unrelaxed OS-LALM              */
+    int niters;          /* outer iterations; each is M subiterations (one full projection pair)     */
+    int rho_mode;        /* 0: continuation rho_k(alpha) with k the subiteration count, 1: fixed    */
+    double rho_fixed;    /* rho when rho_mode == 1, > 0                                              */
+    int potential;       /* 0: hyperbola d^2 (sqrt(1 + (t/d)^2) - 1), 1: Fair d^2 (|t/d| - log(1+|t/d|)) */
+    double delta, beta;  /* potential scale (mm^-1) and regularization strength; beta_i = beta/|s_i| */
+    int huber;           /* 1: Huber curvature for D_R (the paper's choice), 0: maximum curvature   */
+    int algorithm;       /* 1: Algorithm 1 (proposed relaxation), 2: Algorithm 2 (simple relaxation) */
+    int subset_order;    /* ct_subset_order                                                          */
+    int kappa;           /* 0: kappa = 1; 1: certainty weights kappa_j = sqrt(A'w / A'1)             */
+    int start;           /* 0: x holds x0 on entry; 1: zero image                                    */
+    int init_full;       /* 0: initial gradient from the last subset (Algorithm 1 as written);
+                            1: full gradient                                                         */
+    double dl_scale;     /* multiplies D_L (1 = the majorizer diag{A'WA1})                            */
+    const float *x_ref;  /* optional device reference image for the trace (NULL = none)              */
+    double mu_water;     /* HU scale of the trace: HU = 1000 mu / mu_water (air = 0)                  */
+    double fov_radius;   /* trace RMSD region: pixel centres within this radius (mm); <= 0: image    */
+    int use_graph;       /* 1: replay one captured hipGraph per iteration; 0: plain launches          */
+} ct_rlalm_params;
+
+/* Fill p with the defaults: alpha 1.999, 20 iterations, continuation, hyperbola delta 1e-4 beta 1024,
+   Huber curvature, Algorithm 1, sequential order, kappa off, start 0, last-subset init, D_L scale 1,
+   no trace reference, mu_water 0.02, whole image, graph on. */
+void ct_rlalm_params_default(ct_rlalm_params *p);
+
+typedef struct {
+    int iter;            /* outer iteration count after which the row was taken                      */
+    double seconds;      /* host wall time since the solve call started (synchronised)               */
+    double rmsd_hu;      /* RMSD to x_ref in HU over the trace region (FP64 reduction on the device) */
+    double rho;          /* rho of the last subiteration of that iteration                           */
+    int finite;          /* 1 when x, g and h were all finite                                        */
+} ct_trace_row;
+
+/*
+ * Whole solve (Algorithm 1 or 2): D_L = diag{A'WA1} (Section III-A), optional certainty weights,
+ * initialisation on the last subset, then niters * M subiterations with rho_k(alpha).
+ * y, w: [nviews][nb] in the geometry's storage type. x: float32 [ny][nx]; on entry x0 (start == 0),
+ * on exit x^(niters). trace: NULL, or niters rows (the call then synchronises once per iteration).
+ * Returns CT_ERR_DIVERGED when a non-finite value appears (checked at the end, and per iteration
+ * when tracing); x then holds the last iterate computed.
+ */
+ct_status ct_rlalm_solve(ct_geom *g, const ct_rlalm_params *p, const void *y, const void *w, float *x,
+                         ct_trace_row *trace, void *stream);
+
+/*
+ * Low-level state interface (checkpoint / resume). The state after t subiterations is (x, g, h, t);
+ * rho and the subset follow from t. dl and kappa are the solve constants.
+ *
+ * ct_rlalm_prepare: dl = dl_scale * A'(w .* A 1) over all views; kappa (if non-NULL and p->kappa)
+ *   = sqrt(A'w / A'1). Both [ny][nx] float32, caller-owned.
+ * ct_rlalm_init: x = max(x, 0); zeta = g = M grad L_{M-1}(x) (or the full gradient), h = D_L x - zeta
+ *   (Algorithm 1) or h = zeta (Algorithm 2). This is the t = 0 state.
+ * ct_rlalm_iterate: advance the state by nsub subiterations starting at subiteration t0.
+ */
+ct_status ct_rlalm_prepare(ct_geom *g, const ct_rlalm_params *p, const void *w, float *dl, float *kappa,
+                           void *stream);
+ct_status ct_rlalm_init(ct_geom *g, const ct_rlalm_params *p, const void *y, const void *w, const float *dl,
+                        float *x, float *gv, float *h, void *stream);
+ct_status ct_rlalm_iterate(ct_geom *g, const ct_rlalm_params *p, const void *y, const void *w, const float *dl,
+                           const float *kappa, float *x, float *gv, float *h, long long t0, long long nsub,
+                           void *stream);
+
+/* Thread-local message describing the last non-OK status of a call made on this thread. */
+const char *ct_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CTRLALM_CT_H */

@@ -1,0 +1,86 @@
+"""ctypes binding to libctrlalm.so (the C ABI of include/ct.h).
+
+Argument marshalling only: every step of the reconstruction runs in the library's HIP kernels. Tensors
+are torch CUDA (HIP) tensors; their data pointers and torch's current stream are passed through.
+The binding raises if the shared library is missing or fails to load -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libctrlalm.so")
+
+CT_OK, CT_ERR_INVALID_ARG, CT_ERR_OOM, CT_ERR_HIP, CT_ERR_UNSUPPORTED, CT_ERR_DIVERGED = range(6)
+STATUS_NAMES = {0: "CT_OK", 1: "CT_ERR_INVALID_ARG", 2: "CT_ERR_OOM", 3: "CT_ERR_HIP", 4: "CT_ERR_UNSUPPORTED",
+                5: "CT_ERR_DIVERGED"}
+
+#: Every entry point declared in include/ct.h.
+EXPORTS = ("ct_geom_create", "ct_geom_destroy", "ct_forward", "ct_back", "ct_rlalm_params_default",
+           "ct_rlalm_solve", "ct_rlalm_prepare", "ct_rlalm_init", "ct_rlalm_iterate", "ct_last_error")
+
+
+class GeomDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+                ("nb", ctypes.c_int), ("du", ctypes.c_double), ("u_offset", ctypes.c_double), ("det", ctypes.c_int),
+                ("nviews", ctypes.c_int), ("beta0", ctypes.c_double), ("span", ctypes.c_double),
+                ("dso", ctypes.c_double), ("dsd", ctypes.c_double), ("nsubsets", ctypes.c_int),
+                ("storage", ctypes.c_int)]
+
+
+class RlalmParams(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("niters", ctypes.c_int), ("rho_mode", ctypes.c_int),
+                ("rho_fixed", ctypes.c_double), ("potential", ctypes.c_int), ("delta", ctypes.c_double),
+                ("beta", ctypes.c_double), ("huber", ctypes.c_int), ("algorithm", ctypes.c_int),
+                ("subset_order", ctypes.c_int), ("kappa", ctypes.c_int), ("start", ctypes.c_int),
+                ("init_full", ctypes.c_int), ("dl_scale", ctypes.c_double), ("x_ref", ctypes.c_void_p),
+                ("mu_water", ctypes.c_double), ("fov_radius", ctypes.c_double), ("use_graph", ctypes.c_int)]
+
+
+class TraceRow(ctypes.Structure):
+    _fields_ = [("iter", ctypes.c_int), ("seconds", ctypes.c_double), ("rmsd_hu", ctypes.c_double),
+                ("rho", ctypes.c_double), ("finite", ctypes.c_int)]
+
+
+class CtError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libctrlalm.so (raises FileNotFoundError / OSError when it is absent or broken)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FileNotFoundError(f"{LIB_PATH} is missing: build it with paper_1512_04564_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, ll = ctypes.c_void_p, ctypes.c_int, ctypes.c_longlong
+    L.ct_geom_create.argtypes = [ctypes.POINTER(GeomDesc), ctypes.POINTER(vp)]
+    L.ct_geom_destroy.argtypes = [vp]
+    L.ct_geom_destroy.restype = None
+    L.ct_forward.argtypes = [vp, i, vp, vp, vp]
+    L.ct_back.argtypes = [vp, i, vp, vp, vp]
+    L.ct_rlalm_params_default.argtypes = [ctypes.POINTER(RlalmParams)]
+    L.ct_rlalm_params_default.restype = None
+    L.ct_rlalm_solve.argtypes = [vp, ctypes.POINTER(RlalmParams), vp, vp, vp, ctypes.POINTER(TraceRow), vp]
+    L.ct_rlalm_prepare.argtypes = [vp, ctypes.POINTER(RlalmParams), vp, vp, vp, vp]
+    L.ct_rlalm_init.argtypes = [vp, ctypes.POINTER(RlalmParams), vp, vp, vp, vp, vp, vp, vp]
+    L.ct_rlalm_iterate.argtypes = [vp, ctypes.POINTER(RlalmParams), vp, vp, vp, vp, vp, vp, vp, ll, ll, vp]
+    L.ct_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("ct_geom_destroy", "ct_rlalm_params_default", "ct_last_error"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(status: int) -> None:
+    if status != CT_OK:
+        msg = load().ct_last_error()
+        raise CtError(status, msg.decode() if msg else "")

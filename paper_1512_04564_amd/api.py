@@ -1,0 +1,196 @@
+"""Python front end of libctrlalm: geometry handles, projections and the relaxed OS-LALM solver.
+
+Same names as the C ABI (include/ct.h) minus the ``ct_`` prefix. Images are float32 CUDA tensors
+``[ny][nx]``; sinograms are float32 CUDA tensors ``[views][nb]``. Work is enqueued on torch's current
+stream (or the stream passed in). Nothing here computes: it checks shapes and forwards pointers.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+
+import torch
+
+from . import _lib
+from ._lib import CtError, GeomDesc, RlalmParams, TraceRow, check
+
+__all__ = ["Geometry", "Params", "forward", "back", "rlalm_solve", "rlalm_prepare", "rlalm_init", "rlalm_iterate",
+           "CtError"]
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _ptr(t: torch.Tensor, *, shape=None, name="tensor", dtype=torch.float32) -> int:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t.data_ptr()
+
+
+class Geometry:
+    """Owning wrapper of a ``ct_geom`` handle (device tables + solver workspace)."""
+
+    def __init__(self, geom, storage: int = 0):
+        self.desc_py = geom
+        det = {"flat": 0, "arc": 1}[geom.det] if isinstance(geom.det, str) else int(geom.det)
+        d = GeomDesc(geom.nx, geom.ny, geom.dx, geom.dy, geom.nb, geom.du, geom.u_offset, det, geom.nviews,
+                     geom.beta0, geom.span, geom.dso, geom.dsd, geom.nsubsets, storage)
+        self._lib = _lib.load()
+        h = ctypes.c_void_p()
+        check(self._lib.ct_geom_create(ctypes.byref(d), ctypes.byref(h)))
+        self.handle = h
+        self.nx, self.ny, self.nb, self.nviews, self.nsubsets = geom.nx, geom.ny, geom.nb, geom.nviews, geom.nsubsets
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            self._lib.ct_geom_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def views_in(self, subset: int) -> int:
+        return self.nviews if subset == -1 else self.nviews // self.nsubsets
+
+    @property
+    def img_shape(self):
+        return (self.ny, self.nx)
+
+
+@dataclasses.dataclass
+class Params:
+    alpha: float = 1.999
+    niters: int = 20
+    rho_mode: str = "continuation"   # or "fixed"
+    rho_fixed: float = 0.05
+    potential: str = "hyperbola"     # or "fair"
+    delta: float = 1e-4
+    beta: float = 1024.0
+    huber: bool = True
+    algorithm: int = 1
+    subset_order: str = "sequential"  # or "bitrev"
+    kappa: bool = False
+    start: str = "given"             # or "zero"
+    init_full: bool = False
+    dl_scale: float = 1.0
+    mu_water: float = 0.02
+    fov_radius: float = 0.0
+    use_graph: bool = True
+
+    def to_c(self, x_ref: torch.Tensor | None = None) -> RlalmParams:
+        p = RlalmParams()
+        _lib.load().ct_rlalm_params_default(ctypes.byref(p))
+        p.alpha = self.alpha
+        p.niters = self.niters
+        p.rho_mode = {"continuation": 0, "fixed": 1}[self.rho_mode]
+        p.rho_fixed = self.rho_fixed
+        p.potential = {"hyperbola": 0, "fair": 1}[self.potential]
+        p.delta = self.delta
+        p.beta = self.beta
+        p.huber = int(self.huber)
+        p.algorithm = self.algorithm
+        p.subset_order = {"sequential": 0, "bitrev": 1}[self.subset_order]
+        p.kappa = int(self.kappa)
+        p.start = {"given": 0, "zero": 1}[self.start]
+        p.init_full = int(self.init_full)
+        p.dl_scale = self.dl_scale
+        p.x_ref = x_ref.data_ptr() if x_ref is not None else None
+        p.mu_water = self.mu_water
+        p.fov_radius = self.fov_radius
+        p.use_graph = int(self.use_graph)
+        return p
+
+
+def forward(g: Geometry, x: torch.Tensor, subset: int = -1, out: torch.Tensor | None = None, stream=None):
+    """A_m x (subset m) or A x (subset -1): ``[views][nb]`` float32."""
+    nv = g.views_in(subset)
+    if out is None:
+        out = torch.empty((nv, g.nb), dtype=torch.float32, device=x.device)
+    check(g._lib.ct_forward(g.handle, subset, _ptr(x, shape=g.img_shape, name="x"),
+                            _ptr(out, shape=(nv, g.nb), name="out"), _stream_handle(stream)))
+    return out
+
+
+def back(g: Geometry, r: torch.Tensor, subset: int = -1, out: torch.Tensor | None = None, stream=None):
+    """A_m' r (subset m) or A' r (subset -1): ``[ny][nx]`` float32."""
+    nv = g.views_in(subset)
+    if out is None:
+        out = torch.empty(g.img_shape, dtype=torch.float32, device=r.device)
+    check(g._lib.ct_back(g.handle, subset, _ptr(r, shape=(nv, g.nb), name="r"),
+                         _ptr(out, shape=g.img_shape, name="out"), _stream_handle(stream)))
+    return out
+
+
+def rlalm_solve(g: Geometry, p: Params, y: torch.Tensor, w: torch.Tensor, x: torch.Tensor, *,
+                x_ref: torch.Tensor | None = None, trace: bool = False, stream=None):
+    """Run the whole solve in place on ``x``. Returns the trace rows (list of dicts) when ``trace``."""
+    sino = (g.nviews, g.nb)
+    cp = p.to_c(x_ref)
+    if x_ref is not None:
+        _ptr(x_ref, shape=g.img_shape, name="x_ref")
+    rows = (TraceRow * max(p.niters, 1))() if trace else None
+    st = g._lib.ct_rlalm_solve(g.handle, ctypes.byref(cp), _ptr(y, shape=sino, name="y"),
+                               _ptr(w, shape=sino, name="w"), _ptr(x, shape=g.img_shape, name="x"),
+                               rows, _stream_handle(stream))
+    check(st)
+    if trace:
+        return [dict(iter=r.iter, seconds=r.seconds, rmsd_hu=r.rmsd_hu, rho=r.rho, finite=bool(r.finite))
+                for r in rows[:p.niters]]
+    return None
+
+
+def rlalm_prepare(g: Geometry, p: Params, w: torch.Tensor, dl: torch.Tensor, kappa: torch.Tensor | None = None,
+                  stream=None):
+    cp = p.to_c()
+    check(g._lib.ct_rlalm_prepare(g.handle, ctypes.byref(cp), _ptr(w, shape=(g.nviews, g.nb), name="w"),
+                                  _ptr(dl, shape=g.img_shape, name="dl"),
+                                  _ptr(kappa, shape=g.img_shape, name="kappa") if kappa is not None else None,
+                                  _stream_handle(stream)))
+
+
+def rlalm_init(g: Geometry, p: Params, y, w, dl, x, gv, h, stream=None):
+    cp = p.to_c()
+    sino = (g.nviews, g.nb)
+    check(g._lib.ct_rlalm_init(g.handle, ctypes.byref(cp), _ptr(y, shape=sino, name="y"),
+                               _ptr(w, shape=sino, name="w"), _ptr(dl, shape=g.img_shape, name="dl"),
+                               _ptr(x, shape=g.img_shape, name="x"), _ptr(gv, shape=g.img_shape, name="g"),
+                               _ptr(h, shape=g.img_shape, name="h"), _stream_handle(stream)))
+
+
+def rlalm_iterate(g: Geometry, p: Params, y, w, dl, x, gv, h, t0: int, nsub: int, kappa=None, stream=None):
+    cp = p.to_c()
+    sino = (g.nviews, g.nb)
+    check(g._lib.ct_rlalm_iterate(g.handle, ctypes.byref(cp), _ptr(y, shape=sino, name="y"),
+                                  _ptr(w, shape=sino, name="w"), _ptr(dl, shape=g.img_shape, name="dl"),
+                                  _ptr(kappa, shape=g.img_shape, name="kappa") if kappa is not None else None,
+                                  _ptr(x, shape=g.img_shape, name="x"), _ptr(gv, shape=g.img_shape, name="g"),
+                                  _ptr(h, shape=g.img_shape, name="h"), int(t0), int(nsub), _stream_handle(stream)))
+
+
+def rho_table(p: Params, n: int):
+    """The continuation values the solver uses (FP64 closed form, Section III-B), for reporting."""
+    out = []
+    for k in range(n):
+        if p.rho_mode == "fixed":
+            out.append(p.rho_fixed)
+        elif k == 0:
+            out.append(1.0)
+        else:
+            a = math.pi / (p.alpha * (k + 1))
+            out.append(a * math.sqrt(1.0 - (a / 2.0) ** 2))
+    return out

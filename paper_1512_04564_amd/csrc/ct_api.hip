@@ -1,0 +1,568 @@
+// C ABI of libctrlalm (include/ct.h): argument checking, workspace, and the relaxed OS-LALM driver.
+//
+// One subiteration is two kernels: the forward projection of subset m(t) with the fused residual
+// epilogue, then the fused back-projection / relaxed-update kernel (dual update of subiteration t and
+// x-step of subiteration t+1). An outer iteration (M subiterations) is captured once as a hipGraph and
+// replayed; the subiteration index is read from a device counter that a one-thread kernel at the end of
+// the graph advances, so one captured graph serves every iteration.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ct_internal.hpp"
+
+namespace ct {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+ct_status fail(ct_status st, const std::string &msg)
+{
+    set_error(msg);
+    return st;
+}
+
+namespace {
+
+template <typename T>
+ct_status dev_alloc(T **p, size_t n)
+{
+    if (*p) return CT_OK;
+    hipError_t e = hipMalloc((void **)p, n * sizeof(T) > 0 ? n * sizeof(T) : sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(e == hipErrorOutOfMemory ? CT_ERR_OOM : CT_ERR_HIP,
+                    std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    return CT_OK;
+}
+
+template <typename T>
+void dev_free(T **p)
+{
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+}
+
+ct_status check_desc(const ct_geom_desc *d)
+{
+    if (!d) return fail(CT_ERR_INVALID_ARG, "desc is NULL");
+    if (d->nx < 1 || d->ny < 1 || d->nx > 4096 || d->ny > 4096) return fail(CT_ERR_INVALID_ARG, "nx, ny must be in [1, 4096]");
+    if (!(d->dx > 0) || !(d->dy > 0) || !(d->du > 0)) return fail(CT_ERR_INVALID_ARG, "dx, dy, du must be > 0");
+    if (d->nb < 1 || d->nb > 8192) return fail(CT_ERR_INVALID_ARG, "nb must be in [1, 8192]");
+    if (d->nviews < 1 || d->nviews > (1 << 20)) return fail(CT_ERR_INVALID_ARG, "nviews must be in [1, 2^20]");
+    if (d->nsubsets < 1 || d->nviews % d->nsubsets != 0)
+        return fail(CT_ERR_INVALID_ARG, "nsubsets must be >= 1 and divide nviews");
+    if (!(d->dso > 0) || !(d->dsd > d->dso)) return fail(CT_ERR_INVALID_ARG, "need dsd > dso > 0");
+    if (d->det != CT_DET_FLAT && d->det != CT_DET_ARC) return fail(CT_ERR_INVALID_ARG, "det must be flat or arc");
+    if (d->storage != CT_F32) return fail(CT_ERR_UNSUPPORTED, "only float32 storage is implemented");
+    double hx = 0.5 * d->nx * d->dx, hy = 0.5 * d->ny * d->dy;
+    if (std::sqrt(hx * hx + hy * hy) >= 0.95 * d->dso)
+        return fail(CT_ERR_INVALID_ARG, "the image must lie well inside the source circle");
+    if (!std::isfinite(d->beta0) || !std::isfinite(d->span) || !std::isfinite(d->u_offset))
+        return fail(CT_ERR_INVALID_ARG, "non-finite angle or offset");
+    // Half the detector's fan must stay below 80 degrees so that boundary rays never run parallel to a line.
+    double half = (0.5 * d->nb + std::fabs(d->u_offset)) * d->du;
+    double gam = d->det == CT_DET_FLAT ? std::atan(half / d->dsd) : half / d->dsd;
+    if (gam > 35.0 * M_PI / 180.0) return fail(CT_ERR_INVALID_ARG, "fan half-angle must be <= 35 degrees");
+    return CT_OK;
+}
+
+ct_status check_params(const ct_rlalm_params *p)
+{
+    if (!p) return fail(CT_ERR_INVALID_ARG, "params is NULL");
+    if (!(p->alpha >= 1.0 && p->alpha < 2.0)) return fail(CT_ERR_INVALID_ARG, "alpha must be in [1, 2)");
+    if (p->niters < 0) return fail(CT_ERR_INVALID_ARG, "niters must be >= 0");
+    if (p->rho_mode != 0 && p->rho_mode != 1) return fail(CT_ERR_INVALID_ARG, "rho_mode must be 0 or 1");
+    if (p->rho_mode == 1 && !(p->rho_fixed > 0)) return fail(CT_ERR_INVALID_ARG, "rho_fixed must be > 0");
+    if (p->potential != 0 && p->potential != 1) return fail(CT_ERR_INVALID_ARG, "potential must be 0 or 1");
+    if (!(p->delta > 0) || !(p->beta >= 0)) return fail(CT_ERR_INVALID_ARG, "need delta > 0, beta >= 0");
+    if (p->algorithm != 1 && p->algorithm != 2) return fail(CT_ERR_INVALID_ARG, "algorithm must be 1 or 2");
+    if (p->subset_order != CT_ORDER_SEQUENTIAL && p->subset_order != CT_ORDER_BITREV)
+        return fail(CT_ERR_INVALID_ARG, "unknown subset order");
+    if (!(p->dl_scale > 0)) return fail(CT_ERR_INVALID_ARG, "dl_scale must be > 0");
+    if (p->start != 0 && p->start != 1) return fail(CT_ERR_INVALID_ARG, "start must be 0 or 1");
+    return CT_OK;
+}
+
+double rho_value(long long k, const ct_rlalm_params *p)
+{
+    if (p->rho_mode == 1) return p->rho_fixed;
+    if (k == 0) return 1.0;
+    double a = M_PI / (p->alpha * (double)(k + 1));
+    double b = M_PI / (2.0 * p->alpha * (double)(k + 1));
+    return a * std::sqrt(1.0 - b * b);
+}
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+ct_status ensure_workspace(ct_geom *g, size_t r_views, size_t rho_len)
+{
+    Workspace &W = g->ws;
+    const ct_geom_desc &d = g->desc;
+    const size_t npix = (size_t)d.nx * d.ny;
+    W.npix = npix;
+    CT_TRY(dev_alloc(&W.xa, npix));
+    CT_TRY(dev_alloc(&W.xb, npix));
+    CT_TRY(dev_alloc(&W.xta, npix));
+    CT_TRY(dev_alloc(&W.xtb, npix));
+    CT_TRY(dev_alloc(&W.tmp, npix));
+    CT_TRY(dev_alloc(&W.tbase, 4));
+    CT_TRY(dev_alloc(&W.red, 3 + 3 * 256 + 8));
+    const size_t need_r = r_views * (size_t)d.nb;
+    if (need_r > W.r_cap) {
+        dev_free(&W.r);
+        CT_TRY(dev_alloc(&W.r, need_r));
+        W.r_cap = need_r;
+    }
+    if (rho_len > W.rho_cap) {
+        dev_free(&W.rho);
+        CT_TRY(dev_alloc(&W.rho, rho_len));
+        W.rho_cap = rho_len;
+    }
+    return CT_OK;
+}
+
+void free_workspace(ct_geom *g)
+{
+    Workspace &W = g->ws;
+    dev_free(&W.xa);
+    dev_free(&W.xb);
+    dev_free(&W.xta);
+    dev_free(&W.xtb);
+    dev_free(&W.tmp);
+    dev_free(&W.r);
+    dev_free(&W.rho);
+    dev_free(&W.tbase);
+    dev_free(&W.red);
+    dev_free(&W.dl);
+    dev_free(&W.kappa);
+    dev_free(&W.gv);
+    dev_free(&W.h);
+    W.r_cap = W.rho_cap = 0;
+}
+
+}  // namespace ct
+
+using namespace ct;
+
+// ------------------------------------------------------------------------------------------------
+// Graph cache: one executable graph per (ping-pong parity) for a given set of pointers and params.
+// ------------------------------------------------------------------------------------------------
+namespace {
+
+bool params_equal(const ct_rlalm_params &a, const ct_rlalm_params &b)
+{
+    return a.alpha == b.alpha && a.rho_mode == b.rho_mode && a.rho_fixed == b.rho_fixed &&
+           a.potential == b.potential && a.delta == b.delta && a.beta == b.beta && a.huber == b.huber &&
+           a.algorithm == b.algorithm && a.subset_order == b.subset_order && a.kappa == b.kappa;
+}
+
+bool key_equal(const GraphKey &a, const GraphKey &b)
+{
+    return a.y == b.y && a.w == b.w && a.dl == b.dl && a.kappa == b.kappa && a.gv == b.gv && a.h == b.h &&
+           a.rho == b.rho && a.r == b.r && a.t0mod == b.t0mod && a.parity == b.parity && a.len == b.len &&
+           params_equal(a.p, b.p);
+}
+
+void drop_graph_cache(ct_geom *g)
+{
+    GraphCache &c = g->graphs;
+    for (int i = 0; i < 2; ++i)
+        if (c.exec[i]) (void)hipGraphExecDestroy(c.exec[i]);
+    if (c.cap) (void)hipStreamDestroy(c.cap);
+    c = GraphCache();
+}
+
+struct Ctx {
+    ct_geom *g;
+    const ct_rlalm_params *p;
+    const float *y, *w, *dl, *kappa;
+    float *gv, *h;
+    std::vector<int> order;
+    int M, nvm;
+};
+
+UpdateArgs make_update(const Ctx &c)
+{
+    UpdateArgs U;
+    U.gv = c.gv;
+    U.h = c.h;
+    U.dl = c.dl;
+    U.kappa = c.kappa;
+    U.rho = c.g->ws.rho;
+    U.tbase = c.g->ws.tbase;
+    U.alpha = (float)c.p->alpha;
+    U.algorithm = c.p->algorithm;
+    U.potential = c.p->potential;
+    U.delta = (float)c.p->delta;
+    U.beta_ax = (float)c.p->beta;
+    U.beta_dg = (float)(c.p->beta / std::sqrt(2.0));
+    U.huber = c.p->huber;
+    return U;
+}
+
+// One subiteration t (relative offset tofs from the device counter): FP of subset m(t) on cur, then the
+// fused BP + dual(t) + x-step(t+1) writing nxt.
+hipError_t launch_subiter(const Ctx &c, long long t_abs, long long tofs, int cur_is_a, hipStream_t s)
+{
+    Workspace &W = c.g->ws;
+    const GeomDev &G = c.g->dev;
+    const int m = c.order[(size_t)(t_abs % c.M)];
+    const float *x = cur_is_a ? W.xa : W.xb;
+    const float *xT = cur_is_a ? W.xta : W.xtb;
+    hipError_t e = launch_forward(G, x, xT, 0, m, c.M, c.nvm, FP_RESIDUAL, c.y, c.w, (float)c.M, W.r, s);
+    if (e != hipSuccess) return e;
+    UpdateArgs U = make_update(c);
+    U.x = x;
+    U.x_next = cur_is_a ? W.xb : W.xa;
+    U.xT_next = cur_is_a ? W.xtb : W.xta;
+    U.tofs = tofs;
+    return launch_back_update(G, BP_FULL, W.r, m, c.M, c.nvm, nullptr, U, s);
+}
+
+ct_status upload_rho(ct_geom *g, const ct_rlalm_params *p, long long len, hipStream_t s)
+{
+    std::vector<float> tab((size_t)len);
+    for (long long k = 0; k < len; ++k) tab[(size_t)k] = (float)rho_value(k, p);
+    CT_TRY(ensure_workspace(g, g->desc.nviews, (size_t)len));
+    CT_HIP_CHECK(hipMemcpyAsync(g->ws.rho, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    CT_HIP_CHECK(hipStreamSynchronize(s));  // the host table is about to go out of scope
+    return CT_OK;
+}
+
+// Advance (x in buffer A on entry) from state t0 by nsub subiterations. On exit the buffer holding
+// x^(t0+nsub) is returned through final_is_a.
+ct_status run_subiters(const Ctx &c, long long t0, long long nsub, int use_graph, hipStream_t s, int *final_is_a,
+                       ct_trace_row *trace, const ct_rlalm_params *p, std::chrono::steady_clock::time_point tstart)
+{
+    ct_geom *g = c.g;
+    Workspace &W = g->ws;
+    const GeomDev &G = g->dev;
+    // x-step of subiteration t0 from the state (x^t0 in A): writes x^(t0+1) into B
+    {
+        CT_HIP_CHECK(launch_set_counter(W.tbase, 0, s));
+        UpdateArgs U = make_update(c);
+        U.x = W.xa;
+        U.x_next = W.xb;
+        U.xT_next = W.xtb;
+        U.tofs = t0;
+        CT_HIP_CHECK(launch_back_update(G, BP_XSTEP, nullptr, 0, 1, 0, nullptr, U, s));
+    }
+    int cur_a = 0;  // x^(t0+1) is in B
+    long long t = t0;
+    const long long tend = t0 + nsub;
+    const int M = c.M;
+    // graph length: one iteration, doubled when M is odd so that the ping-pong parity is preserved
+    const int L = (M % 2 == 0) ? M : 2 * M;
+    const bool traced = trace != nullptr;
+    auto trace_point = [&](long long t_done) -> ct_status {
+        // called when t_done subiterations are complete and t_done % M == 0
+        if (!traced || t_done % M != 0 || t_done == 0) return CT_OK;
+        long long it = t_done / M;
+        if (it < 1 || it > p->niters) return CT_OK;
+        // x^(t_done) is the input of the last projection: the "cur" buffer before the last swap
+        const float *xcur = cur_a ? W.xb : W.xa;  // after the swap below, the previous cur is the other one
+        CT_HIP_CHECK(launch_trace_reduce(xcur, p->x_ref, c.gv, c.h, g->desc.nx, g->desc.ny, (float)g->desc.dx,
+                                         (float)g->desc.dy, (float)p->fov_radius, W.red, s));
+        double host[3];
+        CT_HIP_CHECK(hipMemcpyAsync(host, W.red, sizeof(host), hipMemcpyDeviceToHost, s));
+        CT_HIP_CHECK(hipStreamSynchronize(s));
+        ct_trace_row &row = trace[it - 1];
+        row.iter = (int)it;
+        row.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - tstart).count();
+        row.rmsd_hu = (p->x_ref && host[1] > 0) ? 1000.0 / p->mu_water * std::sqrt(host[0] / host[1]) : NAN;
+        row.rho = rho_value(t_done - 1, p);
+        row.finite = host[2] == 0.0;
+        return CT_OK;
+    };
+    auto plain_one = [&]() -> ct_status {
+        CT_HIP_CHECK(launch_set_counter(W.tbase, 0, s));
+        CT_HIP_CHECK(launch_subiter(c, t, t, cur_a, s));
+        cur_a ^= 1;
+        ++t;
+        return trace_point(t);
+    };
+    if (use_graph && nsub >= L) {
+        // plain launches until t is at an iteration boundary relative to t0 (keeps traces aligned)
+        while (t < tend && (t % M) != 0) CT_TRY(plain_one());
+        GraphCache &gc = g->graphs;
+        if (!gc.cap) CT_HIP_CHECK(hipStreamCreateWithFlags(&gc.cap, hipStreamNonBlocking));
+        const int chunk = traced ? M : L;  // traced runs replay per iteration, still needing parity graphs
+        while (tend - t >= chunk) {
+            const int parity = cur_a;
+            GraphKey key{c.y, c.w, c.dl, c.kappa, c.gv, c.h, W.rho, W.r, (int)(t % M), parity, chunk, *p};
+            if (!gc.valid[parity] || !key_equal(gc.key[parity], key)) {
+                if (gc.exec[parity]) (void)hipGraphExecDestroy(gc.exec[parity]);
+                gc.exec[parity] = nullptr;
+                gc.valid[parity] = false;
+                hipGraph_t graph;
+                CT_HIP_CHECK(hipStreamBeginCapture(gc.cap, hipStreamCaptureModeThreadLocal));
+                int ca = parity;
+                hipError_t e = hipSuccess;
+                for (int j = 0; j < chunk && e == hipSuccess; ++j) {
+                    e = launch_subiter(c, t + j, j, ca, gc.cap);
+                    ca ^= 1;
+                }
+                if (e == hipSuccess) e = launch_add_counter(W.tbase, chunk, gc.cap);
+                hipError_t e2 = hipStreamEndCapture(gc.cap, &graph);
+                if (e != hipSuccess) return fail(CT_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+                if (e2 != hipSuccess) return fail(CT_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
+                hipError_t e3 = hipGraphInstantiate(&gc.exec[parity], graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (e3 != hipSuccess) return fail(CT_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e3));
+                gc.key[parity] = key;
+                gc.valid[parity] = true;
+            }
+            CT_HIP_CHECK(launch_set_counter(W.tbase, (int)t, s));
+            CT_HIP_CHECK(hipGraphLaunch(gc.exec[parity], s));
+            if (chunk % 2) cur_a ^= 1;
+            t += chunk;
+            CT_TRY(trace_point(t));
+        }
+    }
+    while (t < tend) CT_TRY(plain_one());
+    // x^(tend) is the input of the last projection
+    *final_is_a = nsub > 0 ? (cur_a ^ 1) : 1;  // with nsub == 0 nothing ran; caller keeps its x
+    if (nsub == 0) *final_is_a = -1;
+    return CT_OK;
+}
+
+Ctx make_ctx(ct_geom *g, const ct_rlalm_params *p, const void *y, const void *w, const float *dl, const float *kappa,
+             float *gv, float *h)
+{
+    Ctx c;
+    c.g = g;
+    c.p = p;
+    c.y = static_cast<const float *>(y);
+    c.w = static_cast<const float *>(w);
+    c.dl = dl;
+    c.kappa = (p->kappa && kappa) ? kappa : nullptr;
+    c.gv = gv;
+    c.h = h;
+    c.M = g->desc.nsubsets;
+    c.nvm = g->desc.nviews / c.M;
+    c.order = subset_order(c.M, p->subset_order);
+    return c;
+}
+
+ct_status do_prepare(ct_geom *g, const ct_rlalm_params *p, const float *w, float *dl, float *kappa, hipStream_t s)
+{
+    CT_TRY(ensure_workspace(g, g->desc.nviews, 4));
+    Workspace &W = g->ws;
+    const GeomDev &G = g->dev;
+    const int nv = g->desc.nviews;
+    const size_t npix = W.npix;
+    // D_L = A' (w .* A 1) over all views
+    CT_HIP_CHECK(launch_forward(G, nullptr, nullptr, 1, 0, 1, nv, FP_WEIGHTED, nullptr, w, 1.f, W.r, s));
+    UpdateArgs U;
+    CT_HIP_CHECK(launch_back_update(G, BP_BACK, W.r, 0, 1, nv, dl, U, s));
+    if (p->dl_scale != 1.0) CT_HIP_CHECK(launch_scale(dl, npix, (float)p->dl_scale, s));
+    if (p->kappa && kappa) {
+        // kappa = sqrt(A'w / A'1)
+        CT_HIP_CHECK(launch_back_update(G, BP_BACK, w, 0, 1, nv, kappa, U, s));
+        CT_HIP_CHECK(launch_fill(W.r, (size_t)nv * g->desc.nb, 1.f, s));
+        CT_HIP_CHECK(launch_back_update(G, BP_BACK, W.r, 0, 1, nv, W.tmp, U, s));
+        CT_HIP_CHECK(launch_kappa(kappa, W.tmp, kappa, npix, s));
+    }
+    return CT_OK;
+}
+
+// x (caller) -> clipped copy in A (+ transpose); then the initial gradient and g, h.
+ct_status do_init(const Ctx &c, const float *x_in, int zero_start, hipStream_t s)
+{
+    ct_geom *g = c.g;
+    Workspace &W = g->ws;
+    const GeomDev &G = g->dev;
+    CT_HIP_CHECK(launch_clip_copy(x_in, W.xa, W.xta, g->desc.nx, g->desc.ny, zero_start, s));
+    UpdateArgs U = make_update(c);
+    U.x = W.xa;
+    if (c.p->init_full) {
+        CT_HIP_CHECK(launch_forward(G, W.xa, W.xta, 0, 0, 1, g->desc.nviews, FP_RESIDUAL, c.y, c.w, 1.f, W.r, s));
+        CT_HIP_CHECK(launch_back_update(G, BP_INIT, W.r, 0, 1, g->desc.nviews, nullptr, U, s));
+    } else {
+        const int m = c.order[(size_t)c.M - 1];
+        CT_HIP_CHECK(launch_forward(G, W.xa, W.xta, 0, m, c.M, c.nvm, FP_RESIDUAL, c.y, c.w, (float)c.M, W.r, s));
+        CT_HIP_CHECK(launch_back_update(G, BP_INIT, W.r, m, c.M, c.nvm, nullptr, U, s));
+    }
+    return CT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ct_last_error(void) { return g_last_error.c_str(); }
+
+void ct_rlalm_params_default(ct_rlalm_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->alpha = 1.999;
+    p->niters = 20;
+    p->rho_mode = 0;
+    p->rho_fixed = 0.05;
+    p->potential = 0;
+    p->delta = 1e-4;
+    p->beta = 1024.0;
+    p->huber = 1;
+    p->algorithm = 1;
+    p->subset_order = CT_ORDER_SEQUENTIAL;
+    p->kappa = 0;
+    p->start = 0;
+    p->init_full = 0;
+    p->dl_scale = 1.0;
+    p->x_ref = nullptr;
+    p->mu_water = 0.02;
+    p->fov_radius = 0.0;
+    p->use_graph = 1;
+}
+
+ct_status ct_geom_create(const ct_geom_desc *desc, ct_geom **out)
+{
+    if (!out) return fail(CT_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    CT_TRY(check_desc(desc));
+    ct_geom *g = new (std::nothrow) ct_geom();
+    if (!g) return fail(CT_ERR_OOM, "host allocation failed");
+    g->desc = *desc;
+    (void)hipGetDevice(&g->device);
+    ct_status st = build_geometry(g);
+    if (st != CT_OK) {
+        free_geometry(g);
+        delete g;
+        return st;
+    }
+    *out = g;
+    return CT_OK;
+}
+
+void ct_geom_destroy(ct_geom *g)
+{
+    if (!g) return;
+    (void)hipDeviceSynchronize();
+    drop_graph_cache(g);
+    free_workspace(g);
+    free_geometry(g);
+    delete g;
+}
+
+static ct_status subset_range(const ct_geom *g, int subset, int *vstart, int *vstride, int *nv)
+{
+    const int M = g->desc.nsubsets;
+    if (subset == -1) {
+        *vstart = 0;
+        *vstride = 1;
+        *nv = g->desc.nviews;
+        return CT_OK;
+    }
+    if (subset < 0 || subset >= M) return fail(CT_ERR_INVALID_ARG, "subset must be -1 or in [0, M)");
+    *vstart = subset;
+    *vstride = M;
+    *nv = g->desc.nviews / M;
+    return CT_OK;
+}
+
+ct_status ct_forward(const ct_geom *gc, int subset, const float *x, float *p, void *stream)
+{
+    if (!gc || !x || !p) return fail(CT_ERR_INVALID_ARG, "NULL argument");
+    ct_geom *g = const_cast<ct_geom *>(gc);
+    int vs, vst, nv;
+    CT_TRY(subset_range(g, subset, &vs, &vst, &nv));
+    CT_TRY(ensure_workspace(g, 0, 4));
+    hipStream_t s = as_stream(stream);
+    CT_HIP_CHECK(launch_transpose(x, g->ws.tmp, g->desc.nx, g->desc.ny, s));
+    CT_HIP_CHECK(launch_forward(g->dev, x, g->ws.tmp, 0, vs, vst, nv, FP_PLAIN, nullptr, nullptr, 1.f, p, s));
+    return CT_OK;
+}
+
+ct_status ct_back(const ct_geom *gc, int subset, const float *r, float *x, void *stream)
+{
+    if (!gc || !r || !x) return fail(CT_ERR_INVALID_ARG, "NULL argument");
+    ct_geom *g = const_cast<ct_geom *>(gc);
+    int vs, vst, nv;
+    CT_TRY(subset_range(g, subset, &vs, &vst, &nv));
+    UpdateArgs U;
+    CT_HIP_CHECK(launch_back_update(g->dev, BP_BACK, r, vs, vst, nv, x, U, as_stream(stream)));
+    return CT_OK;
+}
+
+ct_status ct_rlalm_prepare(ct_geom *g, const ct_rlalm_params *p, const void *w, float *dl, float *kappa, void *stream)
+{
+    if (!g || !w || !dl) return fail(CT_ERR_INVALID_ARG, "NULL argument");
+    CT_TRY(check_params(p));
+    return do_prepare(g, p, static_cast<const float *>(w), dl, kappa, as_stream(stream));
+}
+
+ct_status ct_rlalm_init(ct_geom *g, const ct_rlalm_params *p, const void *y, const void *w, const float *dl, float *x,
+                        float *gv, float *h, void *stream)
+{
+    if (!g || !y || !w || !dl || !x || !gv || !h) return fail(CT_ERR_INVALID_ARG, "NULL argument");
+    CT_TRY(check_params(p));
+    CT_TRY(ensure_workspace(g, g->desc.nviews, 4));
+    hipStream_t s = as_stream(stream);
+    Ctx c = make_ctx(g, p, y, w, dl, nullptr, gv, h);
+    CT_TRY(do_init(c, x, p->start == 1, s));
+    CT_HIP_CHECK(hipMemcpyAsync(x, g->ws.xa, g->ws.npix * sizeof(float), hipMemcpyDeviceToDevice, s));
+    return CT_OK;
+}
+
+ct_status ct_rlalm_iterate(ct_geom *g, const ct_rlalm_params *p, const void *y, const void *w, const float *dl,
+                           const float *kappa, float *x, float *gv, float *h, long long t0, long long nsub,
+                           void *stream)
+{
+    if (!g || !y || !w || !dl || !x || !gv || !h) return fail(CT_ERR_INVALID_ARG, "NULL argument");
+    CT_TRY(check_params(p));
+    if (t0 < 0 || nsub < 0 || t0 + nsub + 2 > (1ll << 30)) return fail(CT_ERR_INVALID_ARG, "bad t0 / nsub");
+    if (p->kappa && !kappa) return fail(CT_ERR_INVALID_ARG, "kappa requested but NULL");
+    if (nsub == 0) return CT_OK;
+    hipStream_t s = as_stream(stream);
+    CT_TRY(ensure_workspace(g, g->desc.nviews, (size_t)(t0 + nsub + 2)));
+    CT_TRY(upload_rho(g, p, t0 + nsub + 2, s));
+    Ctx c = make_ctx(g, p, y, w, dl, kappa, gv, h);
+    CT_HIP_CHECK(hipMemcpyAsync(g->ws.xa, x, g->ws.npix * sizeof(float), hipMemcpyDeviceToDevice, s));
+    int fin = 1;
+    CT_TRY(run_subiters(c, t0, nsub, p->use_graph, s, &fin, nullptr, p, std::chrono::steady_clock::now()));
+    if (fin >= 0)
+        CT_HIP_CHECK(hipMemcpyAsync(x, fin ? g->ws.xa : g->ws.xb, g->ws.npix * sizeof(float), hipMemcpyDeviceToDevice, s));
+    return CT_OK;
+}
+
+ct_status ct_rlalm_solve(ct_geom *g, const ct_rlalm_params *p, const void *y, const void *w, float *x,
+                         ct_trace_row *trace, void *stream)
+{
+    auto tstart = std::chrono::steady_clock::now();
+    if (!g || !y || !w || !x) return fail(CT_ERR_INVALID_ARG, "NULL argument");
+    CT_TRY(check_params(p));
+    hipStream_t s = as_stream(stream);
+    const long long nsub = (long long)p->niters * g->desc.nsubsets;
+    CT_TRY(ensure_workspace(g, g->desc.nviews, (size_t)(nsub + 2)));
+    Workspace &W = g->ws;
+    CT_TRY(dev_alloc(&W.dl, W.npix));
+    CT_TRY(dev_alloc(&W.gv, W.npix));
+    CT_TRY(dev_alloc(&W.h, W.npix));
+    if (p->kappa) CT_TRY(dev_alloc(&W.kappa, W.npix));
+    CT_TRY(upload_rho(g, p, nsub + 2, s));
+    CT_TRY(do_prepare(g, p, static_cast<const float *>(w), W.dl, p->kappa ? W.kappa : nullptr, s));
+    Ctx c = make_ctx(g, p, y, w, W.dl, W.kappa, W.gv, W.h);
+    CT_TRY(do_init(c, x, p->start == 1, s));
+    int fin = -1;
+    if (nsub > 0) CT_TRY(run_subiters(c, 0, nsub, p->use_graph, s, &fin, trace, p, tstart));
+    const float *xf = fin == 0 ? W.xb : W.xa;
+    CT_HIP_CHECK(hipMemcpyAsync(x, xf, W.npix * sizeof(float), hipMemcpyDeviceToDevice, s));
+    // finiteness check of the final state (FP64 reduction, one synchronisation)
+    CT_HIP_CHECK(launch_trace_reduce(x, nullptr, W.gv, W.h, g->desc.nx, g->desc.ny, (float)g->desc.dx,
+                                     (float)g->desc.dy, 0.f, W.red, s));
+    double host[3];
+    CT_HIP_CHECK(hipMemcpyAsync(host, W.red, sizeof(host), hipMemcpyDeviceToHost, s));
+    CT_HIP_CHECK(hipStreamSynchronize(s));
+    if (host[2] != 0.0) return fail(CT_ERR_DIVERGED, "non-finite values in the final state");
+    return CT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,152 @@
+// Host-side geometry tables for the distance-driven fan-beam projector (FP64 -> FP32 device tables).
+//
+// The projector is the distance-driven operator (the paper cites, but does not define, its projector):
+// for a view whose central ray is within 45 degrees of the y axis ("row sweep"; decided here in FP64
+// as |sin b| >= |cos b| - 1e-12) the image lines are rows, otherwise columns. Detector boundary k is the
+// ray from the source through the detector point at u_k = (k - nb/2 + u_offset) du; it crosses line l
+// at U_k(l), an affine function of the line index. The weight of pixel q of line l in bin k is
+//     (line spacing / |cos theta_k|) * |[q, q+1] intersect [U_k(l), U_k+1(l)]| / |U_k+1(l) - U_k(l)|
+// (pixel units), theta_k being the angle between the ray through the bin centre and the line normal.
+//
+// The kernels evaluate U_k(l) = fmaf(lc, B_k, A_k) from the FP32 (A_k, B_k) stored here, in the forward
+// and in the back-projector alike, so both see bit-identical boundaries.
+#include <cmath>
+#include <cstring>
+
+#include "ct_internal.hpp"
+
+namespace ct {
+
+namespace {
+
+struct View64 {
+    double c, s;        // central direction d = (c, s)
+    double sx, sy;      // source
+    bool row;
+};
+
+View64 view64(const ct_geom_desc &d, int v)
+{
+    View64 o;
+    double beta = d.beta0 + d.span * (double)v / (double)d.nviews;
+    o.c = std::cos(beta);
+    o.s = std::sin(beta);
+    o.sx = -d.dso * o.c;
+    o.sy = -d.dso * o.s;
+    o.row = std::fabs(o.s) >= std::fabs(o.c) - 1e-12;
+    return o;
+}
+
+void det_point64(const ct_geom_desc &d, const View64 &o, double u, double *px, double *py)
+{
+    // detector axis e = (-s, c)
+    if (d.det == CT_DET_FLAT) {
+        double off = d.dsd - d.dso;
+        *px = off * o.c - u * o.s;
+        *py = off * o.s + u * o.c;
+    } else {
+        double gam = u / d.dsd;
+        double cg = std::cos(gam), sg = std::sin(gam);
+        *px = o.sx + d.dsd * (cg * o.c - sg * o.s);
+        *py = o.sy + d.dsd * (cg * o.s + sg * o.c);
+    }
+}
+
+}  // namespace
+
+ct_status build_geometry(ct_geom *g)
+{
+    const ct_geom_desc &d = g->desc;
+    const int nv = d.nviews, nb = d.nb;
+    std::vector<float2> bnd((size_t)nv * (nb + 1));
+    std::vector<float> scale((size_t)nv * nb);
+    std::vector<float4> inv(nv);
+    g->rowsweep.assign(nv, 0);
+    for (int v = 0; v < nv; ++v) {
+        View64 o = view64(d, v);
+        g->rowsweep[v] = o.row ? 1 : 0;
+        for (int k = 0; k <= nb; ++k) {
+            double u = ((double)k - 0.5 * nb + d.u_offset) * d.du;
+            double px, py;
+            det_point64(d, o, u, &px, &py);
+            double A, B;
+            if (o.row) {
+                double slope = (px - o.sx) / (py - o.sy);       // dx/dy along the ray
+                A = (o.sx - o.sy * slope) / d.dx;
+                B = d.dy * slope / d.dx;
+            } else {
+                double slope = (py - o.sy) / (px - o.sx);       // dy/dx along the ray
+                A = (o.sy - o.sx * slope) / d.dy;
+                B = d.dx * slope / d.dy;
+            }
+            bnd[(size_t)v * (nb + 1) + k] = make_float2((float)A, (float)B);
+        }
+        for (int k = 0; k < nb; ++k) {
+            double u = ((double)k + 0.5 - 0.5 * nb + d.u_offset) * d.du;
+            double cx, cy;
+            det_point64(d, o, u, &cx, &cy);
+            double rx = cx - o.sx, ry = cy - o.sy, len = std::sqrt(rx * rx + ry * ry);
+            scale[(size_t)v * nb + k] = (float)(o.row ? d.dy * len / std::fabs(ry) : d.dx * len / std::fabs(rx));
+        }
+        // inverse map: point at along-line coordinate e and line coordinate lc (view pixel units)
+        double ex = -o.s, ey = o.c;
+        if (o.row)  // X = e dx, Y = lc dy
+            inv[v] = make_float4((float)(d.dx * ex), (float)(d.dy * ey), (float)(d.dx * o.c), (float)(d.dy * o.s));
+        else        // X = lc dx, Y = e dy
+            inv[v] = make_float4((float)(d.dy * ey), (float)(d.dx * ex), (float)(d.dy * o.s), (float)(d.dx * o.c));
+    }
+    CT_HIP_CHECK(hipMalloc(&g->bnd, bnd.size() * sizeof(float2)));
+    CT_HIP_CHECK(hipMalloc(&g->scale, scale.size() * sizeof(float)));
+    CT_HIP_CHECK(hipMalloc(&g->inv, inv.size() * sizeof(float4)));
+    CT_HIP_CHECK(hipMalloc(&g->d_rowsweep, nv * sizeof(int)));
+    CT_HIP_CHECK(hipMemcpy(g->bnd, bnd.data(), bnd.size() * sizeof(float2), hipMemcpyHostToDevice));
+    CT_HIP_CHECK(hipMemcpy(g->scale, scale.data(), scale.size() * sizeof(float), hipMemcpyHostToDevice));
+    CT_HIP_CHECK(hipMemcpy(g->inv, inv.data(), inv.size() * sizeof(float4), hipMemcpyHostToDevice));
+    CT_HIP_CHECK(hipMemcpy(g->d_rowsweep, g->rowsweep.data(), nv * sizeof(int), hipMemcpyHostToDevice));
+    GeomDev &G = g->dev;
+    G.nx = d.nx;
+    G.ny = d.ny;
+    G.nb = nb;
+    G.nviews = nv;
+    G.arc = d.det == CT_DET_ARC;
+    G.dso = (float)d.dso;
+    G.c_kf = (float)(d.dsd / d.du);
+    G.k0 = (float)(0.5 * nb - d.u_offset);
+    G.bnd = g->bnd;
+    G.scale = g->scale;
+    G.inv = g->inv;
+    G.rowsweep = g->d_rowsweep;
+    return CT_OK;
+}
+
+void free_geometry(ct_geom *g)
+{
+    if (g->bnd) (void)hipFree(g->bnd);
+    if (g->scale) (void)hipFree(g->scale);
+    if (g->inv) (void)hipFree(g->inv);
+    if (g->d_rowsweep) (void)hipFree(g->d_rowsweep);
+    g->bnd = nullptr;
+    g->scale = nullptr;
+    g->inv = nullptr;
+    g->d_rowsweep = nullptr;
+}
+
+std::vector<int> subset_order(int M, int kind)
+{
+    std::vector<int> o;
+    if (kind == CT_ORDER_BITREV) {
+        int P = 1, bits = 0;
+        while (P < M) { P <<= 1; ++bits; }
+        for (int i = 0; i < P; ++i) {
+            int r = 0;
+            for (int b = 0; b < bits; ++b)
+                if (i & (1 << b)) r |= 1 << (bits - 1 - b);
+            if (r < M) o.push_back(r);
+        }
+    } else {
+        for (int m = 0; m < M; ++m) o.push_back(m);
+    }
+    return o;
+}
+
+}  // namespace ct
