@@ -1,0 +1,211 @@
+"""Benchmark: relaxed OS-LALM on one MI355X at the 512^2 fan-beam workload.
+
+Workload: 512x512 image (0.98 mm), flat detector 888 x 1.0239 mm, 984 views over 360 degrees,
+541/949 mm, seeded random-ellipse phantom with Poisson 1e5 + Gaussian sigma 5 noise, 41 subsets,
+alpha = 1.999, 100 iterations. One "step" is one complete solve through the C ABI (ct_rlalm_solve):
+D_L, initialisation and 100 outer iterations of 41 subiterations each, with y and w already in HBM.
+`value` is OS-RLALM outer iterations per second over the timed steps.
+
+Also reported: the unrelaxed (alpha = 1) rate on the same GPU, the per-launch duration of both
+projector kernels (HIP events on the stream they run on) and the ALU roofline of the dominant one,
+time to 1 HU when a converged reference x* for this scan is available, and the FP64 CPU oracle's rate
+on a bounded sample (rank 0 only).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32e12 non-packed FP32 VALU lane-operations/s
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+XSTAR = os.path.join(ROOT, "tests", "golden", "xstar_cfg2_seed100.npz")
+
+
+def dd_work_counts(g):
+    """Distance-driven work per outer iteration (all views), FP64 geometry written out here:
+    nonzeros of A, (bin, line) pairs, (pixel, view) pairs."""
+    u = (np.arange(g.nb + 1) - g.nb / 2.0 + g.u_offset) * g.du
+    nnz = 0
+    for v in range(g.nviews):
+        beta = g.beta0 + g.span * v / g.nviews
+        c, s = math.cos(beta), math.sin(beta)
+        S = np.array([-g.dso * c, -g.dso * s])
+        P = np.stack([(g.dsd - g.dso) * c - u * s, (g.dsd - g.dso) * s + u * c], axis=1)
+        row = abs(s) >= abs(c) - 1e-12
+        nl, nq = (g.ny, g.nx) if row else (g.nx, g.ny)
+        dl, dq = (g.dy, g.dx) if row else (g.dx, g.dy)
+        al, aq = (1, 0) if row else (0, 1)
+        cl = (np.arange(nl) - (nl - 1) / 2.0) * dl
+        t = (cl[:, None] - S[al]) / (P[None, :, al] - S[al])
+        b = (S[aq] + t * (P[None, :, aq] - S[aq])) / dq + nq / 2.0
+        lo = np.clip(np.minimum(b[:, :-1], b[:, 1:]), 0, nq)
+        hi = np.clip(np.maximum(b[:, :-1], b[:, 1:]), 0, nq)
+        n = np.where(hi > lo, np.ceil(hi) - np.floor(lo), 0)
+        nnz += int(n.sum())
+    return dict(nnz=nnz, bin_lines=g.nviews * g.nb * max(g.nx, g.ny), pix_views=g.nviews * g.nx * g.ny)
+
+
+def oracle_baseline(g, s, iters):
+    """The FP64 CPU oracle as it stands: `iters` outer iterations of Algorithm 1 (after D_L and init)."""
+    import oracle
+    p = oracle.params(alpha=1.999, niters=1, nsubsets=g.nsubsets)
+    y, w = s.y.astype(np.float64), s.w.astype(np.float64)
+    dl = oracle.dl(g, w)
+    x, gv, h = oracle.rlalm_init(g, p, y, w, dl, np.zeros((g.ny, g.nx)))
+    t0 = time.perf_counter()
+    oracle.rlalm_iterate(g, p, y, w, dl, x, gv, h, 0, iters * g.nsubsets)
+    dt = time.perf_counter() - t0
+    return dict(value=iters / dt, unit="iter/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"{iters} outer iterations ({iters * g.nsubsets} subiterations) of Algorithm 1 on the "
+                       f"same 512^2 scan, FP64, after D_L and initialisation; {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--niters", type=int, default=100)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-iters", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU design is described "
+              f"in DESIGN.md and not implemented.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1512_04564_amd import api, synth
+
+    dev = torch.device("cuda:0")
+    g = synth.CFG2
+    s = synth.noisy_scan(g, 100, truth=False)
+    G = api.Geometry(g)
+    y = torch.as_tensor(s.y, device=dev)
+    w = torch.as_tensor(s.w, device=dev)
+    x = torch.zeros((g.ny, g.nx), device=dev)
+    stream = torch.cuda.current_stream()
+
+    def solve(alpha, niters, xref=None, trace=False):
+        p = api.Params(alpha=alpha, niters=niters, start="zero", fov_radius=synth.fov_radius(g))
+        return api.rlalm_solve(G, p, y, w, x, x_ref=xref, trace=trace)
+
+    for _ in range(args.warmup):
+        solve(1.999, args.niters)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        solve(1.999, args.niters)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    iters_per_s = args.niters / (ms_per_step / 1e3)
+
+    # unrelaxed OS-LALM on the same GPU (same kernels, alpha = 1)
+    solve(1.0, args.niters)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(2):
+        solve(1.0, args.niters)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    iters_per_s_unrelaxed = args.niters / (e0.elapsed_time(e1) / 2 / 1e3)
+
+    # per-launch duration of the solve's two kernels: a timed solve brackets every forward-projection and
+    # fused back-projection/update launch with hipEvents on the stream they run on
+    kt_iters = 5
+    p_t = api.Params(alpha=1.999, niters=kt_iters, start="zero", time_kernels=True)
+    api.rlalm_solve(G, p_t, y, w, x)
+    kt = api.kernel_times(G)
+    times = {"forward": kt["ms_forward"] / kt["n_forward"] * 1e-3, "update": kt["ms_update"] / kt["n_update"] * 1e-3}
+
+    M = g.nsubsets
+    work = dd_work_counts(g)
+    vm = g.nviews // M
+    npix = g.nx * g.ny
+    ops = {
+        # per-unit figures: 6 VALU ops per nonzero of A, 4 per (bin, line) in the forward projector, 12 per
+        # (pixel, view) for the back-projector's inverse map, 3 per residual sample, 68 per pixel for the
+        # dual update, regularizer stencil (8 neighbours) and x-step
+        "forward": (6 * work["nnz"] + 4 * work["bin_lines"]) / M + 3 * vm * g.nb,
+        "update": (6 * work["nnz"] + 12 * work["pix_views"]) / M + 68 * npix,
+    }
+    dom = max(times, key=lambda k: times[k])
+    achieved = ops[dom] / times[dom] / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
+                "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                "kernel": "k_back_update<BP_FULL> (fused subset back-projection + relaxed update)" if dom == "update"
+                else "k_forward<FP_RESIDUAL> (subset forward projection + weighted residual)",
+                "ops_per_launch": ops[dom], "us_per_launch": round(times[dom] * 1e6, 2),
+                "us_per_launch_all": {k: round(v * 1e6, 2) for k, v in times.items()},
+                "achieved_all_TOPs": {k: round(ops[k] / times[k] / 1e12, 3) for k in times},
+                "launches_timed": kt["n_update"], "nnz_per_subset": work["nnz"] / M}
+
+    # time to 1 HU against the oracle's converged reference, when it is available
+    t1hu = None
+    if os.path.exists(XSTAR):
+        xstar = torch.as_tensor(np.load(XSTAR)["x"], device=dev)
+        t1hu = {}
+        for alpha in (1.999, 1.0):
+            rows = solve(alpha, args.niters, xref=xstar, trace=True)
+            hit = [r["iter"] for r in rows if r["rmsd_hu"] <= 1.0]
+            best = min(r["rmsd_hu"] for r in rows)
+            entry = {"iters": hit[0] if hit else None, "best_rmsd_hu": round(best, 3),
+                     "rmsd_hu_at": {str(r["iter"]): round(r["rmsd_hu"], 2) for r in rows if r["iter"] in (1, 5, 10, 20, 50, 100)}}
+            if hit:
+                torch.cuda.synchronize()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                solve(alpha, hit[0])
+                b.record(stream)
+                torch.cuda.synchronize()
+                entry["seconds"] = a.elapsed_time(b) / 1e3
+            t1hu[f"alpha={alpha}"] = entry
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = oracle_baseline(g, s, args.cpu_iters)
+
+    line = {
+        "metric": "OS-RLALM iterations/s (and time to 1 HU RMSD), 512^2 fan-beam",
+        "value": round(iters_per_s, 2),
+        "unit": "iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2-D fan-beam PWLS, 512x512 0.98 mm, 888 bins x 1.0239 mm, 984 views, "
+                               "541/949 mm, 41 subsets, alpha 1.999, 100 iterations per solve, seed 100",
+                   "iters_per_step": args.niters, "subsets": M, "alpha": 1.999},
+        "unrelaxed_iters_per_s": round(iters_per_s_unrelaxed, 2),
+        "wall_s": round(wall, 3),
+        "time_to_1hu": t1hu,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -12,6 +12,6 @@ __all__ = ["synth", "api"]
 def __getattr__(name):
     # The binding imports torch; load it lazily so that synth alone stays light.
     if name == "api":
-        from . import api
-        return api
+        import importlib
+        return importlib.import_module(__name__ + ".api")
     raise AttributeError(name)

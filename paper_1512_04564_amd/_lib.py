@@ -18,7 +18,8 @@ STATUS_NAMES = {0: "CT_OK", 1: "CT_ERR_INVALID_ARG", 2: "CT_ERR_OOM", 3: "CT_ERR
 
 #: Every entry point declared in include/ct.h.
 EXPORTS = ("ct_geom_create", "ct_geom_destroy", "ct_forward", "ct_back", "ct_rlalm_params_default",
-           "ct_rlalm_solve", "ct_rlalm_prepare", "ct_rlalm_init", "ct_rlalm_iterate", "ct_last_error")
+           "ct_rlalm_solve", "ct_rlalm_prepare", "ct_rlalm_init", "ct_rlalm_iterate", "ct_rlalm_kernel_times",
+           "ct_last_error")
 
 
 class GeomDesc(ctypes.Structure):
@@ -35,7 +36,13 @@ class RlalmParams(ctypes.Structure):
                 ("beta", ctypes.c_double), ("huber", ctypes.c_int), ("algorithm", ctypes.c_int),
                 ("subset_order", ctypes.c_int), ("kappa", ctypes.c_int), ("start", ctypes.c_int),
                 ("init_full", ctypes.c_int), ("dl_scale", ctypes.c_double), ("x_ref", ctypes.c_void_p),
-                ("mu_water", ctypes.c_double), ("fov_radius", ctypes.c_double), ("use_graph", ctypes.c_int)]
+                ("mu_water", ctypes.c_double), ("fov_radius", ctypes.c_double), ("use_graph", ctypes.c_int),
+                ("time_kernels", ctypes.c_int)]
+
+
+class KernelTimes(ctypes.Structure):
+    _fields_ = [("n_forward", ctypes.c_longlong), ("n_update", ctypes.c_longlong), ("ms_forward", ctypes.c_double),
+                ("ms_update", ctypes.c_double)]
 
 
 class TraceRow(ctypes.Structure):
@@ -72,6 +79,7 @@ def load() -> ctypes.CDLL:
     L.ct_rlalm_prepare.argtypes = [vp, ctypes.POINTER(RlalmParams), vp, vp, vp, vp]
     L.ct_rlalm_init.argtypes = [vp, ctypes.POINTER(RlalmParams), vp, vp, vp, vp, vp, vp, vp]
     L.ct_rlalm_iterate.argtypes = [vp, ctypes.POINTER(RlalmParams), vp, vp, vp, vp, vp, vp, vp, ll, ll, vp]
+    L.ct_rlalm_kernel_times.argtypes = [vp, ctypes.POINTER(KernelTimes)]
     L.ct_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name not in ("ct_geom_destroy", "ct_rlalm_params_default", "ct_last_error"):

@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import CtError, GeomDesc, RlalmParams, TraceRow, check
 
 __all__ = ["Geometry", "Params", "forward", "back", "rlalm_solve", "rlalm_prepare", "rlalm_init", "rlalm_iterate",
-           "CtError"]
+           "kernel_times", "CtError"]
 
 
 def _stream_handle(stream) -> int:
@@ -91,6 +91,7 @@ class Params:
     mu_water: float = 0.02
     fov_radius: float = 0.0
     use_graph: bool = True
+    time_kernels: bool = False
 
     def to_c(self, x_ref: torch.Tensor | None = None) -> RlalmParams:
         p = RlalmParams()
@@ -113,6 +114,7 @@ class Params:
         p.mu_water = self.mu_water
         p.fov_radius = self.fov_radius
         p.use_graph = int(self.use_graph)
+        p.time_kernels = int(self.time_kernels)
         return p
 
 
@@ -180,6 +182,13 @@ def rlalm_iterate(g: Geometry, p: Params, y, w, dl, x, gv, h, t0: int, nsub: int
                                   _ptr(kappa, shape=g.img_shape, name="kappa") if kappa is not None else None,
                                   _ptr(x, shape=g.img_shape, name="x"), _ptr(gv, shape=g.img_shape, name="g"),
                                   _ptr(h, shape=g.img_shape, name="h"), int(t0), int(nsub), _stream_handle(stream)))
+
+
+def kernel_times(g: Geometry) -> dict:
+    """Event-measured kernel totals of the last solve / iterate made with ``time_kernels=True``."""
+    kt = _lib.KernelTimes()
+    check(g._lib.ct_rlalm_kernel_times(g.handle, ctypes.byref(kt)))
+    return dict(n_forward=kt.n_forward, n_update=kt.n_update, ms_forward=kt.ms_forward, ms_update=kt.ms_update)
 
 
 def rho_table(p: Params, n: int):

@@ -14,7 +14,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libctrlalm.so")
 ARCH = os.environ.get("CTRLALM_ARCH", "gfx950")
 
-SOURCES = ["ct_geom.cpp", "ct_kernels.hip", "ct_api.hip"]
+# (source, extra flags). The projector / update kernels carry no NaN semantics; reductions keep them.
+SOURCES = [("ct_geom.cpp", []), ("ct_kernels.hip", ["-fno-honor-nans"]), ("ct_reduce.hip", []), ("ct_api.hip", [])]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
@@ -31,10 +32,10 @@ def build(verbose: bool = False) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     objs = []
-    for src in SOURCES:
+    for src, extra in SOURCES:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = [_hipcc(), *HIPCC_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [_hipcc(), *HIPCC_FLAGS, *extra, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), file=sys.stderr)
         subprocess.run(cmd, check=True)

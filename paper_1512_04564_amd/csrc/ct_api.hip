@@ -160,7 +160,8 @@ bool params_equal(const ct_rlalm_params &a, const ct_rlalm_params &b)
 {
     return a.alpha == b.alpha && a.rho_mode == b.rho_mode && a.rho_fixed == b.rho_fixed &&
            a.potential == b.potential && a.delta == b.delta && a.beta == b.beta && a.huber == b.huber &&
-           a.algorithm == b.algorithm && a.subset_order == b.subset_order && a.kappa == b.kappa;
+           a.algorithm == b.algorithm && a.subset_order == b.subset_order && a.kappa == b.kappa &&
+           a.potential == b.potential;
 }
 
 bool key_equal(const GraphKey &a, const GraphKey &b)
@@ -209,21 +210,27 @@ UpdateArgs make_update(const Ctx &c)
 
 // One subiteration t (relative offset tofs from the device counter): FP of subset m(t) on cur, then the
 // fused BP + dual(t) + x-step(t+1) writing nxt.
-hipError_t launch_subiter(const Ctx &c, long long t_abs, long long tofs, int cur_is_a, hipStream_t s)
+hipError_t launch_subiter_part(const Ctx &c, long long t_abs, long long tofs, int cur_is_a, int part, hipStream_t s)
 {
     Workspace &W = c.g->ws;
     const GeomDev &G = c.g->dev;
     const int m = c.order[(size_t)(t_abs % c.M)];
     const float *x = cur_is_a ? W.xa : W.xb;
     const float *xT = cur_is_a ? W.xta : W.xtb;
-    hipError_t e = launch_forward(G, x, xT, 0, m, c.M, c.nvm, FP_RESIDUAL, c.y, c.w, (float)c.M, W.r, s);
-    if (e != hipSuccess) return e;
+    if (part == 0) return launch_forward(G, x, xT, 0, m, c.M, c.nvm, FP_RESIDUAL, c.y, c.w, (float)c.M, W.r, s);
     UpdateArgs U = make_update(c);
     U.x = x;
     U.x_next = cur_is_a ? W.xb : W.xa;
     U.xT_next = cur_is_a ? W.xtb : W.xta;
     U.tofs = tofs;
     return launch_back_update(G, BP_FULL, W.r, m, c.M, c.nvm, nullptr, U, s);
+}
+
+hipError_t launch_subiter(const Ctx &c, long long t_abs, long long tofs, int cur_is_a, hipStream_t s)
+{
+    hipError_t e = launch_subiter_part(c, t_abs, tofs, cur_is_a, 0, s);
+    if (e != hipSuccess) return e;
+    return launch_subiter_part(c, t_abs, tofs, cur_is_a, 1, s);
 }
 
 ct_status upload_rho(ct_geom *g, const ct_rlalm_params *p, long long len, hipStream_t s)
@@ -238,8 +245,19 @@ ct_status upload_rho(ct_geom *g, const ct_rlalm_params *p, long long len, hipStr
 
 // Advance (x in buffer A on entry) from state t0 by nsub subiterations. On exit the buffer holding
 // x^(t0+nsub) is returned through final_is_a.
+struct KernelTimer {
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    ct_kernel_times kt{};
+    ~KernelTimer()
+    {
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
 ct_status run_subiters(const Ctx &c, long long t0, long long nsub, int use_graph, hipStream_t s, int *final_is_a,
-                       ct_trace_row *trace, const ct_rlalm_params *p, std::chrono::steady_clock::time_point tstart)
+                       ct_trace_row *trace, const ct_rlalm_params *p, std::chrono::steady_clock::time_point tstart,
+                       KernelTimer *timer = nullptr)
 {
     ct_geom *g = c.g;
     Workspace &W = g->ws;
@@ -283,12 +301,28 @@ ct_status run_subiters(const Ctx &c, long long t0, long long nsub, int use_graph
     };
     auto plain_one = [&]() -> ct_status {
         CT_HIP_CHECK(launch_set_counter(W.tbase, 0, s));
-        CT_HIP_CHECK(launch_subiter(c, t, t, cur_a, s));
+        if (timer) {
+            CT_HIP_CHECK(hipEventRecord(timer->ev[0], s));
+            CT_HIP_CHECK(launch_subiter_part(c, t, t, cur_a, 0, s));
+            CT_HIP_CHECK(hipEventRecord(timer->ev[1], s));
+            CT_HIP_CHECK(launch_subiter_part(c, t, t, cur_a, 1, s));
+            CT_HIP_CHECK(hipEventRecord(timer->ev[2], s));
+            CT_HIP_CHECK(hipEventSynchronize(timer->ev[2]));
+            float f = 0.f, u = 0.f;
+            CT_HIP_CHECK(hipEventElapsedTime(&f, timer->ev[0], timer->ev[1]));
+            CT_HIP_CHECK(hipEventElapsedTime(&u, timer->ev[1], timer->ev[2]));
+            timer->kt.n_forward += 1;
+            timer->kt.n_update += 1;
+            timer->kt.ms_forward += f;
+            timer->kt.ms_update += u;
+        } else {
+            CT_HIP_CHECK(launch_subiter(c, t, t, cur_a, s));
+        }
         cur_a ^= 1;
         ++t;
         return trace_point(t);
     };
-    if (use_graph && nsub >= L) {
+    if (use_graph && !timer && nsub >= L) {
         // plain launches until t is at an iteration boundary relative to t0 (keeps traces aligned)
         while (t < tend && (t % M) != 0) CT_TRY(plain_one());
         GraphCache &gc = g->graphs;
@@ -399,6 +433,14 @@ extern "C" {
 
 const char *ct_last_error(void) { return g_last_error.c_str(); }
 
+ct_status ct_rlalm_kernel_times(const ct_geom *g, ct_kernel_times *out)
+{
+    if (!g || !out) return fail(CT_ERR_INVALID_ARG, "NULL argument");
+    if (!g->ktimes_valid) return fail(CT_ERR_INVALID_ARG, "no solve with time_kernels = 1 on this handle");
+    *out = g->ktimes;
+    return CT_OK;
+}
+
 void ct_rlalm_params_default(ct_rlalm_params *p)
 {
     if (!p) return;
@@ -421,6 +463,7 @@ void ct_rlalm_params_default(ct_rlalm_params *p)
     p->mu_water = 0.02;
     p->fov_radius = 0.0;
     p->use_graph = 1;
+    p->time_kernels = 0;
 }
 
 ct_status ct_geom_create(const ct_geom_desc *desc, ct_geom **out)
@@ -527,7 +570,15 @@ ct_status ct_rlalm_iterate(ct_geom *g, const ct_rlalm_params *p, const void *y, 
     Ctx c = make_ctx(g, p, y, w, dl, kappa, gv, h);
     CT_HIP_CHECK(hipMemcpyAsync(g->ws.xa, x, g->ws.npix * sizeof(float), hipMemcpyDeviceToDevice, s));
     int fin = 1;
-    CT_TRY(run_subiters(c, t0, nsub, p->use_graph, s, &fin, nullptr, p, std::chrono::steady_clock::now()));
+    KernelTimer timer;
+    if (p->time_kernels)
+        for (auto &e : timer.ev) CT_HIP_CHECK(hipEventCreate(&e));
+    CT_TRY(run_subiters(c, t0, nsub, p->use_graph, s, &fin, nullptr, p, std::chrono::steady_clock::now(),
+                        p->time_kernels ? &timer : nullptr));
+    if (p->time_kernels) {
+        g->ktimes = timer.kt;
+        g->ktimes_valid = true;
+    }
     if (fin >= 0)
         CT_HIP_CHECK(hipMemcpyAsync(x, fin ? g->ws.xa : g->ws.xb, g->ws.npix * sizeof(float), hipMemcpyDeviceToDevice, s));
     return CT_OK;
@@ -552,7 +603,15 @@ ct_status ct_rlalm_solve(ct_geom *g, const ct_rlalm_params *p, const void *y, co
     Ctx c = make_ctx(g, p, y, w, W.dl, W.kappa, W.gv, W.h);
     CT_TRY(do_init(c, x, p->start == 1, s));
     int fin = -1;
-    if (nsub > 0) CT_TRY(run_subiters(c, 0, nsub, p->use_graph, s, &fin, trace, p, tstart));
+    KernelTimer timer;
+    if (p->time_kernels)
+        for (auto &e : timer.ev) CT_HIP_CHECK(hipEventCreate(&e));
+    if (nsub > 0)
+        CT_TRY(run_subiters(c, 0, nsub, p->use_graph, s, &fin, trace, p, tstart, p->time_kernels ? &timer : nullptr));
+    if (p->time_kernels) {
+        g->ktimes = timer.kt;
+        g->ktimes_valid = true;
+    }
     const float *xf = fin == 0 ? W.xb : W.xa;
     CT_HIP_CHECK(hipMemcpyAsync(x, xf, W.npix * sizeof(float), hipMemcpyDeviceToDevice, s));
     // finiteness check of the final state (FP64 reduction, one synchronisation)

@@ -10,6 +10,7 @@
 //
 // The kernels evaluate U_k(l) = fmaf(lc, B_k, A_k) from the FP32 (A_k, B_k) stored here, in the forward
 // and in the back-projector alike, so both see bit-identical boundaries.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 

@@ -40,6 +40,8 @@ ct_status fail(ct_status st, const std::string &msg);
 //       the view's own pixel units, is u = dsd * (e na + lc nl) / (e da + lc dl + dso);
 //       bin index kf = u / du + nb/2 - u_offset (arc: atan of the same ratio).
 //   rowsweep[v] = 1 for row-sweep views.
+constexpr int kBpTile = 16;   // back-projection tile edge (pixels)
+
 struct GeomDev {
     int nx, ny, nb, nviews;
     int arc;
@@ -96,6 +98,8 @@ struct ct_geom {
     ct::GeomDev dev{};
     ct::Workspace ws;
     ct::GraphCache graphs;
+    ct_kernel_times ktimes{};
+    bool ktimes_valid = false;
 };
 
 namespace ct {

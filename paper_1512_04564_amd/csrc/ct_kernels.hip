@@ -15,82 +15,157 @@
 // The back-projection kernel also carries the rest of the subiteration (Algorithm 1 of the paper):
 // the g and h recursions with rho_t, then the regularizer gradient / Huber curvature stencil and the
 // clipped x-step of the next subiteration with rho_{t+1}, writing the new image and its transpose.
+//
+// This file is compiled without NaN semantics (-fno-honor-nans): min/max need no canonicalising moves.
+// Finiteness checks live in ct_reduce.hip, which keeps them.
 #include "ct_internal.hpp"
 
 namespace ct {
 
 namespace {
 
-constexpr int FP_BINS = 64;   // bins per forward workgroup (one per lane)
-constexpr int FP_WAVES = 8;   // waves per forward workgroup (line split)
-constexpr int BP_TX = 16, BP_TY = 16;
+constexpr int FP_BINS = 64;          // bins per forward workgroup (one per lane)
+constexpr int FP_WAVES = 16;         // waves per forward workgroup; each streams its own image lines
+constexpr int FP_WIN = 128;          // LDS pixel window of one wave (floats)
+constexpr int FP_PF = FP_WIN / 64;   // prefetch registers per lane
+constexpr int BP_TX = kBpTile, BP_TY = kBpTile;
+constexpr int BP_WIN = 128;          // staged bins per view and tile in the back-projector
 
 __device__ __forceinline__ float rcp_approx(float v) { return __builtin_amdgcn_rcpf(v); }
 
+// Forward projection of the views vstart + vi * vstride (vi = blockIdx.y) for the 64 bins of block
+// blockIdx.x. Each wave streams a contiguous range of image lines: the pixels of line l+1 that the
+// block's footprint covers are loaded into registers (coalesced, clamped addresses) while line l is
+// evaluated from the wave's LDS window. The windows of 64 lines at a time are computed one line per lane
+// and read back with readlane. A bin's overlaps with its pixels are three branch-free taps from LDS (the
+// window is padded, so taps past its end read finite data with zero weight); wider footprints (oblique
+// lines) continue in a loop, and lines whose window exceeds the LDS slice read global memory.
 template <int EPI, bool ONES>
 __global__ __launch_bounds__(FP_BINS *FP_WAVES) void k_forward(GeomDev G, const float *__restrict__ img,
-                                                                const float *__restrict__ imgT,
-                                                                int vstart, int vstride,
-                                                                const float *__restrict__ y,
+                                                                const float *__restrict__ imgT, int vstart,
+                                                                int vstride, const float *__restrict__ y,
                                                                 const float *__restrict__ w, float mscale,
                                                                 float *__restrict__ out)
 {
+    constexpr int PADW = FP_WIN + 4;
     const int vi = blockIdx.y;
     const int v = vstart + vi * vstride;
-    const int lane = threadIdx.x & (FP_BINS - 1);
-    const int wave = threadIdx.x / FP_BINS;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
     const int nb = G.nb;
-    const int k = blockIdx.x * FP_BINS + lane;
+    const int kblk = blockIdx.x * FP_BINS;
+    const int k = kblk + lane;
+    const int kc = min(k, nb - 1);   // lanes past the last bin repeat it; their result is discarded
+    const int klast = min(kblk + FP_BINS, nb);
     const bool row = G.rowsweep[v] != 0;
     const int NL = row ? G.ny : G.nx;
     const int NQ = row ? G.nx : G.ny;
+    const bool even = (NQ & 1) == 0;
+    const int hq = NQ / 2;
     const float *src = row ? img : imgT;
     const float half = 0.5f * (float)NQ;
     const float lc0 = -0.5f * (float)(NL - 1);
+    const float2 *bv = G.bnd + (size_t)v * (nb + 1);
+    const float2 b0 = bv[kc], b1 = bv[kc + 1];
+    const float2 bF = bv[kblk], bL = bv[klast];
+    __shared__ float win[FP_WAVES * PADW];
+    float *wl = win + wave * PADW;
+    for (int t = lane; t < PADW; t += 64) wl[t] = ONES ? 1.f : 0.f;
+    const int l0 = (wave * NL) / FP_WAVES, l1 = ((wave + 1) * NL) / FP_WAVES;
+
+    // pixels [ws, ws + wn) of line l that the block's bins can overlap (boundaries are monotone in k);
+    // computed by lane (l - lb) for the 64 lines starting at lb
+    int ws_v = 0, wn_v = 0;
+    auto windows = [&](int lb) {
+        const float lc = lc0 + (float)(lb + lane);
+        const float uF = fmaf(lc, bF.y, bF.x), uL = fmaf(lc, bL.y, bL.x);
+        const float lo = fmaxf(fminf(uF, uL), -half), hi = fminf(fmaxf(uF, uL), half);
+        ws_v = max((int)floorf(lo + half) - 1, 0);
+        const int we = min((int)floorf(hi + half) + 1, NQ - 1);
+        wn_v = lo < hi ? we - ws_v + 1 : 0;
+    };
+    float pf[FP_PF];
+    auto prefetch = [&](int l, int ws) {
+        if (!ONES) {
+            // unconditional loads (clamped addresses): a fixed register set keeps the prefetch in flight
+            const float *line = src + (size_t)l * NQ;
+#pragma unroll
+            for (int j = 0; j < FP_PF; ++j) pf[j] = line[min(ws + lane + 64 * j, NQ - 1)];
+        }
+    };
+
+    // vmcnt(0): the boundary loads above are complete before the line loop, so that waiting on them
+    // inside the loop cannot also drain the next line's prefetch (vector loads complete in order)
+    __builtin_amdgcn_s_waitcnt(0x0F70);
     float acc = 0.f;
-    if (k < nb) {
-        const float2 b0 = G.bnd[(size_t)v * (nb + 1) + k];
-        const float2 b1 = G.bnd[(size_t)v * (nb + 1) + k + 1];
-        const int l0 = (wave * NL) / FP_WAVES, l1 = ((wave + 1) * NL) / FP_WAVES;
-        for (int l = l0; l < l1; ++l) {
-            const float lc = lc0 + (float)l;
+    int lb = l0;
+    windows(lb);
+    if (l0 < l1) prefetch(l0, __builtin_amdgcn_readfirstlane(ws_v));
+    float lc = lc0 + (float)l0;
+    for (int l = l0; l < l1; ++l, lc += 1.f) {
+        const int ws = __builtin_amdgcn_readlane(ws_v, l - lb);
+        const int wn = __builtin_amdgcn_readlane(wn_v, l - lb);
+        if (!ONES) {
+#pragma unroll
+            for (int j = 0; j < FP_PF; ++j) wl[lane + 64 * j] = pf[j];
+        }
+        // LDS operations of one wave complete in order: the window is readable by every lane below,
+        // and the next line's stores cannot overtake these reads.
+        __builtin_amdgcn_wave_barrier();
+        if (l + 1 < l1) {
+            if (l + 1 - lb == 64) {
+                lb += 64;
+                windows(lb);
+            }
+            prefetch(l + 1, __builtin_amdgcn_readlane(ws_v, l + 1 - lb));
+        }
+        if (wn > 0) {
             const float u0 = fmaf(lc, b0.y, b0.x);
             const float u1 = fmaf(lc, b1.y, b1.x);
             const float lo = fminf(u0, u1), hi = fmaxf(u0, u1);
             const float loc = fmaxf(lo, -half), hic = fminf(hi, half);
             if (loc < hic) {
-                int q0 = (int)floorf(loc + half);
-                if (loc < (float)q0 - half) --q0;              // exact correction of a rounded floor
-                int q1 = (int)floorf(hic + half);
-                if (hic > (float)(q1 + 1) - half) ++q1;
-                q0 = max(q0, 0);
-                q1 = min(q1, NQ - 1);
-                float s = 0.f;
-                if (ONES) {
-                    // all-ones image: the clamped overlaps telescope to the clamped footprint
-                    for (int q = q0; q <= q1; ++q) {
-                        const float e0 = (float)q - half;
-                        s += fmaxf(fminf(hic, e0 + 1.f) - fmaxf(loc, e0), 0.f);
-                    }
+                float e;   // left edge of pixel q0, the first pixel the footprint meets (exact)
+                int q0;
+                if (even) {   // pixel edges sit at integers: floor is exact
+                    e = floorf(loc);
+                    q0 = (int)e + hq;
+                } else {
+                    q0 = (int)floorf(loc + half);
+                    if (loc < (float)q0 - half) --q0;   // exact correction of a rounded floor
+                    e = (float)q0 - half;
+                }
+                // overlap of [loc, hic] with pixel q0 + i, pixel edges e + i: since e <= loc < e + 1,
+                // pixel q0 takes min(d, 1) - f and pixel q0 + i (i >= 1) takes med3(d - i, 0, 1),
+                // with d = hic - e and f = loc - e
+                const float d = hic - e, f = loc - e;
+                float s;
+                if (wn <= FP_WIN) {
+                    const float *tp = wl + (q0 - ws);  // q0 >= ws; three taps stay inside the padding
+                    s = (fminf(d, 1.f) - f) * tp[0];
+                    s = fmaf(__builtin_amdgcn_fmed3f(d - 1.f, 0.f, 1.f), tp[1], s);
+                    s = fmaf(__builtin_amdgcn_fmed3f(d - 2.f, 0.f, 1.f), tp[2], s);
+                    for (int i = 3; (float)i < d; ++i)   // footprint wider than three pixels
+                        s = fmaf(fminf(d - (float)i, 1.f), tp[i], s);
                 } else {
                     const float *line = src + (size_t)l * NQ;
-                    for (int q = q0; q <= q1; ++q) {
-                        const float e0 = (float)q - half;
-                        const float ov = fminf(hic, e0 + 1.f) - fmaxf(loc, e0);
-                        s = fmaf(fmaxf(ov, 0.f), line[q], s);
-                    }
+                    s = (fminf(d, 1.f) - f) * (ONES ? 1.f : line[q0]);
+                    for (int i = 1; (float)i < d; ++i)
+                        s = fmaf(fminf(d - (float)i, 1.f), ONES ? 1.f : line[q0 + i], s);
                 }
                 acc = fmaf(s, rcp_approx(hi - lo), acc);
             }
         }
+        __builtin_amdgcn_wave_barrier();
     }
-    __shared__ float red[FP_WAVES][FP_BINS];
-    red[wave][lane] = acc;
+    __syncthreads();
+    float *red = win;   // reuse: [FP_WAVES][64]
+    red[wave * 64 + lane] = acc;
     __syncthreads();
     if (wave == 0 && k < nb) {
         float p = 0.f;
 #pragma unroll
-        for (int ww = 0; ww < FP_WAVES; ++ww) p += red[ww][lane];
+        for (int ww = 0; ww < FP_WAVES; ++ww) p += red[ww * 64 + lane];
         p *= G.scale[(size_t)v * nb + k];
         const size_t o = (size_t)vi * nb + k;
         const size_t si = (size_t)v * nb + k;
@@ -100,50 +175,49 @@ __global__ __launch_bounds__(FP_BINS *FP_WAVES) void k_forward(GeomDev G, const 
     }
 }
 
-// Back-projection of one pixel over the views vstart + vi * vstride, vi < nv.
-__device__ __forceinline__ float bp_pixel(const GeomDev &G, const float *__restrict__ r, int vstart, int vstride,
-                                          int nv, int i, int j)
+// Back-projection of one pixel for one view: bins whose interval meets the pixel [e0, e0 + 1] on line
+// lc. The candidate range comes from the detector coordinate of the pixel's two edges (inverse map
+// u = dsd (e na + lc nl) / (e da + lc dl + dso)), widened by 0.05 bin, which absorbs the FP32 error of the
+// inverse map and of the boundary table (both far below it); the overlaps themselves are evaluated from
+// the same boundary table and fmaf sequence as the forward projector. ab(k) returns the boundary
+// coefficients of boundary k and rs(k) the residual of bin k premultiplied by its scale.
+template <typename AB, typename RS>
+__device__ __forceinline__ float bp_view(const GeomDev &G, const float4 im, float lc, float e0, int kw0, int kw1,
+                                         AB ab, RS rs)
 {
-    const int nb = G.nb;
-    float zeta = 0.f;
-    for (int vi = 0; vi < nv; ++vi) {
-        const int v = vstart + vi * vstride;
-        const bool row = G.rowsweep[v] != 0;
-        const int l = row ? i : j, q = row ? j : i;
-        const int NL = row ? G.ny : G.nx, NQ = row ? G.nx : G.ny;
-        const float lc = (float)l - 0.5f * (float)(NL - 1);
-        const float e0 = (float)q - 0.5f * (float)NQ;
-        const float e1 = e0 + 1.f;
-        const float4 im = G.inv[v];
-        const float nlc = lc * im.y;
-        const float dlc = fmaf(lc, im.w, G.dso);
-        const float num0 = fmaf(e0, im.x, nlc), den0 = fmaf(e0, im.z, dlc);
-        const float num1 = fmaf(e1, im.x, nlc), den1 = fmaf(e1, im.z, dlc);
-        float t0 = num0 / den0, t1 = num1 / den1;
-        if (G.arc) {
-            t0 = atanf(t0);
-            t1 = atanf(t1);
-        }
-        float kf0 = fmaf(G.c_kf, t0, G.k0), kf1 = fmaf(G.c_kf, t1, G.k0);
-        float kmn = fminf(kf0, kf1), kmx = fmaxf(kf0, kf1);
-        kmn = fminf(fmaxf(kmn, -2.f), (float)nb + 2.f);
-        kmx = fminf(fmaxf(kmx, -2.f), (float)nb + 2.f);
-        const int ka = max((int)floorf(kmn) - 1, 0);
-        const int kb = min((int)floorf(kmx) + 1, nb - 1);
-        if (ka > kb) continue;
-        const float2 *bv = G.bnd + (size_t)v * (nb + 1);
-        const float *sv = G.scale + (size_t)v * nb;
-        const float *rv = r + (size_t)vi * nb;
-        float2 bp = bv[ka];
-        float up = fmaf(lc, bp.y, bp.x);
-        for (int k = ka; k <= kb; ++k) {
-            const float2 bn = bv[k + 1];
-            const float un = fmaf(lc, bn.y, bn.x);
-            const float lo = fminf(up, un), hi = fmaxf(up, un);
-            const float ov = fminf(hi, e1) - fmaxf(lo, e0);
-            if (ov > 0.f) zeta = fmaf(rv[k] * sv[k], ov * rcp_approx(hi - lo), zeta);
-            up = un;
-        }
+    const float nlc = lc * im.y;
+    const float dlc = fmaf(lc, im.w, G.dso);
+    const float num0 = fmaf(e0, im.x, nlc), den0 = fmaf(e0, im.z, dlc);
+    const float num1 = num0 + im.x, den1 = den0 + im.z;
+    float t0 = num0 * rcp_approx(den0), t1 = num1 * rcp_approx(den1);
+    if (G.arc) {
+        t0 = atanf(t0);
+        t1 = atanf(t1);
+    }
+    const float kf0 = fmaf(G.c_kf, t0, G.k0), kf1 = fmaf(G.c_kf, t1, G.k0);
+    const int ka = max((int)floorf(fminf(kf0, kf1) - 0.05f), kw0);
+    const int kb = min((int)floorf(fmaxf(kf0, kf1) + 0.05f), kw1);
+    if (ka > kb) return 0.f;   // the pixel meets no bin (ka <= kb <= kw1 below keeps every index in range)
+    const float e1 = e0 + 1.f;
+    // Bins ka, ka+1, ka+2 unconditionally (boundary indices clamped to the staged range [kw0, kw1 + 1]);
+    // bins past kb lie at least 0.05 bin beyond the pixel, so their overlap is zero, and a clamped
+    // zero-width interval contributes 0 * finite. Pixels that meet more bins continue in a loop.
+    const int kt = kw1 + 1;
+    const float2 b0 = ab(ka), b1 = ab(min(ka + 1, kt)), b2 = ab(min(ka + 2, kt)), b3 = ab(min(ka + 3, kt));
+    const float u0 = fmaf(lc, b0.y, b0.x), u1 = fmaf(lc, b1.y, b1.x);
+    const float u2 = fmaf(lc, b2.y, b2.x), u3 = fmaf(lc, b3.y, b3.x);
+    auto tap = [&](float ua, float ub, int kk) {
+        const float lo = fminf(ua, ub), hi = fmaxf(ua, ub);
+        const float ov = fmaxf(fminf(hi, e1) - fmaxf(lo, e0), 0.f);
+        return rs(min(kk, kw1)) * (ov * rcp_approx(fmaxf(hi - lo, 1e-30f)));
+    };
+    float zeta = tap(u0, u1, ka) + tap(u1, u2, ka + 1) + tap(u2, u3, ka + 2);
+    float up = u3;
+    for (int k = ka + 3; k <= kb; ++k) {
+        const float2 b = ab(k + 1);
+        const float un = fmaf(lc, b.y, b.x);
+        zeta += tap(up, un, k);
+        up = un;
     }
     return zeta;
 }
@@ -159,21 +233,138 @@ __device__ __forceinline__ void pot_terms(int potential, float delta, float t, f
     dphi = t * omega;
 }
 
-template <int MODE>
-__global__ __launch_bounds__(BP_TX *BP_TY) void k_back_update(GeomDev G, const float *__restrict__ r, int vstart,
-                                                              int vstride, int nv, float *__restrict__ out_back,
-                                                              UpdateArgs U)
+// Detector-bin window [k0, k1] of the tile (pixel edges ti0..ti1 x tj0..tj1, tile-local) for view v:
+// the central projection of a convex tile is spanned by the projections of its four corners; one bin of
+// margin on each side absorbs FP32 error (k0 > k1: the tile misses the detector).
+__device__ __forceinline__ int2 tile_window(const GeomDev &G, int v, int i0, int i1, int j0, int j1)
 {
-    const int tx = threadIdx.x % BP_TX, ty = threadIdx.x / BP_TX;
+    const bool row = G.rowsweep[v] != 0;
+    const float4 im = G.inv[v];
+    // corner coordinates in the view's (along-line e, line lc) pixel units
+    const float ea = row ? (float)j0 - 0.5f * G.nx : (float)i0 - 0.5f * G.ny;
+    const float eb = row ? (float)j1 - 0.5f * G.nx : (float)i1 - 0.5f * G.ny;
+    const float la = row ? (float)i0 - 0.5f * G.ny : (float)j0 - 0.5f * G.nx;
+    const float lb = row ? (float)i1 - 0.5f * G.ny : (float)j1 - 0.5f * G.nx;
+    float kmn = 3.0e38f, kmx = -3.0e38f;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const float e = (c & 1) ? eb : ea, lc = (c & 2) ? lb : la;
+        const float num = fmaf(e, im.x, lc * im.y), den = fmaf(e, im.z, fmaf(lc, im.w, G.dso));
+        float t = num / den;
+        if (G.arc) t = atanf(t);
+        const float kf = fmaf(G.c_kf, t, G.k0);
+        kmn = fminf(kmn, kf);
+        kmx = fmaxf(kmx, kf);
+    }
+    if (kmx < -1.f || kmn > (float)G.nb + 1.f) return make_int2(1, 0);
+    return make_int2(max((int)floorf(kmn) - 1, 0), min((int)floorf(kmx) + 1, G.nb - 1));
+}
+
+// Fused back-projection and relaxed update over one 16 x 16 pixel tile. The workgroup has two halves of
+// 256 threads (one thread per pixel each); half h back-projects the views vi = h, h + 2, ..., staging
+// for each view, in LDS, the boundary coefficients and r_k * scale_k of the bins that can meet the tile
+// (double-buffered: the next view's loads are in flight while the current one is evaluated). The
+// tile's bin windows of a chunk of views are computed up front, one view per thread. The two partial
+// sums are added in a fixed order, then half 0 carries out the update of its pixel.
+template <int MODE>
+__global__ __launch_bounds__(2 * BP_TX *BP_TY) void k_back_update(GeomDev G, const float *__restrict__ r,
+                                                                  int vstart, int vstride, int nv,
+                                                                  float *__restrict__ out_back, UpdateArgs U)
+{
+    constexpr int NT = BP_TX * BP_TY;
+    constexpr int WCHUNK = 2 * NT;   // views whose windows are computed per chunk (one per thread)
+    const int hv = __builtin_amdgcn_readfirstlane(threadIdx.x / NT);   // view parity of this half (wave-uniform)
+    const int tid = threadIdx.x % NT;
+    const int tx = tid % BP_TX, ty = tid / BP_TX;
     const int j = blockIdx.x * BP_TX + tx, i = blockIdx.y * BP_TY + ty;
-    const int nx = G.nx, ny = G.ny;
-    __shared__ float tile[BP_TX][BP_TY + 1];
+    const int nx = G.nx, ny = G.ny, nb = G.nb;
+    __shared__ float tile_t[BP_TX][BP_TY + 1];
+    __shared__ float2 s_ab[2][2][BP_WIN + 1];
+    __shared__ float s_rs[2][2][BP_WIN];
+    __shared__ float s_part[NT];
+    __shared__ int2 s_win[WCHUNK];
     const bool inside = i < ny && j < nx;
+    float zeta = 0.f;
+    if (MODE != BP_XSTEP) {
+        const int ti0 = blockIdx.y * BP_TY, ti1 = min(ti0 + BP_TY, ny);
+        const int tj0 = blockIdx.x * BP_TX, tj1 = min(tj0 + BP_TX, nx);
+        // pixel coordinates in both sweep orientations: row sweep lines are rows (l = i, q = j)
+        const float lc_r = (float)i - 0.5f * (float)(ny - 1), e0_r = (float)j - 0.5f * (float)nx;
+        const float lc_c = (float)j - 0.5f * (float)(nx - 1), e0_c = (float)i - 0.5f * (float)ny;
+        for (int c0 = 0; c0 < nv; c0 += WCHUNK) {
+            const int cn = min(WCHUNK, nv - c0);   // views c0 .. c0 + cn - 1 in this chunk
+            if ((int)threadIdx.x < cn) s_win[threadIdx.x] = tile_window(G, vstart + (c0 + threadIdx.x) * vstride, ti0, ti1, tj0, tj1);
+            __syncthreads();
+            // The staging loads are only issued here; the values are combined and stored after the
+            // current view's back-projection, so the loads stay in flight meanwhile.
+            auto stage_load = [&](int ci, float2 &ab, float &rv, float &sv, int &kw0, int &kw1) {
+                kw0 = 1;
+                kw1 = 0;
+                ab = make_float2(0.f, 0.f);
+                rv = 0.f;
+                sv = 0.f;
+                if (ci >= cn) return;
+                const int v = vstart + (c0 + ci) * vstride;
+                const int2 wdw = s_win[ci];
+                kw0 = __builtin_amdgcn_readfirstlane(wdw.x);
+                kw1 = __builtin_amdgcn_readfirstlane(wdw.y);
+                const int n = kw1 - kw0 + 1;
+                if (n <= BP_WIN) {
+                    if (tid <= n) ab = G.bnd[(size_t)v * (nb + 1) + kw0 + tid];
+                    if (tid < n) {
+                        rv = r[(size_t)(c0 + ci) * nb + kw0 + tid];
+                        sv = G.scale[(size_t)v * nb + kw0 + tid];
+                    }
+                }
+            };
+            auto stage_store = [&](int buf, int kw0, int kw1, float2 ab, float rv, float sv) {
+                const int n = kw1 - kw0 + 1;
+                if (n <= BP_WIN) {
+                    if (tid <= n) s_ab[hv][buf][tid] = ab;
+                    if (tid < n) s_rs[hv][buf][tid] = rv * sv;
+                }
+            };
+            const int niter = (cn + 1) / 2;
+            float2 ab_n;
+            float r_n, sc_n;
+            int kw0_n, kw1_n;
+            stage_load(hv, ab_n, r_n, sc_n, kw0_n, kw1_n);
+            stage_store(0, kw0_n, kw1_n, ab_n, r_n, sc_n);
+            __syncthreads();
+            for (int it = 0; it < niter; ++it) {
+                const int buf = it & 1;
+                const int ci = 2 * it + hv;
+                const int kw0 = kw0_n, kw1 = kw1_n;
+                if (it + 1 < niter) stage_load(ci + 2, ab_n, r_n, sc_n, kw0_n, kw1_n);
+                if (inside && ci < cn && kw0 <= kw1) {
+                    const int v = vstart + (c0 + ci) * vstride;
+                    const bool row = G.rowsweep[v] != 0;
+                    const float lc = row ? lc_r : lc_c, e0 = row ? e0_r : e0_c;
+                    const float4 im = G.inv[v];
+                    if (kw1 - kw0 + 1 <= BP_WIN) {
+                        const float2 *sab = s_ab[hv][buf] - kw0;
+                        const float *srs = s_rs[hv][buf] - kw0;
+                        zeta += bp_view(G, im, lc, e0, kw0, kw1, [&](int k) { return sab[k]; },
+                                        [&](int k) { return srs[k]; });
+                    } else {
+                        const float2 *bv = G.bnd + (size_t)v * (nb + 1);
+                        const float *sv = G.scale + (size_t)v * nb;
+                        const float *rv = r + (size_t)(c0 + ci) * nb;
+                        zeta += bp_view(G, im, lc, e0, kw0, kw1, [&](int k) { return bv[k]; },
+                                        [&](int k) { return rv[k] * sv[k]; });
+                    }
+                }
+                if (it + 1 < niter) stage_store(buf ^ 1, kw0_n, kw1_n, ab_n, r_n, sc_n);
+                __syncthreads();
+            }
+        }
+        if (hv == 1) s_part[tid] = zeta;
+        __syncthreads();
+        if (hv == 0) zeta += s_part[tid];
+    }
     float xn = 0.f;
-    if (inside) {
+    if (hv == 0 && inside) {   // half 1 only takes part in the barriers from here on
         const size_t idx = (size_t)i * nx + j;
-        float zeta = 0.f;
-        if (MODE != BP_XSTEP) zeta = bp_pixel(G, r, vstart, vstride, nv, i, j);
         if (MODE == BP_BACK) {
             out_back[idx] = zeta;
         } else {
@@ -226,11 +417,11 @@ __global__ __launch_bounds__(BP_TX *BP_TY) void k_back_update(GeomDev G, const f
     }
     if (MODE == BP_FULL || MODE == BP_XSTEP || MODE == BP_INIT_XSTEP) {
         // transpose through LDS: write xT_next[j][i] in runs of BP_TY along i
-        tile[tx][ty] = xn;
+        if (hv == 0) tile_t[tx][ty] = xn;
         __syncthreads();
         const int jj = blockIdx.x * BP_TX + ty;   // swapped roles
         const int ii = blockIdx.y * BP_TY + tx;
-        if (jj < nx && ii < ny) U.xT_next[(size_t)jj * ny + ii] = tile[ty][tx];
+        if (hv == 0 && jj < nx && ii < ny) U.xT_next[(size_t)jj * ny + ii] = tile_t[ty][tx];
     }
 }
 
@@ -283,60 +474,6 @@ __global__ void k_kappa(const float *bw, const float *b1, float *kappa, size_t n
 __global__ void k_add_counter(int *c, int add) { c[0] += add; }
 __global__ void k_set_counter(int *c, int value) { c[0] = value; }
 
-// Deterministic FP64 partial sums: one partial per block, then a single-block final pass.
-constexpr int RED_THREADS = 256;
-constexpr int RED_BLOCKS = 256;
-
-__global__ __launch_bounds__(RED_THREADS) void k_trace_partial(const float *__restrict__ x,
-                                                              const float *__restrict__ ref,
-                                                              const float *__restrict__ gv,
-                                                              const float *__restrict__ h, int nx, int ny, float dx,
-                                                              float dy, float radius, double *__restrict__ part)
-{
-    const size_t n = (size_t)nx * ny;
-    double s = 0.0, c = 0.0, bad = 0.0;
-    for (size_t p = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; p < n; p += (size_t)RED_BLOCKS * RED_THREADS) {
-        const int i = (int)(p / nx), j = (int)(p % nx);
-        const float xv = x[p];
-        if (!isfinite(xv) || (gv && !isfinite(gv[p])) || (h && !isfinite(h[p]))) bad += 1.0;
-        if (ref) {
-            const float px = ((float)j - 0.5f * (float)(nx - 1)) * dx;
-            const float py = ((float)i - 0.5f * (float)(ny - 1)) * dy;
-            if (radius <= 0.f || px * px + py * py <= radius * radius) {
-                const double dd = (double)xv - (double)ref[p];
-                s += dd * dd;
-                c += 1.0;
-            }
-        }
-    }
-    __shared__ double sh[3][RED_THREADS];
-    sh[0][threadIdx.x] = s;
-    sh[1][threadIdx.x] = c;
-    sh[2][threadIdx.x] = bad;
-    __syncthreads();
-    for (int st = RED_THREADS / 2; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st)
-            for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + st];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        for (int q = 0; q < 3; ++q) part[(size_t)q * RED_BLOCKS + blockIdx.x] = sh[q][0];
-}
-
-__global__ __launch_bounds__(RED_BLOCKS) void k_trace_final(const double *__restrict__ part, double *__restrict__ out)
-{
-    __shared__ double sh[3][RED_BLOCKS];
-    for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] = part[(size_t)q * RED_BLOCKS + threadIdx.x];
-    __syncthreads();
-    for (int st = RED_BLOCKS / 2; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st)
-            for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + st];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        for (int q = 0; q < 3; ++q) out[q] = sh[q][0];
-}
-
 }  // namespace
 
 hipError_t launch_forward(const GeomDev &G, const float *img, const float *imgT, int ones, int vstart, int vstride,
@@ -362,7 +499,7 @@ hipError_t launch_forward(const GeomDev &G, const float *img, const float *imgT,
 hipError_t launch_back_update(const GeomDev &G, int mode, const float *r, int vstart, int vstride, int nv,
                               float *out_back, const UpdateArgs &U, hipStream_t s)
 {
-    dim3 grid((G.nx + BP_TX - 1) / BP_TX, (G.ny + BP_TY - 1) / BP_TY), block(BP_TX * BP_TY);
+    dim3 grid((G.nx + BP_TX - 1) / BP_TX, (G.ny + BP_TY - 1) / BP_TY), block(2 * BP_TX * BP_TY);
 #define CT_BP_CASE(M)                                                                                          \
     case M: hipLaunchKernelGGL(k_back_update<M>, grid, block, 0, s, G, r, vstart, vstride, nv, out_back, U); break;
     switch (mode) {
@@ -419,17 +556,6 @@ hipError_t launch_add_counter(int *c, int add, hipStream_t s)
 hipError_t launch_set_counter(int *c, int value, hipStream_t s)
 {
     hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(1), 0, s, c, value);
-    return hipGetLastError();
-}
-
-hipError_t launch_trace_reduce(const float *x, const float *ref, const float *gv, const float *h, int nx, int ny,
-                               float dx, float dy, float radius, double *out, hipStream_t s)
-{
-    // out must hold 3 doubles followed by 3 * RED_BLOCKS doubles of scratch
-    double *part = out + 3;
-    hipLaunchKernelGGL(k_trace_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, x, ref, gv, h, nx, ny, dx, dy,
-                       radius, part);
-    hipLaunchKernelGGL(k_trace_final, dim3(1), dim3(RED_BLOCKS), 0, s, part, out);
     return hipGetLastError();
 }
 
