@@ -109,9 +109,10 @@ typedef struct {
     double mu_water;     /* HU scale of the trace: HU = 1000 mu / mu_water (air = 0)                  */
     double fov_radius;   /* trace RMSD region: pixel centres within this radius (mm); <= 0: image    */
     int use_graph;       /* 1: replay one captured hipGraph per iteration; 0: plain launches          */
-    int time_kernels;    /* 1: plain launches with a hipEvent pair around every projection and update
-                            kernel of the subiterations (synchronising once per subiteration); the
-                            totals are read with ct_rlalm_kernel_times                                */
+    int time_kernels;    /* 1 (ct_rlalm_solve only): after the solve, replay the last subiteration's
+                            projection kernel and update kernel 50 times each, back to back between
+                            one hipEvent pair per kernel (the result is already in x; only solve-owned
+                            workspace is rewritten); read with ct_rlalm_kernel_times                  */
 } ct_rlalm_params;
 
 /* Fill p with the defaults: alpha 1.999, 20 iterations, continuation, hyperbola delta 1e-4 beta 1024,
@@ -156,10 +157,10 @@ ct_status ct_rlalm_iterate(ct_geom *g, const ct_rlalm_params *p, const void *y, 
                            const float *kappa, float *x, float *gv, float *h, long long t0, long long nsub,
                            void *stream);
 
-/* Per-kernel GPU time of the subiterations of the last solve / iterate call made with time_kernels = 1 on
-   this handle: n_* launches and their summed event-measured durations (ms). The forward kernel is the
-   subset projection with its residual epilogue; the update kernel is the fused back-projection / update.
-   Returns CT_ERR_INVALID_ARG if no timed call has been made. */
+/* Kernel timing of the last ct_rlalm_solve made with time_kernels = 1 on this handle: n_* back-to-back
+   launches and their total event-measured duration (ms). The forward kernel is the subset projection
+   with its residual epilogue; the update kernel is the fused back-projection / relaxed update.
+   Returns CT_ERR_INVALID_ARG if no timed solve has been made. */
 typedef struct {
     long long n_forward, n_update;
     double ms_forward, ms_update;

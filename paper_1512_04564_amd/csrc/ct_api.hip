@@ -245,19 +245,8 @@ ct_status upload_rho(ct_geom *g, const ct_rlalm_params *p, long long len, hipStr
 
 // Advance (x in buffer A on entry) from state t0 by nsub subiterations. On exit the buffer holding
 // x^(t0+nsub) is returned through final_is_a.
-struct KernelTimer {
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-    ct_kernel_times kt{};
-    ~KernelTimer()
-    {
-        for (auto &e : ev)
-            if (e) (void)hipEventDestroy(e);
-    }
-};
-
 ct_status run_subiters(const Ctx &c, long long t0, long long nsub, int use_graph, hipStream_t s, int *final_is_a,
-                       ct_trace_row *trace, const ct_rlalm_params *p, std::chrono::steady_clock::time_point tstart,
-                       KernelTimer *timer = nullptr)
+                       ct_trace_row *trace, const ct_rlalm_params *p, std::chrono::steady_clock::time_point tstart)
 {
     ct_geom *g = c.g;
     Workspace &W = g->ws;
@@ -301,28 +290,12 @@ ct_status run_subiters(const Ctx &c, long long t0, long long nsub, int use_graph
     };
     auto plain_one = [&]() -> ct_status {
         CT_HIP_CHECK(launch_set_counter(W.tbase, 0, s));
-        if (timer) {
-            CT_HIP_CHECK(hipEventRecord(timer->ev[0], s));
-            CT_HIP_CHECK(launch_subiter_part(c, t, t, cur_a, 0, s));
-            CT_HIP_CHECK(hipEventRecord(timer->ev[1], s));
-            CT_HIP_CHECK(launch_subiter_part(c, t, t, cur_a, 1, s));
-            CT_HIP_CHECK(hipEventRecord(timer->ev[2], s));
-            CT_HIP_CHECK(hipEventSynchronize(timer->ev[2]));
-            float f = 0.f, u = 0.f;
-            CT_HIP_CHECK(hipEventElapsedTime(&f, timer->ev[0], timer->ev[1]));
-            CT_HIP_CHECK(hipEventElapsedTime(&u, timer->ev[1], timer->ev[2]));
-            timer->kt.n_forward += 1;
-            timer->kt.n_update += 1;
-            timer->kt.ms_forward += f;
-            timer->kt.ms_update += u;
-        } else {
-            CT_HIP_CHECK(launch_subiter(c, t, t, cur_a, s));
-        }
+        CT_HIP_CHECK(launch_subiter(c, t, t, cur_a, s));
         cur_a ^= 1;
         ++t;
         return trace_point(t);
     };
-    if (use_graph && !timer && nsub >= L) {
+    if (use_graph && nsub >= L) {
         // plain launches until t is at an iteration boundary relative to t0 (keeps traces aligned)
         while (t < tend && (t % M) != 0) CT_TRY(plain_one());
         GraphCache &gc = g->graphs;
@@ -365,6 +338,42 @@ ct_status run_subiters(const Ctx &c, long long t0, long long nsub, int use_graph
     *final_is_a = nsub > 0 ? (cur_a ^ 1) : 1;  // with nsub == 0 nothing ran; caller keeps its x
     if (nsub == 0) *final_is_a = -1;
     return CT_OK;
+}
+
+// Kernel timing: replay the two kernels of subiteration t (input image in A when cur_is_a) kTimingReps
+// times each, back to back between one hipEvent pair per kernel, on the solve's stream. Runs after the
+// solve's result has been copied out; it only rewrites solve-owned workspace (g, h, the spare image).
+constexpr int kTimingReps = 50;
+
+ct_status time_last_subiteration(const Ctx &c, long long t, int cur_is_a, hipStream_t s)
+{
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    ct_status st = CT_OK;
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) st = fail(CT_ERR_HIP, "hipEventCreate failed");
+    if (st == CT_OK) {
+        hipError_t e = launch_set_counter(c.g->ws.tbase, 0, s);
+        if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+        for (int r = 0; r < kTimingReps && e == hipSuccess; ++r) e = launch_subiter_part(c, t, t, cur_is_a, 0, s);
+        if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+        for (int r = 0; r < kTimingReps && e == hipSuccess; ++r) e = launch_subiter_part(c, t, t, cur_is_a, 1, s);
+        if (e == hipSuccess) e = hipEventRecord(ev[2], s);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[2]);
+        float f = 0.f, u = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&f, ev[0], ev[1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&u, ev[1], ev[2]);
+        if (e != hipSuccess) st = fail(CT_ERR_HIP, std::string("kernel timing: ") + hipGetErrorString(e));
+        else {
+            c.g->ktimes.n_forward = kTimingReps;
+            c.g->ktimes.n_update = kTimingReps;
+            c.g->ktimes.ms_forward = f;
+            c.g->ktimes.ms_update = u;
+            c.g->ktimes_valid = true;
+        }
+    }
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return st;
 }
 
 Ctx make_ctx(ct_geom *g, const ct_rlalm_params *p, const void *y, const void *w, const float *dl, const float *kappa,
@@ -570,15 +579,7 @@ ct_status ct_rlalm_iterate(ct_geom *g, const ct_rlalm_params *p, const void *y, 
     Ctx c = make_ctx(g, p, y, w, dl, kappa, gv, h);
     CT_HIP_CHECK(hipMemcpyAsync(g->ws.xa, x, g->ws.npix * sizeof(float), hipMemcpyDeviceToDevice, s));
     int fin = 1;
-    KernelTimer timer;
-    if (p->time_kernels)
-        for (auto &e : timer.ev) CT_HIP_CHECK(hipEventCreate(&e));
-    CT_TRY(run_subiters(c, t0, nsub, p->use_graph, s, &fin, nullptr, p, std::chrono::steady_clock::now(),
-                        p->time_kernels ? &timer : nullptr));
-    if (p->time_kernels) {
-        g->ktimes = timer.kt;
-        g->ktimes_valid = true;
-    }
+    CT_TRY(run_subiters(c, t0, nsub, p->use_graph, s, &fin, nullptr, p, std::chrono::steady_clock::now()));
     if (fin >= 0)
         CT_HIP_CHECK(hipMemcpyAsync(x, fin ? g->ws.xa : g->ws.xb, g->ws.npix * sizeof(float), hipMemcpyDeviceToDevice, s));
     return CT_OK;
@@ -603,15 +604,7 @@ ct_status ct_rlalm_solve(ct_geom *g, const ct_rlalm_params *p, const void *y, co
     Ctx c = make_ctx(g, p, y, w, W.dl, W.kappa, W.gv, W.h);
     CT_TRY(do_init(c, x, p->start == 1, s));
     int fin = -1;
-    KernelTimer timer;
-    if (p->time_kernels)
-        for (auto &e : timer.ev) CT_HIP_CHECK(hipEventCreate(&e));
-    if (nsub > 0)
-        CT_TRY(run_subiters(c, 0, nsub, p->use_graph, s, &fin, trace, p, tstart, p->time_kernels ? &timer : nullptr));
-    if (p->time_kernels) {
-        g->ktimes = timer.kt;
-        g->ktimes_valid = true;
-    }
+    if (nsub > 0) CT_TRY(run_subiters(c, 0, nsub, p->use_graph, s, &fin, trace, p, tstart));
     const float *xf = fin == 0 ? W.xb : W.xa;
     CT_HIP_CHECK(hipMemcpyAsync(x, xf, W.npix * sizeof(float), hipMemcpyDeviceToDevice, s));
     // finiteness check of the final state (FP64 reduction, one synchronisation)
@@ -621,6 +614,7 @@ ct_status ct_rlalm_solve(ct_geom *g, const ct_rlalm_params *p, const void *y, co
     CT_HIP_CHECK(hipMemcpyAsync(host, W.red, sizeof(host), hipMemcpyDeviceToHost, s));
     CT_HIP_CHECK(hipStreamSynchronize(s));
     if (host[2] != 0.0) return fail(CT_ERR_DIVERGED, "non-finite values in the final state");
+    if (p->time_kernels && nsub > 0) CT_TRY(time_last_subiteration(c, nsub - 1, fin == 0 ? 0 : 1, s));
     return CT_OK;
 }
 
