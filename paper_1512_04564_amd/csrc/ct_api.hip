@@ -54,6 +54,8 @@ ct_status check_desc(const ct_geom_desc *d)
     if (!(d->dx > 0) || !(d->dy > 0) || !(d->du > 0)) return fail(CT_ERR_INVALID_ARG, "dx, dy, du must be > 0");
     if (d->nb < 1 || d->nb > 8192) return fail(CT_ERR_INVALID_ARG, "nb must be in [1, 8192]");
     if (d->nviews < 1 || d->nviews > (1 << 20)) return fail(CT_ERR_INVALID_ARG, "nviews must be in [1, 2^20]");
+    if ((long long)d->nviews * (d->nb + 1) >= (1ll << 31))
+        return fail(CT_ERR_INVALID_ARG, "nviews * (nb + 1) must stay below 2^31");
     if (d->nsubsets < 1 || d->nviews % d->nsubsets != 0)
         return fail(CT_ERR_INVALID_ARG, "nsubsets must be >= 1 and divide nviews");
     if (!(d->dso > 0) || !(d->dsd > d->dso)) return fail(CT_ERR_INVALID_ARG, "need dsd > dso > 0");

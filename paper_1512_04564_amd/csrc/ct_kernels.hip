@@ -282,7 +282,8 @@ __global__ __launch_bounds__(2 * BP_TX *BP_TY) void k_back_update(GeomDev G, con
     __shared__ float2 s_ab[2][2][BP_WIN + 1];
     __shared__ float s_rs[2][2][BP_WIN];
     __shared__ float s_part[NT];
-    __shared__ int2 s_win[WCHUNK];
+    __shared__ int4 s_desc[WCHUNK];   // per view of the chunk: bin window k0, k1; view index; row-sweep flag
+    __shared__ float4 s_im[WCHUNK];   // per view of the chunk: inverse-map coefficients
     const bool inside = i < ny && j < nx;
     float zeta = 0.f;
     if (MODE != BP_XSTEP) {
@@ -293,7 +294,12 @@ __global__ __launch_bounds__(2 * BP_TX *BP_TY) void k_back_update(GeomDev G, con
         const float lc_c = (float)j - 0.5f * (float)(nx - 1), e0_c = (float)i - 0.5f * (float)ny;
         for (int c0 = 0; c0 < nv; c0 += WCHUNK) {
             const int cn = min(WCHUNK, nv - c0);   // views c0 .. c0 + cn - 1 in this chunk
-            if ((int)threadIdx.x < cn) s_win[threadIdx.x] = tile_window(G, vstart + (c0 + threadIdx.x) * vstride, ti0, ti1, tj0, tj1);
+            if ((int)threadIdx.x < cn) {
+                const int v = vstart + (c0 + threadIdx.x) * vstride;
+                const int2 w = tile_window(G, v, ti0, ti1, tj0, tj1);
+                s_desc[threadIdx.x] = make_int4(w.x, w.y, v, G.rowsweep[v]);
+                s_im[threadIdx.x] = G.inv[v];
+            }
             __syncthreads();
             // The staging loads are only issued here; the values are combined and stored after the
             // current view's back-projection, so the loads stay in flight meanwhile.
@@ -304,16 +310,18 @@ __global__ __launch_bounds__(2 * BP_TX *BP_TY) void k_back_update(GeomDev G, con
                 rv = 0.f;
                 sv = 0.f;
                 if (ci >= cn) return;
-                const int v = vstart + (c0 + ci) * vstride;
-                const int2 wdw = s_win[ci];
-                kw0 = __builtin_amdgcn_readfirstlane(wdw.x);
-                kw1 = __builtin_amdgcn_readfirstlane(wdw.y);
+                const int4 dsc = s_desc[ci];
+                kw0 = __builtin_amdgcn_readfirstlane(dsc.x);
+                kw1 = __builtin_amdgcn_readfirstlane(dsc.y);
+                const unsigned v = (unsigned)__builtin_amdgcn_readfirstlane(dsc.z);
                 const int n = kw1 - kw0 + 1;
                 if (n <= BP_WIN) {
-                    if (tid <= n) ab = G.bnd[(size_t)v * (nb + 1) + kw0 + tid];
+                    // 32-bit element offsets (the geometry keeps nviews * (nb + 1) below 2^31)
+                    const unsigned t = (unsigned)tid;
+                    if (tid <= n) ab = G.bnd[v * (unsigned)(nb + 1) + (unsigned)kw0 + t];
                     if (tid < n) {
-                        rv = r[(size_t)(c0 + ci) * nb + kw0 + tid];
-                        sv = G.scale[(size_t)v * nb + kw0 + tid];
+                        rv = r[(unsigned)(c0 + ci) * (unsigned)nb + (unsigned)kw0 + t];
+                        sv = G.scale[v * (unsigned)nb + (unsigned)kw0 + t];
                     }
                 }
             };
@@ -337,10 +345,15 @@ __global__ __launch_bounds__(2 * BP_TX *BP_TY) void k_back_update(GeomDev G, con
                 const int kw0 = kw0_n, kw1 = kw1_n;
                 if (it + 1 < niter) stage_load(ci + 2, ab_n, r_n, sc_n, kw0_n, kw1_n);
                 if (inside && ci < cn && kw0 <= kw1) {
-                    const int v = vstart + (c0 + ci) * vstride;
-                    const bool row = G.rowsweep[v] != 0;
+                    const int4 dsc = s_desc[ci];
+                    const int v = __builtin_amdgcn_readfirstlane(dsc.z);
+                    const bool row = __builtin_amdgcn_readfirstlane(dsc.w) != 0;
                     const float lc = row ? lc_r : lc_c, e0 = row ? e0_r : e0_c;
-                    const float4 im = G.inv[v];
+                    const float4 imv = s_im[ci];
+                    const float4 im = make_float4(__builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, imv.x))),
+                                                  __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, imv.y))),
+                                                  __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, imv.z))),
+                                                  __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, imv.w))));
                     if (kw1 - kw0 + 1 <= BP_WIN) {
                         const float2 *sab = s_ab[hv][buf] - kw0;
                         const float *srs = s_rs[hv][buf] - kw0;
