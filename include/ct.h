@@ -87,6 +87,15 @@ ct_status ct_forward(const ct_geom *g, int subset, const float *x, float *p, voi
  */
 ct_status ct_back(const ct_geom *g, int subset, const float *r, float *x, void *stream);
 
+/*
+ * x = FBP-like image of the sinogram y ([nviews][nb] float32), [ny][nx] float32, overwritten: per view a
+ * cosine pre-weight on the detector magnified to the isocentre, the spatial Ram-Lak filter, then
+ * pixel-driven back-projection with linear interpolation and the fan weight (dso / L)^2, clipped at zero.
+ * Algorithm 1 starts from an FBP image; this is its plain, unwindowed form. Flat detector only
+ * (CT_ERR_UNSUPPORTED otherwise). Uses the handle's workspace: do not overlap with a solve on the handle.
+ */
+ct_status ct_fbp(const ct_geom *g, const void *y, float *x, void *stream);
+
 /* Subset processing order (the paper leaves it open). */
 typedef enum { CT_ORDER_SEQUENTIAL = 0, CT_ORDER_BITREV = 1 } ct_subset_order;
 
@@ -101,7 +110,7 @@ typedef struct {
     int algorithm;       /* 1: Algorithm 1 (proposed relaxation), 2: Algorithm 2 (simple relaxation) */
     int subset_order;    /* ct_subset_order                                                          */
     int kappa;           /* 0: kappa = 1; 1: certainty weights kappa_j = sqrt(A'w / A'1)             */
-    int start;           /* 0: x holds x0 on entry; 1: zero image                                    */
+    int start;           /* 0: x holds x0 on entry; 1: zero image; 2: FBP-like image (ct_fbp)       */
     int init_full;       /* 0: initial gradient from the last subset (Algorithm 1 as written);
                             1: full gradient                                                         */
     double dl_scale;     /* multiplies D_L (1 = the majorizer diag{A'WA1})                            */

@@ -15,7 +15,7 @@ import torch
 from . import _lib
 from ._lib import CtError, GeomDesc, RlalmParams, TraceRow, check
 
-__all__ = ["Geometry", "Params", "forward", "back", "rlalm_solve", "rlalm_prepare", "rlalm_init", "rlalm_iterate",
+__all__ = ["Geometry", "Params", "forward", "back", "fbp", "rlalm_solve", "rlalm_prepare", "rlalm_init", "rlalm_iterate",
            "kernel_times", "CtError"]
 
 
@@ -85,7 +85,7 @@ class Params:
     algorithm: int = 1
     subset_order: str = "sequential"  # or "bitrev"
     kappa: bool = False
-    start: str = "given"             # or "zero"
+    start: str = "given"             # or "zero", "fbp"
     init_full: bool = False
     dl_scale: float = 1.0
     mu_water: float = 0.02
@@ -107,7 +107,7 @@ class Params:
         p.algorithm = self.algorithm
         p.subset_order = {"sequential": 0, "bitrev": 1}[self.subset_order]
         p.kappa = int(self.kappa)
-        p.start = {"given": 0, "zero": 1}[self.start]
+        p.start = {"given": 0, "zero": 1, "fbp": 2}[self.start]
         p.init_full = int(self.init_full)
         p.dl_scale = self.dl_scale
         p.x_ref = x_ref.data_ptr() if x_ref is not None else None
@@ -135,6 +135,15 @@ def back(g: Geometry, r: torch.Tensor, subset: int = -1, out: torch.Tensor | Non
         out = torch.empty(g.img_shape, dtype=torch.float32, device=r.device)
     check(g._lib.ct_back(g.handle, subset, _ptr(r, shape=(nv, g.nb), name="r"),
                          _ptr(out, shape=g.img_shape, name="out"), _stream_handle(stream)))
+    return out
+
+
+def fbp(g: Geometry, y: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+    """FBP-like start image of the sinogram y: ``[ny][nx]`` float32."""
+    if out is None:
+        out = torch.empty(g.img_shape, dtype=torch.float32, device=y.device)
+    check(g._lib.ct_fbp(g.handle, _ptr(y, shape=(g.nviews, g.nb), name="y"), _ptr(out, shape=g.img_shape, name="out"),
+                        _stream_handle(stream)))
     return out
 
 

@@ -15,7 +15,8 @@ LIB = os.path.join(HERE, "libctrlalm.so")
 ARCH = os.environ.get("CTRLALM_ARCH", "gfx950")
 
 # (source, extra flags). The projector / update kernels carry no NaN semantics; reductions keep them.
-SOURCES = [("ct_geom.cpp", []), ("ct_kernels.hip", ["-fno-honor-nans"]), ("ct_reduce.hip", []), ("ct_api.hip", [])]
+SOURCES = [("ct_geom.cpp", []), ("ct_kernels.hip", ["-fno-honor-nans"]), ("ct_reduce.hip", []), ("ct_fbp.hip", []),
+           ("ct_api.hip", [])]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

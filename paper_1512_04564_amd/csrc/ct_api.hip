@@ -86,7 +86,7 @@ ct_status check_params(const ct_rlalm_params *p)
     if (p->subset_order != CT_ORDER_SEQUENTIAL && p->subset_order != CT_ORDER_BITREV)
         return fail(CT_ERR_INVALID_ARG, "unknown subset order");
     if (!(p->dl_scale > 0)) return fail(CT_ERR_INVALID_ARG, "dl_scale must be > 0");
-    if (p->start != 0 && p->start != 1) return fail(CT_ERR_INVALID_ARG, "start must be 0 or 1");
+    if (p->start < 0 || p->start > 2) return fail(CT_ERR_INVALID_ARG, "start must be 0, 1 or 2");
     return CT_OK;
 }
 
@@ -546,6 +546,16 @@ ct_status ct_back(const ct_geom *gc, int subset, const float *r, float *x, void 
     return CT_OK;
 }
 
+ct_status ct_fbp(const ct_geom *gc, const void *y, float *x, void *stream)
+{
+    if (!gc || !y || !x) return fail(CT_ERR_INVALID_ARG, "NULL argument");
+    ct_geom *g = const_cast<ct_geom *>(gc);
+    if (g->desc.det != CT_DET_FLAT) return fail(CT_ERR_UNSUPPORTED, "the FBP-like start supports the flat detector only");
+    CT_TRY(ensure_workspace(g, g->desc.nviews, 4));
+    CT_HIP_CHECK(launch_fbp(g, static_cast<const float *>(y), g->ws.r, g->cs, x, as_stream(stream)));
+    return CT_OK;
+}
+
 ct_status ct_rlalm_prepare(ct_geom *g, const ct_rlalm_params *p, const void *w, float *dl, float *kappa, void *stream)
 {
     if (!g || !w || !dl) return fail(CT_ERR_INVALID_ARG, "NULL argument");
@@ -602,6 +612,10 @@ ct_status ct_rlalm_solve(ct_geom *g, const ct_rlalm_params *p, const void *y, co
     CT_TRY(dev_alloc(&W.h, W.npix));
     if (p->kappa) CT_TRY(dev_alloc(&W.kappa, W.npix));
     CT_TRY(upload_rho(g, p, nsub + 2, s));
+    if (p->start == 2) {   // FBP-like start image, written into x
+        if (g->desc.det != CT_DET_FLAT) return fail(CT_ERR_UNSUPPORTED, "the FBP-like start supports the flat detector only");
+        CT_HIP_CHECK(launch_fbp(g, static_cast<const float *>(y), W.r, g->cs, x, s));
+    }
     CT_TRY(do_prepare(g, p, static_cast<const float *>(w), W.dl, p->kappa ? W.kappa : nullptr, s));
     Ctx c = make_ctx(g, p, y, w, W.dl, W.kappa, W.gv, W.h);
     CT_TRY(do_init(c, x, p->start == 1, s));

@@ -62,10 +62,12 @@ ct_status build_geometry(ct_geom *g)
     std::vector<float2> bnd((size_t)nv * (nb + 1));
     std::vector<float> scale((size_t)nv * nb);
     std::vector<float4> inv(nv);
+    std::vector<double2> cs(nv);
     g->rowsweep.assign(nv, 0);
     for (int v = 0; v < nv; ++v) {
         View64 o = view64(d, v);
         g->rowsweep[v] = o.row ? 1 : 0;
+        cs[v] = make_double2(o.c, o.s);
         for (int k = 0; k <= nb; ++k) {
             double u = ((double)k - 0.5 * nb + d.u_offset) * d.du;
             double px, py;
@@ -100,6 +102,8 @@ ct_status build_geometry(ct_geom *g)
     CT_HIP_CHECK(hipMalloc(&g->scale, scale.size() * sizeof(float)));
     CT_HIP_CHECK(hipMalloc(&g->inv, inv.size() * sizeof(float4)));
     CT_HIP_CHECK(hipMalloc(&g->d_rowsweep, nv * sizeof(int)));
+    CT_HIP_CHECK(hipMalloc(&g->cs, nv * sizeof(double2)));
+    CT_HIP_CHECK(hipMemcpy(g->cs, cs.data(), nv * sizeof(double2), hipMemcpyHostToDevice));
     CT_HIP_CHECK(hipMemcpy(g->bnd, bnd.data(), bnd.size() * sizeof(float2), hipMemcpyHostToDevice));
     CT_HIP_CHECK(hipMemcpy(g->scale, scale.data(), scale.size() * sizeof(float), hipMemcpyHostToDevice));
     CT_HIP_CHECK(hipMemcpy(g->inv, inv.data(), inv.size() * sizeof(float4), hipMemcpyHostToDevice));
@@ -126,6 +130,8 @@ void free_geometry(ct_geom *g)
     if (g->scale) (void)hipFree(g->scale);
     if (g->inv) (void)hipFree(g->inv);
     if (g->d_rowsweep) (void)hipFree(g->d_rowsweep);
+    if (g->cs) (void)hipFree(g->cs);
+    g->cs = nullptr;
     g->bnd = nullptr;
     g->scale = nullptr;
     g->inv = nullptr;

@@ -95,6 +95,7 @@ struct ct_geom {
     float *scale = nullptr;
     float4 *inv = nullptr;
     int *d_rowsweep = nullptr;
+    double2 *cs = nullptr;  // per view (cos beta, sin beta) in FP64, for the FBP-like start
     ct::GeomDev dev{};
     ct::Workspace ws;
     ct::GraphCache graphs;
@@ -144,6 +145,8 @@ hipError_t launch_back_update(const GeomDev &G, int mode, const float *r, int vs
                               float *out_back, const UpdateArgs &U, hipStream_t s);
 
 hipError_t launch_transpose(const float *x, float *xT, int nx, int ny, hipStream_t s);
+// FBP-like image of sinogram y into x (flat detector); q is an [nviews][nb] scratch sinogram.
+hipError_t launch_fbp(const ct_geom *g, const float *y, float *q, const double2 *cs, float *x, hipStream_t s);
 hipError_t launch_clip_copy(const float *in, float *out, float *outT, int nx, int ny, int zero, hipStream_t s);
 hipError_t launch_scale(float *x, size_t n, float a, hipStream_t s);
 hipError_t launch_fill(float *x, size_t n, float a, hipStream_t s);
