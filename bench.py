@@ -1,15 +1,17 @@
 """Benchmark: relaxed OS-LALM on one MI355X at the 512^2 fan-beam workload.
 
 Workload: 512x512 image (0.98 mm), flat detector 888 x 1.0239 mm, 984 views over 360 degrees,
-541/949 mm, seeded random-ellipse phantom with Poisson 1e5 + Gaussian sigma 5 noise, 41 subsets,
-alpha = 1.999, 100 iterations. One "step" is one complete solve through the C ABI (ct_rlalm_solve):
-D_L, initialisation and 100 outer iterations of 41 subiterations each, with y and w already in HBM.
-`value` is OS-RLALM outer iterations per second over the timed steps.
+541/949 mm, seeded random-ellipse phantom with Poisson 1e5 + Gaussian sigma 5 noise, 41 subsets in
+bit-reversed order, alpha = 1.999, 100 iterations. One "step" is one complete solve through the C ABI
+(ct_rlalm_solve): D_L, initialisation and 100 outer iterations of 41 subiterations each, with y and w
+already in HBM. `value` is OS-RLALM outer iterations per second over the timed steps.
 
-Also reported: the unrelaxed (alpha = 1) rate on the same GPU, the per-launch duration of both
-projector kernels (HIP events on the stream they run on) and the ALU roofline of the dominant one,
-time to 1 HU when a converged reference x* for this scan is available, and the FP64 CPU oracle's rate
-on a bounded sample (rank 0 only).
+Also reported: the unrelaxed (alpha = 1) rate on the same GPU; the rate with 16-bit storage; the
+uneven 32-slice batch (one launch per kernel per subiteration for all slices) against the same slices
+solved one after another; the per-launch duration of both projector kernels (HIP events on the stream
+they run on) and the ALU roofline of the dominant one; time to 1 HU from the zero and FBP-like starts
+when a converged reference x* for this scan is available; and the FP64 CPU oracle's rate on a bounded
+sample (rank 0 only).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -34,6 +36,7 @@ XSTAR = os.path.join(ROOT, "tests", "golden", "xstar_cfg2_seed100.npz")
 KERNEL_SRC = os.path.join(ROOT, "paper_1512_04564_amd", "csrc", "ct_kernels.hip")
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic_k_back_update_cfg2.json")
 COPY_BYTES = 256 * 2 ** 20   # calibration copy of the counter workload (bytes read = bytes written)
+ORDER = "bitrev"             # subset order of every benchmarked solve
 
 
 def kernel_source_hash() -> str:
@@ -65,7 +68,7 @@ def pmc_workload():
     y = torch.as_tensor(s.y, device="cuda:0")
     w = torch.as_tensor(s.w, device="cuda:0")
     x = torch.zeros((g.ny, g.nx), device="cuda:0")
-    p = api.Params(alpha=1.999, niters=2, start="zero")
+    p = api.Params(alpha=1.999, niters=2, subset_order=ORDER, start="zero")
     for _ in range(2):
         api.rlalm_solve(G, p, y, w, x)
     a = torch.ones(COPY_BYTES // 4, device="cuda:0")
@@ -102,7 +105,7 @@ def dd_work_counts(g):
 def oracle_baseline(g, s, iters):
     """The FP64 CPU oracle as it stands: `iters` outer iterations of Algorithm 1 (after D_L and init)."""
     import oracle
-    p = oracle.params(alpha=1.999, niters=1, nsubsets=g.nsubsets)
+    p = oracle.params(alpha=1.999, niters=1, nsubsets=g.nsubsets, subset_order=ORDER)
     y, w = s.y.astype(np.float64), s.w.astype(np.float64)
     dl = oracle.dl(g, w)
     x, gv, h = oracle.rlalm_init(g, p, y, w, dl, np.zeros((g.ny, g.nx)))
@@ -122,6 +125,8 @@ def main():
     ap.add_argument("--niters", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--no-batch", action="store_true", help="skip the uneven 32-slice batch")
+    ap.add_argument("--batch-iters", type=int, default=20)
     ap.add_argument("--pmc-workload", action="store_true", help="run the short counter workload and exit")
     args = ap.parse_args()
     if args.pmc_workload:
@@ -144,9 +149,19 @@ def main():
     x = torch.zeros((g.ny, g.nx), device=dev)
     stream = torch.cuda.current_stream()
 
-    def solve(alpha, niters, xref=None, trace=False):
-        p = api.Params(alpha=alpha, niters=niters, start="zero", fov_radius=synth.fov_radius(g))
+    def solve(alpha, niters, xref=None, trace=False, start="zero"):
+        p = api.Params(alpha=alpha, niters=niters, subset_order=ORDER, start=start, fov_radius=synth.fov_radius(g))
         return api.rlalm_solve(G, p, y, w, x, x_ref=xref, trace=trace)
+
+    def timed(fn, reps):
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps / 1e3
 
     for _ in range(args.warmup):
         solve(1.999, args.niters)
@@ -176,7 +191,7 @@ def main():
     # per-launch duration of the solve's two kernels: after a solve, its last subiteration's projection and
     # update kernels are replayed back to back between hipEvent pairs on the stream they run on
     kt_iters = 2
-    p_t = api.Params(alpha=1.999, niters=kt_iters, start="zero", time_kernels=True)
+    p_t = api.Params(alpha=1.999, niters=kt_iters, subset_order=ORDER, start="zero", time_kernels=True)
     api.rlalm_solve(G, p_t, y, w, x)
     kt = api.kernel_times(G)
     times = {"forward": kt["ms_forward"] / kt["n_forward"] * 1e-3, "update": kt["ms_update"] / kt["n_update"] * 1e-3}
@@ -206,26 +221,64 @@ def main():
     if roofline["traffic"] is not None:
         roofline["traffic_GBs"] = round(roofline["traffic"] / times[dom] / 1e9, 1)
 
-    # time to 1 HU against the oracle's converged reference, when it is available
+    # 16-bit storage of y, w, residual and projector image copies (float16 with w, beta scaled by 2^-6)
+    storage = {"f32": round(iters_per_s, 2)}
+    for st, dt, c in (("f16", torch.float16, 2.0 ** -6), ("bf16", torch.bfloat16, 1.0)):
+        Gs = api.Geometry(g, st)
+        ys, ws = y.to(dt), (w * c).to(dt)
+        ps = api.Params(alpha=1.999, niters=args.niters, subset_order=ORDER, start="zero", beta=1024.0 * c)
+        api.rlalm_solve(Gs, ps, ys, ws, x)
+        storage[st] = round(args.niters / timed(lambda: api.rlalm_solve(Gs, ps, ys, ws, x), 2), 2)
+        del Gs
+
+    # uneven batch: 11 x 256^2 / 492 views, 11 x 384^2 / 738, 10 x 512^2 / 984 (M = 41), one scan per
+    # class shared by its slices (the kernels' work does not depend on the data values)
+    batched = None
+    if not args.no_batch:
+        counts = (11, 11, 10)
+        cls_scans = [synth.noisy_scan(gc, 300 + i, truth=False) for i, gc in enumerate(synth.BATCH_CLASSES)]
+        geoms, ys_b, ws_b = [], [], []
+        for i, (gc, sc) in enumerate(zip(synth.BATCH_CLASSES, cls_scans)):
+            yb, wb = torch.as_tensor(sc.y, device=dev), torch.as_tensor(sc.w, device=dev)
+            for _ in range(counts[i]):
+                geoms.append(gc)
+                ys_b.append(yb)
+                ws_b.append(wb)
+        Gb = [api.Geometry(gc) for gc in geoms]
+        xs_b = [torch.zeros((gc.ny, gc.nx), device=dev) for gc in geoms]
+        pb = api.Params(alpha=1.999, niters=args.batch_iters, subset_order=ORDER, start="zero")
+        cfg = api.rlalm_solve_batched(Gb, pb, ys_b, ws_b, xs_b, autotune=True)
+        t_batch = timed(lambda: api.rlalm_solve_batched(Gb, pb, ys_b, ws_b, xs_b, autotune=True), 2)
+
+        def one_by_one():
+            for i in range(len(geoms)):
+                api.rlalm_solve(Gb[i], pb, ys_b[i], ws_b[i], xs_b[i])
+
+        one_by_one()
+        t_seq = timed(one_by_one, 2)
+        n = len(geoms)
+        batched = {"slices": n, "classes": "11 x 256^2/492 views/444 bins, 11 x 384^2/738/666, 10 x 512^2/984/888",
+                   "iters_per_solve": args.batch_iters, "seconds_batched": round(t_batch, 4),
+                   "seconds_one_by_one": round(t_seq, 4),
+                   "slice_iters_per_s": round(n * args.batch_iters / t_batch, 1),
+                   "speedup_vs_one_by_one": round(t_seq / t_batch, 3), "launch_shape": cfg}
+        del Gb, xs_b
+
+    # time to 1 HU against the oracle's converged reference, when it is available (zero and FBP-like starts)
     t1hu = None
     if os.path.exists(XSTAR):
         xstar = torch.as_tensor(np.load(XSTAR)["x"], device=dev)
         t1hu = {}
-        for alpha in (1.999, 1.0):
-            rows = solve(alpha, args.niters, xref=xstar, trace=True)
+        for alpha, start in ((1.999, "zero"), (1.999, "fbp"), (1.0, "zero"), (1.0, "fbp")):
+            rows = solve(alpha, args.niters, xref=xstar, trace=True, start=start)
             hit = [r["iter"] for r in rows if r["rmsd_hu"] <= 1.0]
             best = min(r["rmsd_hu"] for r in rows)
             entry = {"iters": hit[0] if hit else None, "best_rmsd_hu": round(best, 3),
                      "rmsd_hu_at": {str(r["iter"]): round(r["rmsd_hu"], 2) for r in rows if r["iter"] in (1, 5, 10, 20, 50, 100)}}
             if hit:
-                torch.cuda.synchronize()
-                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                a.record(stream)
-                solve(alpha, hit[0])
-                b.record(stream)
-                torch.cuda.synchronize()
-                entry["seconds"] = a.elapsed_time(b) / 1e3
-            t1hu[f"alpha={alpha}"] = entry
+                solve(alpha, hit[0], start=start)
+                entry["seconds"] = round(timed(lambda: solve(alpha, hit[0], start=start), 3), 5)
+            t1hu[f"alpha={alpha},start={start}"] = entry
 
     cpu = None
     if not args.no_cpu:
@@ -245,9 +298,12 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "2-D fan-beam PWLS, 512x512 0.98 mm, 888 bins x 1.0239 mm, 984 views, "
-                               "541/949 mm, 41 subsets, alpha 1.999, 100 iterations per solve, seed 100",
-                   "iters_per_step": args.niters, "subsets": M, "alpha": 1.999},
+                               "541/949 mm, 41 subsets (bit-reversed order), alpha 1.999, 100 iterations per "
+                               "solve, seed 100",
+                   "iters_per_step": args.niters, "subsets": M, "alpha": 1.999, "subset_order": ORDER},
         "unrelaxed_iters_per_s": round(iters_per_s_unrelaxed, 2),
+        "storage_iters_per_s": storage,
+        "batched": batched,
         "wall_s": round(wall, 3),
         "time_to_1hu": t1hu,
         "roofline": roofline,

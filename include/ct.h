@@ -44,7 +44,14 @@ typedef enum {
 
 typedef enum { CT_DET_FLAT = 0, CT_DET_ARC = 1 } ct_detector;
 
-/* Storage type of the sinogram inputs y and w (the image state is always float32). */
+/*
+ * Storage type of the solver's sinogram inputs y and w, of its residual block M w (A_m x - y) and of the
+ * image copies its forward projector reads. Sums are float32 in every mode, and the image state x, g, h
+ * and D_L stay float32; 16-bit values are rounded to nearest even on store. CT_BF16 keeps float32's
+ * range. CT_F16 overflows above 65504: w and the residual must stay below that; scaling w and beta by
+ * the same power of two leaves every iterate unchanged (the x-step's numerator and denominator both
+ * scale), which is how a caller brings large count-based weights into range.
+ */
 typedef enum { CT_F32 = 0, CT_F16 = 1, CT_BF16 = 2 } ct_dtype;
 
 typedef struct {
@@ -58,7 +65,7 @@ typedef struct {
     double beta0, span;  /* first view angle and angular span (rad); views at beta0 + span v / nviews */
     double dso, dsd;     /* source-isocentre and source-detector distances (mm), dsd > dso > 0      */
     int nsubsets;        /* M >= 1, nviews % M == 0                                                  */
-    int storage;         /* ct_dtype of y and w passed to the solver                                 */
+    int storage;         /* ct_dtype: solver storage of y, w, residual and projector image copies    */
 } ct_geom_desc;
 
 typedef struct ct_geom ct_geom; /* opaque: device geometry tables + solver workspace */
@@ -88,7 +95,7 @@ ct_status ct_forward(const ct_geom *g, int subset, const float *x, float *p, voi
 ct_status ct_back(const ct_geom *g, int subset, const float *r, float *x, void *stream);
 
 /*
- * x = FBP-like image of the sinogram y ([nviews][nb] float32), [ny][nx] float32, overwritten: per view a
+ * x = FBP-like image of the sinogram y ([nviews][nb], storage type), [ny][nx] float32, overwritten: per view a
  * cosine pre-weight on the detector magnified to the isocentre, the spatial Ram-Lak filter, then
  * pixel-driven back-projection with linear interpolation and the fan weight (dso / L)^2, clipped at zero.
  * Algorithm 1 starts from an FBP image; this is its plain, unwindowed form. Flat detector only
@@ -147,6 +154,31 @@ typedef struct {
  */
 ct_status ct_rlalm_solve(ct_geom *g, const ct_rlalm_params *p, const void *y, const void *w, float *x,
                          ct_trace_row *trace, void *stream);
+
+/*
+ * Batched solve of n independent slices (2-D scans of possibly different sizes) in lockstep: at every
+ * subiteration one forward-projection launch and one fused update launch cover all slices (a 1-D grid
+ * whose workgroups look up their slice), and each outer iteration is replayed from one captured
+ * hipGraph. The arithmetic per slice is that of ct_rlalm_solve (Algorithm 1 with rho_k(alpha)).
+ *   g[i]: a distinct handle per slice; all share nsubsets (M) and storage. y[i], w[i]: that slice's
+ *     sinograms in the storage type; x[i]: its float32 image (x0 on entry when p->start == 0, result
+ *     on exit). p applies to every slice; trace and time_kernels are not available here (CT_ERR_UNSUPPORTED).
+ *   autotune: 0 = default launch shape (16-wave projection workgroups, slices in the given order; with
+ *     n == 1 the result equals ct_rlalm_solve bit for bit); 1 = time the candidate shapes (8 or 16 waves
+ *     per projection workgroup; given order or largest slice first) on this set of slice shapes and
+ *     keep the fastest, cached per process for that set. The order never changes a result; the wave
+ *     count changes the projection's summation order.
+ *   chosen: if non-NULL, receives the launch shape used.
+ * Returns CT_ERR_DIVERGED (message names the slice) if any slice ends non-finite.
+ */
+typedef struct {
+    int fp_waves;          /* waves per forward-projection workgroup (8 or 16)                       */
+    int largest_first;     /* 1: slices ordered by decreasing work in the batched grids              */
+    double ms_subiteration;/* timed cost of one batched subiteration (autotune only; else 0)          */
+} ct_batch_config;
+ct_status ct_rlalm_solve_batched(ct_geom *const *g, int n, const ct_rlalm_params *p, const void *const *y,
+                                 const void *const *w, float *const *x, int autotune, ct_batch_config *chosen,
+                                 void *stream);
 
 /*
  * Low-level state interface (checkpoint / resume). The state after t subiterations is (x, g, h, t);

@@ -18,8 +18,8 @@ STATUS_NAMES = {0: "CT_OK", 1: "CT_ERR_INVALID_ARG", 2: "CT_ERR_OOM", 3: "CT_ERR
 
 #: Every entry point declared in include/ct.h.
 EXPORTS = ("ct_geom_create", "ct_geom_destroy", "ct_forward", "ct_back", "ct_fbp", "ct_rlalm_params_default",
-           "ct_rlalm_solve", "ct_rlalm_prepare", "ct_rlalm_init", "ct_rlalm_iterate", "ct_rlalm_kernel_times",
-           "ct_last_error")
+           "ct_rlalm_solve", "ct_rlalm_solve_batched", "ct_rlalm_prepare", "ct_rlalm_init", "ct_rlalm_iterate",
+           "ct_rlalm_kernel_times", "ct_last_error")
 
 
 class GeomDesc(ctypes.Structure):
@@ -43,6 +43,10 @@ class RlalmParams(ctypes.Structure):
 class KernelTimes(ctypes.Structure):
     _fields_ = [("n_forward", ctypes.c_longlong), ("n_update", ctypes.c_longlong), ("ms_forward", ctypes.c_double),
                 ("ms_update", ctypes.c_double)]
+
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("fp_waves", ctypes.c_int), ("largest_first", ctypes.c_int), ("ms_subiteration", ctypes.c_double)]
 
 
 class TraceRow(ctypes.Structure):
@@ -77,6 +81,8 @@ def load() -> ctypes.CDLL:
     L.ct_rlalm_params_default.argtypes = [ctypes.POINTER(RlalmParams)]
     L.ct_rlalm_params_default.restype = None
     L.ct_rlalm_solve.argtypes = [vp, ctypes.POINTER(RlalmParams), vp, vp, vp, ctypes.POINTER(TraceRow), vp]
+    L.ct_rlalm_solve_batched.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(RlalmParams), ctypes.POINTER(vp),
+                                         ctypes.POINTER(vp), ctypes.POINTER(vp), i, ctypes.POINTER(BatchConfig), vp]
     L.ct_rlalm_prepare.argtypes = [vp, ctypes.POINTER(RlalmParams), vp, vp, vp, vp]
     L.ct_rlalm_init.argtypes = [vp, ctypes.POINTER(RlalmParams), vp, vp, vp, vp, vp, vp, vp]
     L.ct_rlalm_iterate.argtypes = [vp, ctypes.POINTER(RlalmParams), vp, vp, vp, vp, vp, vp, vp, ll, ll, vp]

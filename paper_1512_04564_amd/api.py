@@ -1,8 +1,10 @@
 """Python front end of libctrlalm: geometry handles, projections and the relaxed OS-LALM solver.
 
 Same names as the C ABI (include/ct.h) minus the ``ct_`` prefix. Images are float32 CUDA tensors
-``[ny][nx]``; sinograms are float32 CUDA tensors ``[views][nb]``. Work is enqueued on torch's current
-stream (or the stream passed in). Nothing here computes: it checks shapes and forwards pointers.
+``[ny][nx]``; sinograms are CUDA tensors ``[views][nb]``: float32 for the projection operators, and the
+geometry's storage dtype (float32, float16 or bfloat16) for the solver's y and w. Work is enqueued on
+torch's current stream (or the stream passed in). Nothing here computes: it checks shapes and forwards
+pointers.
 """
 from __future__ import annotations
 
@@ -15,8 +17,8 @@ import torch
 from . import _lib
 from ._lib import CtError, GeomDesc, RlalmParams, TraceRow, check
 
-__all__ = ["Geometry", "Params", "forward", "back", "fbp", "rlalm_solve", "rlalm_prepare", "rlalm_init", "rlalm_iterate",
-           "kernel_times", "CtError"]
+__all__ = ["Geometry", "Params", "forward", "back", "fbp", "rlalm_solve", "rlalm_solve_batched", "rlalm_prepare",
+           "rlalm_init", "rlalm_iterate", "kernel_times", "CtError"]
 
 
 def _stream_handle(stream) -> int:
@@ -39,11 +41,19 @@ def _ptr(t: torch.Tensor, *, shape=None, name="tensor", dtype=torch.float32) -> 
     return t.data_ptr()
 
 
-class Geometry:
-    """Owning wrapper of a ``ct_geom`` handle (device tables + solver workspace)."""
+STORAGE = {"f32": (0, torch.float32), "f16": (1, torch.float16), "bf16": (2, torch.bfloat16)}
 
-    def __init__(self, geom, storage: int = 0):
+
+class Geometry:
+    """Owning wrapper of a ``ct_geom`` handle (device tables + solver workspace).
+
+    ``storage``: "f32", "f16" or "bf16" -- the dtype of the solver's sinogram inputs y and w, and of its
+    internal residual block and projector image copies (ct_geom_desc.storage)."""
+
+    def __init__(self, geom, storage: str = "f32"):
         self.desc_py = geom
+        self.storage = storage
+        storage, self.sino_dtype = STORAGE[storage]
         det = {"flat": 0, "arc": 1}[geom.det] if isinstance(geom.det, str) else int(geom.det)
         d = GeomDesc(geom.nx, geom.ny, geom.dx, geom.dy, geom.nb, geom.du, geom.u_offset, det, geom.nviews,
                      geom.beta0, geom.span, geom.dso, geom.dsd, geom.nsubsets, storage)
@@ -142,8 +152,8 @@ def fbp(g: Geometry, y: torch.Tensor, out: torch.Tensor | None = None, stream=No
     """FBP-like start image of the sinogram y: ``[ny][nx]`` float32."""
     if out is None:
         out = torch.empty(g.img_shape, dtype=torch.float32, device=y.device)
-    check(g._lib.ct_fbp(g.handle, _ptr(y, shape=(g.nviews, g.nb), name="y"), _ptr(out, shape=g.img_shape, name="out"),
-                        _stream_handle(stream)))
+    check(g._lib.ct_fbp(g.handle, _ptr(y, shape=(g.nviews, g.nb), name="y", dtype=g.sino_dtype),
+                        _ptr(out, shape=g.img_shape, name="out"), _stream_handle(stream)))
     return out
 
 
@@ -155,8 +165,9 @@ def rlalm_solve(g: Geometry, p: Params, y: torch.Tensor, w: torch.Tensor, x: tor
     if x_ref is not None:
         _ptr(x_ref, shape=g.img_shape, name="x_ref")
     rows = (TraceRow * max(p.niters, 1))() if trace else None
-    st = g._lib.ct_rlalm_solve(g.handle, ctypes.byref(cp), _ptr(y, shape=sino, name="y"),
-                               _ptr(w, shape=sino, name="w"), _ptr(x, shape=g.img_shape, name="x"),
+    sd = g.sino_dtype
+    st = g._lib.ct_rlalm_solve(g.handle, ctypes.byref(cp), _ptr(y, shape=sino, name="y", dtype=sd),
+                               _ptr(w, shape=sino, name="w", dtype=sd), _ptr(x, shape=g.img_shape, name="x"),
                                rows, _stream_handle(stream))
     check(st)
     if trace:
@@ -165,10 +176,30 @@ def rlalm_solve(g: Geometry, p: Params, y: torch.Tensor, w: torch.Tensor, x: tor
     return None
 
 
+def rlalm_solve_batched(geoms, p: Params, ys, ws, xs, *, autotune: bool = False, stream=None) -> dict:
+    """Solve len(geoms) independent slices in lockstep (one launch per kernel per subiteration for all
+    slices, one graph replay per iteration), in place on each ``xs[i]``. Returns the launch shape used:
+    ``{"fp_waves", "largest_first", "ms_subiteration"}``."""
+    n = len(geoms)
+    if not (len(ys) == len(ws) == len(xs) == n) or n == 0:
+        raise ValueError("geoms, ys, ws and xs must be non-empty and of equal length")
+    cp = p.to_c()
+    VP = ctypes.c_void_p * n
+    hs = VP(*[g.handle.value for g in geoms])
+    yp = VP(*[_ptr(y, shape=(g.nviews, g.nb), name="y", dtype=g.sino_dtype) for g, y in zip(geoms, ys)])
+    wp = VP(*[_ptr(w, shape=(g.nviews, g.nb), name="w", dtype=g.sino_dtype) for g, w in zip(geoms, ws)])
+    xp = VP(*[_ptr(x, shape=g.img_shape, name="x") for g, x in zip(geoms, xs)])
+    cfg = _lib.BatchConfig()
+    check(geoms[0]._lib.ct_rlalm_solve_batched(hs, n, ctypes.byref(cp), yp, wp, xp, int(autotune), ctypes.byref(cfg),
+                                               _stream_handle(stream)))
+    return dict(fp_waves=cfg.fp_waves, largest_first=bool(cfg.largest_first), ms_subiteration=cfg.ms_subiteration)
+
+
 def rlalm_prepare(g: Geometry, p: Params, w: torch.Tensor, dl: torch.Tensor, kappa: torch.Tensor | None = None,
                   stream=None):
     cp = p.to_c()
-    check(g._lib.ct_rlalm_prepare(g.handle, ctypes.byref(cp), _ptr(w, shape=(g.nviews, g.nb), name="w"),
+    check(g._lib.ct_rlalm_prepare(g.handle, ctypes.byref(cp),
+                                  _ptr(w, shape=(g.nviews, g.nb), name="w", dtype=g.sino_dtype),
                                   _ptr(dl, shape=g.img_shape, name="dl"),
                                   _ptr(kappa, shape=g.img_shape, name="kappa") if kappa is not None else None,
                                   _stream_handle(stream)))
@@ -177,8 +208,9 @@ def rlalm_prepare(g: Geometry, p: Params, w: torch.Tensor, dl: torch.Tensor, kap
 def rlalm_init(g: Geometry, p: Params, y, w, dl, x, gv, h, stream=None):
     cp = p.to_c()
     sino = (g.nviews, g.nb)
-    check(g._lib.ct_rlalm_init(g.handle, ctypes.byref(cp), _ptr(y, shape=sino, name="y"),
-                               _ptr(w, shape=sino, name="w"), _ptr(dl, shape=g.img_shape, name="dl"),
+    sd = g.sino_dtype
+    check(g._lib.ct_rlalm_init(g.handle, ctypes.byref(cp), _ptr(y, shape=sino, name="y", dtype=sd),
+                               _ptr(w, shape=sino, name="w", dtype=sd), _ptr(dl, shape=g.img_shape, name="dl"),
                                _ptr(x, shape=g.img_shape, name="x"), _ptr(gv, shape=g.img_shape, name="g"),
                                _ptr(h, shape=g.img_shape, name="h"), _stream_handle(stream)))
 
@@ -186,8 +218,9 @@ def rlalm_init(g: Geometry, p: Params, y, w, dl, x, gv, h, stream=None):
 def rlalm_iterate(g: Geometry, p: Params, y, w, dl, x, gv, h, t0: int, nsub: int, kappa=None, stream=None):
     cp = p.to_c()
     sino = (g.nviews, g.nb)
-    check(g._lib.ct_rlalm_iterate(g.handle, ctypes.byref(cp), _ptr(y, shape=sino, name="y"),
-                                  _ptr(w, shape=sino, name="w"), _ptr(dl, shape=g.img_shape, name="dl"),
+    sd = g.sino_dtype
+    check(g._lib.ct_rlalm_iterate(g.handle, ctypes.byref(cp), _ptr(y, shape=sino, name="y", dtype=sd),
+                                  _ptr(w, shape=sino, name="w", dtype=sd), _ptr(dl, shape=g.img_shape, name="dl"),
                                   _ptr(kappa, shape=g.img_shape, name="kappa") if kappa is not None else None,
                                   _ptr(x, shape=g.img_shape, name="x"), _ptr(gv, shape=g.img_shape, name="g"),
                                   _ptr(h, shape=g.img_shape, name="h"), int(t0), int(nsub), _stream_handle(stream)))

@@ -5,9 +5,13 @@
 // x-step of subiteration t+1). An outer iteration (M subiterations) is captured once as a hipGraph and
 // replayed; the subiteration index is read from a device counter that a one-thread kernel at the end of
 // the graph advances, so one captured graph serves every iteration.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -60,7 +64,8 @@ ct_status check_desc(const ct_geom_desc *d)
         return fail(CT_ERR_INVALID_ARG, "nsubsets must be >= 1 and divide nviews");
     if (!(d->dso > 0) || !(d->dsd > d->dso)) return fail(CT_ERR_INVALID_ARG, "need dsd > dso > 0");
     if (d->det != CT_DET_FLAT && d->det != CT_DET_ARC) return fail(CT_ERR_INVALID_ARG, "det must be flat or arc");
-    if (d->storage != CT_F32) return fail(CT_ERR_UNSUPPORTED, "only float32 storage is implemented");
+    if (d->storage != CT_F32 && d->storage != CT_F16 && d->storage != CT_BF16)
+        return fail(CT_ERR_INVALID_ARG, "storage must be CT_F32, CT_F16 or CT_BF16");
     double hx = 0.5 * d->nx * d->dx, hy = 0.5 * d->ny * d->dy;
     if (std::sqrt(hx * hx + hy * hy) >= 0.95 * d->dso)
         return fail(CT_ERR_INVALID_ARG, "the image must lie well inside the source circle");
@@ -113,6 +118,10 @@ ct_status ensure_workspace(ct_geom *g, size_t r_views, size_t rho_len)
     CT_TRY(dev_alloc(&W.xb, npix));
     CT_TRY(dev_alloc(&W.xta, npix));
     CT_TRY(dev_alloc(&W.xtb, npix));
+    if (d.storage != CT_F32) {
+        CT_TRY(dev_alloc(reinterpret_cast<uint16_t **>(&W.xca), npix));
+        CT_TRY(dev_alloc(reinterpret_cast<uint16_t **>(&W.xcb), npix));
+    }
     CT_TRY(dev_alloc(&W.tmp, npix));
     CT_TRY(dev_alloc(&W.tbase, 4));
     CT_TRY(dev_alloc(&W.red, 3 + 3 * 256 + 8));
@@ -137,6 +146,8 @@ void free_workspace(ct_geom *g)
     dev_free(&W.xb);
     dev_free(&W.xta);
     dev_free(&W.xtb);
+    dev_free(&W.xca);
+    dev_free(&W.xcb);
     dev_free(&W.tmp);
     dev_free(&W.r);
     dev_free(&W.rho);
@@ -185,11 +196,49 @@ void drop_graph_cache(ct_geom *g)
 struct Ctx {
     ct_geom *g;
     const ct_rlalm_params *p;
-    const float *y, *w, *dl, *kappa;
+    const void *y, *w;   // storage type
+    const float *dl, *kappa;
     float *gv, *h;
     std::vector<int> order;
-    int M, nvm;
+    int M, nvm, dtype;
 };
+
+// The forward projector's input copies of ping-pong buffer A (a != 0) or B: float32 storage reads the
+// image itself, 16-bit storage its rounded copy; the transposed copy is always in the storage type.
+const void *proj_img(const Workspace &W, int dtype, int a) { return dtype == CT_F32 ? (a ? W.xa : W.xb) : (a ? W.xca : W.xcb); }
+void *proj_imgT(const Workspace &W, int a) { return a ? W.xta : W.xtb; }
+void *proj_copy(const Workspace &W, int dtype, int a) { return dtype == CT_F32 ? nullptr : (a ? W.xca : W.xcb); }
+
+FpLaunch fp_launch(const GeomDev &G, const void *img, const void *imgT, int vstart, int vstride, int nv, const void *y,
+                   const void *w, float mscale, void *out)
+{
+    FpLaunch a;
+    a.G = G;
+    a.img = img;
+    a.imgT = imgT;
+    a.y = y;
+    a.w = w;
+    a.out = out;
+    a.vstart = vstart;
+    a.vstride = vstride;
+    a.nv = nv;
+    a.mscale = mscale;
+    return a;
+}
+
+BpLaunch bp_launch(const GeomDev &G, const void *r, int vstart, int vstride, int nv, float *out_back,
+                   const UpdateArgs &U)
+{
+    BpLaunch a;
+    a.G = G;
+    a.r = r;
+    a.vstart = vstart;
+    a.vstride = vstride;
+    a.nv = nv;
+    a.out_back = out_back;
+    a.U = U;
+    return a;
+}
 
 UpdateArgs make_update(const Ctx &c)
 {
@@ -217,15 +266,17 @@ hipError_t launch_subiter_part(const Ctx &c, long long t_abs, long long tofs, in
     Workspace &W = c.g->ws;
     const GeomDev &G = c.g->dev;
     const int m = c.order[(size_t)(t_abs % c.M)];
-    const float *x = cur_is_a ? W.xa : W.xb;
-    const float *xT = cur_is_a ? W.xta : W.xtb;
-    if (part == 0) return launch_forward(G, x, xT, 0, m, c.M, c.nvm, FP_RESIDUAL, c.y, c.w, (float)c.M, W.r, s);
+    if (part == 0)
+        return launch_forward(fp_launch(G, proj_img(W, c.dtype, cur_is_a), proj_imgT(W, cur_is_a), m, c.M, c.nvm, c.y,
+                                        c.w, (float)c.M, W.r),
+                              0, FP_RESIDUAL, c.dtype, s);
     UpdateArgs U = make_update(c);
-    U.x = x;
+    U.x = cur_is_a ? W.xa : W.xb;
     U.x_next = cur_is_a ? W.xb : W.xa;
-    U.xT_next = cur_is_a ? W.xtb : W.xta;
+    U.xc_next = proj_copy(W, c.dtype, !cur_is_a);
+    U.xT_next = proj_imgT(W, !cur_is_a);
     U.tofs = tofs;
-    return launch_back_update(G, BP_FULL, W.r, m, c.M, c.nvm, nullptr, U, s);
+    return launch_back_update(bp_launch(G, W.r, m, c.M, c.nvm, nullptr, U), BP_FULL, c.dtype, c.dtype, s);
 }
 
 hipError_t launch_subiter(const Ctx &c, long long t_abs, long long tofs, int cur_is_a, hipStream_t s)
@@ -259,9 +310,10 @@ ct_status run_subiters(const Ctx &c, long long t0, long long nsub, int use_graph
         UpdateArgs U = make_update(c);
         U.x = W.xa;
         U.x_next = W.xb;
+        U.xc_next = proj_copy(W, c.dtype, 0);
         U.xT_next = W.xtb;
         U.tofs = t0;
-        CT_HIP_CHECK(launch_back_update(G, BP_XSTEP, nullptr, 0, 1, 0, nullptr, U, s));
+        CT_HIP_CHECK(launch_back_update(bp_launch(G, nullptr, 0, 1, 0, nullptr, U), BP_XSTEP, c.dtype, c.dtype, s));
     }
     int cur_a = 0;  // x^(t0+1) is in B
     long long t = t0;
@@ -384,8 +436,9 @@ Ctx make_ctx(ct_geom *g, const ct_rlalm_params *p, const void *y, const void *w,
     Ctx c;
     c.g = g;
     c.p = p;
-    c.y = static_cast<const float *>(y);
-    c.w = static_cast<const float *>(w);
+    c.y = y;
+    c.w = w;
+    c.dtype = g->desc.storage;
     c.dl = dl;
     c.kappa = (p->kappa && kappa) ? kappa : nullptr;
     c.gv = gv;
@@ -396,23 +449,24 @@ Ctx make_ctx(ct_geom *g, const ct_rlalm_params *p, const void *y, const void *w,
     return c;
 }
 
-ct_status do_prepare(ct_geom *g, const ct_rlalm_params *p, const float *w, float *dl, float *kappa, hipStream_t s)
+ct_status do_prepare(ct_geom *g, const ct_rlalm_params *p, const void *w, float *dl, float *kappa, hipStream_t s)
 {
     CT_TRY(ensure_workspace(g, g->desc.nviews, 4));
     Workspace &W = g->ws;
     const GeomDev &G = g->dev;
     const int nv = g->desc.nviews;
+    const int dt = g->desc.storage;
     const size_t npix = W.npix;
-    // D_L = A' (w .* A 1) over all views
-    CT_HIP_CHECK(launch_forward(G, nullptr, nullptr, 1, 0, 1, nv, FP_WEIGHTED, nullptr, w, 1.f, W.r, s));
     UpdateArgs U;
-    CT_HIP_CHECK(launch_back_update(G, BP_BACK, W.r, 0, 1, nv, dl, U, s));
+    // D_L = A' (w .* A 1) over all views (float32 intermediate whatever the storage type)
+    CT_HIP_CHECK(launch_forward(fp_launch(G, nullptr, nullptr, 0, 1, nv, nullptr, w, 1.f, W.r), 1, FP_WEIGHTED, dt, s));
+    CT_HIP_CHECK(launch_back_update(bp_launch(G, W.r, 0, 1, nv, dl, U), BP_BACK, CT_F32, CT_F32, s));
     if (p->dl_scale != 1.0) CT_HIP_CHECK(launch_scale(dl, npix, (float)p->dl_scale, s));
     if (p->kappa && kappa) {
         // kappa = sqrt(A'w / A'1)
-        CT_HIP_CHECK(launch_back_update(G, BP_BACK, w, 0, 1, nv, kappa, U, s));
+        CT_HIP_CHECK(launch_back_update(bp_launch(G, w, 0, 1, nv, kappa, U), BP_BACK, dt, CT_F32, s));
         CT_HIP_CHECK(launch_fill(W.r, (size_t)nv * g->desc.nb, 1.f, s));
-        CT_HIP_CHECK(launch_back_update(G, BP_BACK, W.r, 0, 1, nv, W.tmp, U, s));
+        CT_HIP_CHECK(launch_back_update(bp_launch(G, W.r, 0, 1, nv, W.tmp, U), BP_BACK, CT_F32, CT_F32, s));
         CT_HIP_CHECK(launch_kappa(kappa, W.tmp, kappa, npix, s));
     }
     return CT_OK;
@@ -424,18 +478,183 @@ ct_status do_init(const Ctx &c, const float *x_in, int zero_start, hipStream_t s
     ct_geom *g = c.g;
     Workspace &W = g->ws;
     const GeomDev &G = g->dev;
-    CT_HIP_CHECK(launch_clip_copy(x_in, W.xa, W.xta, g->desc.nx, g->desc.ny, zero_start, s));
+    CT_HIP_CHECK(launch_clip_copy(x_in, W.xa, proj_copy(W, c.dtype, 1), W.xta, g->desc.nx, g->desc.ny, zero_start,
+                                  c.dtype, s));
     UpdateArgs U = make_update(c);
     U.x = W.xa;
+    const void *img = proj_img(W, c.dtype, 1);
     if (c.p->init_full) {
-        CT_HIP_CHECK(launch_forward(G, W.xa, W.xta, 0, 0, 1, g->desc.nviews, FP_RESIDUAL, c.y, c.w, 1.f, W.r, s));
-        CT_HIP_CHECK(launch_back_update(G, BP_INIT, W.r, 0, 1, g->desc.nviews, nullptr, U, s));
+        const int nv = g->desc.nviews;
+        CT_HIP_CHECK(launch_forward(fp_launch(G, img, W.xta, 0, 1, nv, c.y, c.w, 1.f, W.r), 0, FP_RESIDUAL, c.dtype, s));
+        CT_HIP_CHECK(launch_back_update(bp_launch(G, W.r, 0, 1, nv, nullptr, U), BP_INIT, c.dtype, c.dtype, s));
     } else {
         const int m = c.order[(size_t)c.M - 1];
-        CT_HIP_CHECK(launch_forward(G, W.xa, W.xta, 0, m, c.M, c.nvm, FP_RESIDUAL, c.y, c.w, (float)c.M, W.r, s));
-        CT_HIP_CHECK(launch_back_update(G, BP_INIT, W.r, m, c.M, c.nvm, nullptr, U, s));
+        CT_HIP_CHECK(launch_forward(fp_launch(G, img, W.xta, m, c.M, c.nvm, c.y, c.w, (float)c.M, W.r), 0, FP_RESIDUAL,
+                                    c.dtype, s));
+        CT_HIP_CHECK(launch_back_update(bp_launch(G, W.r, m, c.M, c.nvm, nullptr, U), BP_INIT, c.dtype, c.dtype, s));
     }
     return CT_OK;
+}
+
+// ---- batched solve ----------------------------------------------------------------------------
+
+// Slice table of a batch in a given slice order, with contiguous workgroup ranges. Buffer index 0 is
+// ping-pong buffer A, 1 is B.
+std::vector<SliceDev> slice_table(const std::vector<Ctx> &cs, const std::vector<int> &order, int fp_waves,
+                                  int *nwg_fp, int *nwg_bp)
+{
+    std::vector<SliceDev> tab;
+    int fp = 0, bp = 0;
+    for (int i : order) {
+        const Ctx &c = cs[(size_t)i];
+        const Workspace &W = c.g->ws;
+        SliceDev S;
+        S.G = c.g->dev;
+        S.M = c.M;
+        S.nvm = c.nvm;
+        S.y = c.y;
+        S.w = c.w;
+        S.r = W.r;
+        S.x[0] = W.xa;
+        S.x[1] = W.xb;
+        S.xc[0] = const_cast<void *>(proj_img(W, c.dtype, 1));
+        S.xc[1] = const_cast<void *>(proj_img(W, c.dtype, 0));
+        S.xt[0] = W.xta;
+        S.xt[1] = W.xtb;
+        S.gv = c.gv;
+        S.h = c.h;
+        S.dl = c.dl;
+        S.kappa = c.kappa;
+        S.fp_begin = fp;
+        fp += forward_workgroups(S.G, S.nvm, fp_waves);
+        S.fp_end = fp;
+        S.bp_begin = bp;
+        bp += update_workgroups(S.G);
+        S.bp_end = bp;
+        tab.push_back(S);
+    }
+    *nwg_fp = fp;
+    *nwg_bp = bp;
+    return tab;
+}
+
+BatchUpdate batch_update(const Ctx &c, long long tofs)
+{
+    const UpdateArgs U = make_update(c);
+    BatchUpdate u;
+    u.rho = U.rho;
+    u.tbase = U.tbase;
+    u.tofs = tofs;
+    u.alpha = U.alpha;
+    u.algorithm = U.algorithm;
+    u.potential = U.potential;
+    u.huber = U.huber;
+    u.delta = U.delta;
+    u.beta_ax = U.beta_ax;
+    u.beta_dg = U.beta_dg;
+    return u;
+}
+
+// One batched subiteration (subset m; tofs relative to the device counter), images in buffer par.
+hipError_t batch_subiter(const SliceDev *dtab, int ns, int nwg_fp, int nwg_bp, int m, int par, const BatchUpdate &u,
+                         int dtype, int fp_waves, hipStream_t s)
+{
+    hipError_t e = launch_forward_batch(dtab, ns, nwg_fp, m, par, dtype, fp_waves, s);
+    if (e != hipSuccess) return e;
+    return launch_update_batch(dtab, ns, nwg_bp, m, par, u, dtype, s);
+}
+
+struct BatchKey {
+    int device;
+    std::vector<int> shape;
+    bool operator<(const BatchKey &o) const { return device != o.device ? device < o.device : shape < o.shape; }
+};
+
+std::mutex g_tune_mu;
+std::map<BatchKey, ct_batch_config> g_tune_cache;
+
+// Device copy of a slice table (caller frees).
+ct_status upload_table(const std::vector<SliceDev> &tab, SliceDev **dtab, hipStream_t s)
+{
+    CT_TRY(dev_alloc(dtab, tab.size()));
+    CT_HIP_CHECK(hipMemcpyAsync(*dtab, tab.data(), tab.size() * sizeof(SliceDev), hipMemcpyHostToDevice, s));
+    CT_HIP_CHECK(hipStreamSynchronize(s));   // the host table may go out of scope
+    return CT_OK;
+}
+
+// Times each candidate launch shape on the prepared slices (two subiterations of warm-up, then kReps
+// timed); it overwrites the slices' ping-pong images, g, h and residual blocks, which the
+// initialisation that follows rewrites.
+ct_status tune_batch(const std::vector<Ctx> &cs, hipStream_t s, ct_batch_config *best)
+{
+    constexpr int kReps = 6;
+    const int n = (int)cs.size();
+    std::vector<int> given(n), largest(n);
+    std::iota(given.begin(), given.end(), 0);
+    largest = given;
+    std::stable_sort(largest.begin(), largest.end(), [&](int a, int b) {
+        auto work = [&](int i) {
+            const ct_geom_desc &d = cs[(size_t)i].g->desc;
+            return (double)d.nx * d.ny * cs[(size_t)i].nvm;
+        };
+        return work(a) > work(b);
+    });
+    for (const Ctx &c : cs) {   // zero images and copies, so that the timed launches read defined data
+        const Workspace &W = c.g->ws;
+        CT_HIP_CHECK(launch_clip_copy(W.xa, W.xa, proj_copy(W, c.dtype, 1), W.xta, c.g->desc.nx, c.g->desc.ny, 1,
+                                      c.dtype, s));
+        CT_HIP_CHECK(launch_clip_copy(W.xb, W.xb, proj_copy(W, c.dtype, 0), W.xtb, c.g->desc.nx, c.g->desc.ny, 1,
+                                      c.dtype, s));
+        CT_HIP_CHECK(launch_fill(c.gv, W.npix, 0.f, s));
+        CT_HIP_CHECK(launch_fill(c.h, W.npix, 0.f, s));
+    }
+    CT_HIP_CHECK(launch_set_counter(cs[0].g->ws.tbase, 0, s));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    CT_HIP_CHECK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(CT_ERR_HIP, "hipEventCreate failed");
+    }
+    ct_status st = CT_OK;
+    best->ms_subiteration = 1e30;
+    const int M = cs[0].M;
+    for (int lf = 0; lf < 2 && st == CT_OK; ++lf) {
+        if (lf == 1 && largest == given) continue;
+        for (int waves : {16, 8}) {
+            int nfp = 0, nbp = 0;
+            std::vector<SliceDev> tab = slice_table(cs, lf ? largest : given, waves, &nfp, &nbp);
+            SliceDev *dtab = nullptr;
+            st = upload_table(tab, &dtab, s);
+            if (st != CT_OK) break;
+            const BatchUpdate u = batch_update(cs[0], 0);
+            hipError_t e = hipSuccess;
+            int par = 1;
+            for (int r = 0; r < 2 + kReps && e == hipSuccess; ++r) {
+                if (r == 2) e = hipEventRecord(e0, s);
+                if (e == hipSuccess)
+                    e = batch_subiter(dtab, n, nfp, nbp, cs[0].order[(size_t)(r % M)], par, u, cs[0].dtype, waves, s);
+                par ^= 1;
+            }
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            (void)hipFree(dtab);
+            if (e != hipSuccess) {
+                st = fail(CT_ERR_HIP, std::string("batch tuning: ") + hipGetErrorString(e));
+                break;
+            }
+            const double per = ms / kReps;
+            if (per < best->ms_subiteration) {
+                best->ms_subiteration = per;
+                best->fp_waves = waves;
+                best->largest_first = lf;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
 }
 
 }  // namespace
@@ -531,7 +750,8 @@ ct_status ct_forward(const ct_geom *gc, int subset, const float *x, float *p, vo
     CT_TRY(ensure_workspace(g, 0, 4));
     hipStream_t s = as_stream(stream);
     CT_HIP_CHECK(launch_transpose(x, g->ws.tmp, g->desc.nx, g->desc.ny, s));
-    CT_HIP_CHECK(launch_forward(g->dev, x, g->ws.tmp, 0, vs, vst, nv, FP_PLAIN, nullptr, nullptr, 1.f, p, s));
+    CT_HIP_CHECK(launch_forward(fp_launch(g->dev, x, g->ws.tmp, vs, vst, nv, nullptr, nullptr, 1.f, p), 0, FP_PLAIN,
+                                CT_F32, s));
     return CT_OK;
 }
 
@@ -542,7 +762,7 @@ ct_status ct_back(const ct_geom *gc, int subset, const float *r, float *x, void 
     int vs, vst, nv;
     CT_TRY(subset_range(g, subset, &vs, &vst, &nv));
     UpdateArgs U;
-    CT_HIP_CHECK(launch_back_update(g->dev, BP_BACK, r, vs, vst, nv, x, U, as_stream(stream)));
+    CT_HIP_CHECK(launch_back_update(bp_launch(g->dev, r, vs, vst, nv, x, U), BP_BACK, CT_F32, CT_F32, as_stream(stream)));
     return CT_OK;
 }
 
@@ -552,7 +772,7 @@ ct_status ct_fbp(const ct_geom *gc, const void *y, float *x, void *stream)
     ct_geom *g = const_cast<ct_geom *>(gc);
     if (g->desc.det != CT_DET_FLAT) return fail(CT_ERR_UNSUPPORTED, "the FBP-like start supports the flat detector only");
     CT_TRY(ensure_workspace(g, g->desc.nviews, 4));
-    CT_HIP_CHECK(launch_fbp(g, static_cast<const float *>(y), g->ws.r, g->cs, x, as_stream(stream)));
+    CT_HIP_CHECK(launch_fbp(g, y, g->desc.storage, g->ws.r, g->cs, x, as_stream(stream)));
     return CT_OK;
 }
 
@@ -560,7 +780,7 @@ ct_status ct_rlalm_prepare(ct_geom *g, const ct_rlalm_params *p, const void *w, 
 {
     if (!g || !w || !dl) return fail(CT_ERR_INVALID_ARG, "NULL argument");
     CT_TRY(check_params(p));
-    return do_prepare(g, p, static_cast<const float *>(w), dl, kappa, as_stream(stream));
+    return do_prepare(g, p, w, dl, kappa, as_stream(stream));
 }
 
 ct_status ct_rlalm_init(ct_geom *g, const ct_rlalm_params *p, const void *y, const void *w, const float *dl, float *x,
@@ -614,9 +834,9 @@ ct_status ct_rlalm_solve(ct_geom *g, const ct_rlalm_params *p, const void *y, co
     CT_TRY(upload_rho(g, p, nsub + 2, s));
     if (p->start == 2) {   // FBP-like start image, written into x
         if (g->desc.det != CT_DET_FLAT) return fail(CT_ERR_UNSUPPORTED, "the FBP-like start supports the flat detector only");
-        CT_HIP_CHECK(launch_fbp(g, static_cast<const float *>(y), W.r, g->cs, x, s));
+        CT_HIP_CHECK(launch_fbp(g, y, g->desc.storage, W.r, g->cs, x, s));
     }
-    CT_TRY(do_prepare(g, p, static_cast<const float *>(w), W.dl, p->kappa ? W.kappa : nullptr, s));
+    CT_TRY(do_prepare(g, p, w, W.dl, p->kappa ? W.kappa : nullptr, s));
     Ctx c = make_ctx(g, p, y, w, W.dl, W.kappa, W.gv, W.h);
     CT_TRY(do_init(c, x, p->start == 1, s));
     int fin = -1;
@@ -631,6 +851,153 @@ ct_status ct_rlalm_solve(ct_geom *g, const ct_rlalm_params *p, const void *y, co
     CT_HIP_CHECK(hipStreamSynchronize(s));
     if (host[2] != 0.0) return fail(CT_ERR_DIVERGED, "non-finite values in the final state");
     if (p->time_kernels && nsub > 0) CT_TRY(time_last_subiteration(c, nsub - 1, fin == 0 ? 0 : 1, s));
+    return CT_OK;
+}
+
+ct_status ct_rlalm_solve_batched(ct_geom *const *gs, int n, const ct_rlalm_params *p, const void *const *y,
+                                 const void *const *w, float *const *x, int autotune, ct_batch_config *chosen,
+                                 void *stream)
+{
+    if (!gs || !y || !w || !x || n < 1) return fail(CT_ERR_INVALID_ARG, "NULL argument or n < 1");
+    CT_TRY(check_params(p));
+    if (p->time_kernels) return fail(CT_ERR_UNSUPPORTED, "time_kernels is not available in the batched solve");
+    if (autotune != 0 && autotune != 1) return fail(CT_ERR_INVALID_ARG, "autotune must be 0 or 1");
+    for (int i = 0; i < n; ++i) {
+        if (!gs[i] || !y[i] || !w[i] || !x[i]) return fail(CT_ERR_INVALID_ARG, "NULL slice argument");
+        if (gs[i]->desc.nsubsets != gs[0]->desc.nsubsets || gs[i]->desc.storage != gs[0]->desc.storage)
+            return fail(CT_ERR_INVALID_ARG, "all slices must share nsubsets and storage");
+        if (gs[i]->device != gs[0]->device) return fail(CT_ERR_INVALID_ARG, "all slices must be on one device");
+        if (p->start == 2 && gs[i]->desc.det != CT_DET_FLAT)
+            return fail(CT_ERR_UNSUPPORTED, "the FBP-like start supports the flat detector only");
+        for (int j = 0; j < i; ++j)
+            if (gs[j] == gs[i]) return fail(CT_ERR_INVALID_ARG, "each slice needs its own handle");
+    }
+    hipStream_t s = as_stream(stream);
+    const long long nsub = (long long)p->niters * gs[0]->desc.nsubsets;
+    std::vector<Ctx> cs;
+    for (int i = 0; i < n; ++i) {
+        ct_geom *g = gs[i];
+        CT_TRY(ensure_workspace(g, g->desc.nviews, (size_t)(nsub + 2)));
+        Workspace &W = g->ws;
+        CT_TRY(dev_alloc(&W.dl, W.npix));
+        CT_TRY(dev_alloc(&W.gv, W.npix));
+        CT_TRY(dev_alloc(&W.h, W.npix));
+        if (p->kappa) CT_TRY(dev_alloc(&W.kappa, W.npix));
+        if (i == 0) CT_TRY(upload_rho(g, p, nsub + 2, s));
+        if (p->start == 2) CT_HIP_CHECK(launch_fbp(g, y[i], g->desc.storage, W.r, g->cs, x[i], s));
+        CT_TRY(do_prepare(g, p, w[i], W.dl, p->kappa ? W.kappa : nullptr, s));
+        cs.push_back(make_ctx(g, p, y[i], w[i], W.dl, W.kappa, W.gv, W.h));
+    }
+    // every slice reads the rho table and subiteration counter of slice 0
+    const Workspace &W0 = gs[0]->ws;
+
+    ct_batch_config cfg{16, 0, 0.0};
+    if (autotune) {
+        BatchKey key{gs[0]->device, {}};
+        for (int i = 0; i < n; ++i) {
+            const ct_geom_desc &d = gs[i]->desc;
+            key.shape.insert(key.shape.end(), {d.nx, d.ny, d.nb, d.nviews, d.nsubsets, d.storage});
+        }
+        bool have = false;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune_cache.find(key);
+            if (it != g_tune_cache.end()) {
+                cfg = it->second;
+                have = true;
+            }
+        }
+        if (!have) {
+            CT_TRY(tune_batch(cs, s, &cfg));
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune_cache[key] = cfg;
+        }
+    }
+    if (chosen) *chosen = cfg;
+
+    // initial state of every slice, then the x-step of subiteration 0 (A -> B)
+    for (int i = 0; i < n; ++i) {
+        const Ctx &c = cs[(size_t)i];
+        CT_TRY(do_init(c, x[i], p->start == 1, s));
+        Workspace &W = c.g->ws;
+        UpdateArgs U = make_update(c);
+        U.rho = W0.rho;
+        U.tbase = W0.tbase;
+        U.x = W.xa;
+        U.x_next = W.xb;
+        U.xc_next = proj_copy(W, c.dtype, 0);
+        U.xT_next = W.xtb;
+        U.tofs = 0;
+        CT_HIP_CHECK(launch_set_counter(W0.tbase, 0, s));
+        CT_HIP_CHECK(launch_back_update(bp_launch(c.g->dev, nullptr, 0, 1, 0, nullptr, U), BP_XSTEP, c.dtype, c.dtype, s));
+    }
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    if (cfg.largest_first)
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            auto work = [&](int i) { return (double)gs[i]->desc.nx * gs[i]->desc.ny * cs[(size_t)i].nvm; };
+            return work(a) > work(b);
+        });
+    int nfp = 0, nbp = 0;
+    std::vector<SliceDev> tab = slice_table(cs, order, cfg.fp_waves, &nfp, &nbp);
+    SliceDev *dtab = nullptr;
+    CT_TRY(upload_table(tab, &dtab, s));
+    struct Guard {
+        SliceDev *p;
+        ~Guard() { if (p) (void)hipFree(p); }
+    } guard{dtab};
+
+    const int M = cs[0].M;
+    const int dt = cs[0].dtype;
+    const std::vector<int> &sub = cs[0].order;
+    int par = 1;   // x^(1) is in B
+    long long t = 0;
+    const int L = (M % 2 == 0) ? M : 2 * M;
+    if (p->use_graph && nsub >= L) {
+        hipStream_t cap = nullptr;
+        CT_HIP_CHECK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        for (int j = 0; j < L && e == hipSuccess; ++j)
+            e = batch_subiter(dtab, n, nfp, nbp, sub[(size_t)(j % M)], (par + j) & 1, batch_update(cs[0], j), dt,
+                              cfg.fp_waves, cap);
+        hipError_t e2 = hipStreamEndCapture(cap, &graph);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (; e == hipSuccess && nsub - t >= L; t += L) {
+            e = launch_set_counter(W0.tbase, (int)t, s);
+            if (e == hipSuccess) e = hipGraphLaunch(exec, s);
+        }
+        hipError_t e3 = hipStreamSynchronize(s);
+        if (e == hipSuccess) e = e3;
+        if (exec) (void)hipGraphExecDestroy(exec);
+        (void)hipStreamDestroy(cap);
+        if (e != hipSuccess) return fail(CT_ERR_HIP, std::string("batched graph: ") + hipGetErrorString(e));
+        // L is even: the parity of the images is unchanged by whole graphs
+    }
+    CT_HIP_CHECK(launch_set_counter(W0.tbase, 0, s));
+    for (; t < nsub; ++t) {
+        CT_HIP_CHECK(batch_subiter(dtab, n, nfp, nbp, sub[(size_t)(t % M)], par, batch_update(cs[0], t), dt,
+                                   cfg.fp_waves, s));
+        par ^= 1;
+    }
+    // x^(nsub) is the input of the last projection: buffer par ^ 1 (par itself when nothing ran)
+    const int fin = nsub > 0 ? (par ^ 1) : 0;
+    std::vector<double> host(3 * (size_t)n);
+    for (int i = 0; i < n; ++i) {
+        ct_geom *g = gs[i];
+        Workspace &W = g->ws;
+        CT_HIP_CHECK(hipMemcpyAsync(x[i], fin ? W.xb : W.xa, W.npix * sizeof(float), hipMemcpyDeviceToDevice, s));
+        CT_HIP_CHECK(launch_trace_reduce(x[i], nullptr, W.gv, W.h, g->desc.nx, g->desc.ny, (float)g->desc.dx,
+                                         (float)g->desc.dy, 0.f, W.red, s));
+        CT_HIP_CHECK(hipMemcpyAsync(&host[3 * (size_t)i], W.red, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    CT_HIP_CHECK(hipStreamSynchronize(s));
+    for (int i = 0; i < n; ++i)
+        if (host[3 * (size_t)i + 2] != 0.0)
+            return fail(CT_ERR_DIVERGED, "non-finite values in the final state of slice " + std::to_string(i));
     return CT_OK;
 }
 

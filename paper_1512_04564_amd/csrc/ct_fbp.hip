@@ -17,16 +17,17 @@ constexpr int FILT_THREADS = 256;
 // q[v][k] = d * sum_k2 h(k - k2) cw(k2) y[v][k2]; the weighted row is staged in LDS. The kernel's DC gain is a
 // near-exact cancellation of h(0) against the odd taps, so the coefficients and the sum are FP64: a one-ulp
 // FP32 mismatch between h(0) and the odd taps leaks a DC offset that the view sum amplifies.
-__global__ __launch_bounds__(FILT_THREADS) void k_fbp_filter(const float *__restrict__ y, float *__restrict__ q,
+template <typename TY>
+__global__ __launch_bounds__(FILT_THREADS) void k_fbp_filter(const TY *__restrict__ y, float *__restrict__ q,
                                                             int nb, double dui, float dso, float uoff_bins,
                                                             double h0, double hodd)
 {
     extern __shared__ float row[];
     const int v = blockIdx.y;
-    const float *yv = y + (size_t)v * nb;
+    const TY *yv = y + (size_t)v * nb;
     for (int k = threadIdx.x; k < nb; k += FILT_THREADS) {
         const float s = ((float)k + 0.5f - 0.5f * (float)nb + uoff_bins) * (float)dui;
-        row[k] = yv[k] * dso * rsqrtf(fmaf(s, s, dso * dso));
+        row[k] = (float)yv[k] * dso * rsqrtf(fmaf(s, s, dso * dso));
     }
     __syncthreads();
     const int k = blockIdx.x * FILT_THREADS + threadIdx.x;
@@ -75,14 +76,25 @@ __global__ __launch_bounds__(256) void k_fbp_back(const float *__restrict__ q, c
 
 }  // namespace
 
-hipError_t launch_fbp(const ct_geom *g, const float *y, float *q, const double2 *cs, float *x, hipStream_t s)
+hipError_t launch_fbp(const ct_geom *g, const void *y, int ytype, float *q, const double2 *cs, float *x, hipStream_t s)
 {
     const ct_geom_desc &d = g->desc;
     const double dui = d.du * d.dso / d.dsd;   // bin width at the isocentre
     const double pi = 3.14159265358979323846;
     dim3 gf((d.nb + FILT_THREADS - 1) / FILT_THREADS, d.nviews);
-    hipLaunchKernelGGL(k_fbp_filter, gf, dim3(FILT_THREADS), d.nb * sizeof(float), s, y, q, d.nb, dui, (float)d.dso,
-                       (float)d.u_offset, 1.0 / (4.0 * dui * dui), -1.0 / (pi * pi * dui * dui));
+    const size_t lds = d.nb * sizeof(float);
+    const double h0 = 1.0 / (4.0 * dui * dui), hodd = -1.0 / (pi * pi * dui * dui);
+    if (ytype == CT_F32)
+        hipLaunchKernelGGL(k_fbp_filter<float>, gf, dim3(FILT_THREADS), lds, s, static_cast<const float *>(y), q, d.nb,
+                           dui, (float)d.dso, (float)d.u_offset, h0, hodd);
+    else if (ytype == CT_F16)
+        hipLaunchKernelGGL(k_fbp_filter<_Float16>, gf, dim3(FILT_THREADS), lds, s, static_cast<const _Float16 *>(y), q,
+                           d.nb, dui, (float)d.dso, (float)d.u_offset, h0, hodd);
+    else if (ytype == CT_BF16)
+        hipLaunchKernelGGL(k_fbp_filter<__bf16>, gf, dim3(FILT_THREADS), lds, s, static_cast<const __bf16 *>(y), q, d.nb,
+                           dui, (float)d.dso, (float)d.u_offset, h0, hodd);
+    else
+        return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const double fac = 0.5 * d.span / d.nviews;

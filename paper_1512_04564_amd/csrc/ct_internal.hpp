@@ -57,8 +57,9 @@ struct GeomDev {
 struct Workspace {
     size_t npix = 0;
     float *xa = nullptr, *xb = nullptr;     // ping-pong images
-    float *xta = nullptr, *xtb = nullptr;   // their transposes [nx][ny]
-    float *r = nullptr;                     // residual block, [max views per launch][nb]
+    float *xta = nullptr, *xtb = nullptr;   // transposed projector copies [nx][ny] (storage type)
+    void *xca = nullptr, *xcb = nullptr;    // projector copies [ny][nx] of 16-bit storage (else unused)
+    float *r = nullptr;                     // residual block, [max views per launch][nb] (float32 capacity)
     size_t r_cap = 0;                       // floats
     float *rho = nullptr;                   // rho table
     size_t rho_cap = 0;
@@ -114,18 +115,29 @@ void free_workspace(ct_geom *g);
 std::vector<int> subset_order(int M, int kind);
 
 // ---- kernel launchers (ct_kernels.hip) ----
+// Storage types: sinogram inputs y, w, the residual block r and the forward projector's image copy are
+// stored as ct_dtype (float32, float16 or bfloat16); accumulation and the image state x, g, h are float32.
 enum FpEpilogue { FP_PLAIN = 0, FP_RESIDUAL = 1, FP_WEIGHTED = 2 };
-// Views v = vstart + vi * vstride for vi in [0, nv). img / imgT: image and its transpose (may be the same
-// pointer semantics as documented in ct_kernels.hip). ones != 0 projects the all-ones image.
-hipError_t launch_forward(const GeomDev &G, const float *img, const float *imgT, int ones, int vstart, int vstride,
-                          int nv, int epi, const float *y, const float *w, float mscale, float *out, hipStream_t s);
 
-enum BpMode { BP_BACK = 0, BP_INIT = 1, BP_FULL = 2, BP_DUAL = 3, BP_XSTEP = 4, BP_INIT_XSTEP = 5 };
+// One forward projection: views v = vstart + vi * vstride, vi in [0, nv), of the image img (row-sweep
+// views) / its transpose imgT (column-sweep views). Epilogues: PLAIN out = A x (float32); RESIDUAL
+// out = mscale * w (A x - y) (storage type); WEIGHTED out = w * A 1 (float32, ones image).
+struct FpLaunch {
+    GeomDev G;
+    const void *img = nullptr, *imgT = nullptr;
+    const void *y = nullptr, *w = nullptr;
+    void *out = nullptr;
+    int vstart = 0, vstride = 1, nv = 0;
+    float mscale = 1.f;
+};
+
+enum BpMode { BP_BACK = 0, BP_INIT = 1, BP_FULL = 2, BP_XSTEP = 3 };
 
 struct UpdateArgs {
-    const float *x = nullptr;      // current x^(t+1) (input of the projection just done)
-    float *x_next = nullptr;       // x-step output
-    float *xT_next = nullptr;      // its transpose
+    const float *x = nullptr;      // current x^(t+1) (input of the projection just done), float32
+    float *x_next = nullptr;       // x-step output, float32
+    void *xc_next = nullptr;       // its forward-projector copy (storage type; unused for float32)
+    void *xT_next = nullptr;       // its transposed copy (storage type)
     float *gv = nullptr;
     float *h = nullptr;
     const float *dl = nullptr;
@@ -141,16 +153,67 @@ struct UpdateArgs {
     int huber = 1;
 };
 
-hipError_t launch_back_update(const GeomDev &G, int mode, const float *r, int vstart, int vstride, int nv,
-                              float *out_back, const UpdateArgs &U, hipStream_t s);
+// One back-projection (BP_BACK: out_back = A' r, r float32 or storage type) or fused back-projection
+// and relaxed update (the other modes) over views vstart + vi * vstride, vi in [0, nv).
+struct BpLaunch {
+    GeomDev G;
+    const void *r = nullptr;
+    int vstart = 0, vstride = 1, nv = 0;
+    float *out_back = nullptr;
+    UpdateArgs U;
+};
+
+// One slice of a batched solve: everything a batched launch needs to address the slice. The images
+// ping-pong between index 0 and 1; the forward projector reads xc / xt (xc == x for float32 storage).
+struct SliceDev {
+    GeomDev G;
+    int M = 1, nvm = 0;
+    const void *y = nullptr, *w = nullptr;
+    void *r = nullptr;
+    float *x[2] = {nullptr, nullptr};
+    void *xc[2] = {nullptr, nullptr};
+    void *xt[2] = {nullptr, nullptr};
+    float *gv = nullptr, *h = nullptr;
+    const float *dl = nullptr, *kappa = nullptr;
+    int fp_begin = 0, fp_end = 0;   // workgroup range of the slice in a batched forward grid
+    int bp_begin = 0, bp_end = 0;   // ... and in a batched update grid
+};
+
+// Scalars shared by every slice of a batched update launch.
+struct BatchUpdate {
+    const float *rho = nullptr;
+    const int *tbase = nullptr;
+    long long tofs = 0;
+    float alpha = 1.999f;
+    int algorithm = 1, potential = 0, huber = 1;
+    float delta = 1e-4f, beta_ax = 1024.f, beta_dg = 1024.f / 1.41421356f;
+};
+
+// dtype: ct_dtype of the storage-typed operands (y, w, residual, image copies).
+hipError_t launch_forward(const FpLaunch &a, int ones, int epi, int dtype, hipStream_t s);
+hipError_t launch_back_update(const BpLaunch &a, int mode, int rtype, int ctype, hipStream_t s);
+// Batched subiteration kernels over slices [0, ns) of the device table tab: the forward projection of
+// subset m (views m + vi * M) from image buffer par with the residual epilogue, and the fused
+// back-projection / relaxed update reading buffer par and writing buffer par ^ 1. nwg_*: grid sizes
+// (tab[ns - 1].fp_end, bp_end). fp_waves selects the forward workgroup shape (8 or 16 waves).
+hipError_t launch_forward_batch(const SliceDev *tab, int ns, int nwg_fp, int m, int par, int dtype, int fp_waves,
+                                hipStream_t s);
+hipError_t launch_update_batch(const SliceDev *tab, int ns, int nwg_bp, int m, int par, const BatchUpdate &u,
+                               int dtype, hipStream_t s);
+int forward_workgroups(const GeomDev &G, int nv, int fp_waves);   // per-launch workgroup count
+int update_workgroups(const GeomDev &G);
 
 hipError_t launch_transpose(const float *x, float *xT, int nx, int ny, hipStream_t s);
 // FBP-like image of sinogram y into x (flat detector); q is an [nviews][nb] scratch sinogram.
-hipError_t launch_fbp(const ct_geom *g, const float *y, float *q, const double2 *cs, float *x, hipStream_t s);
-hipError_t launch_clip_copy(const float *in, float *out, float *outT, int nx, int ny, int zero, hipStream_t s);
+hipError_t launch_fbp(const ct_geom *g, const void *y, int ytype, float *q, const double2 *cs, float *x, hipStream_t s);
+// out = max(in, 0) (or 0), float32; outc (if non-NULL) and outT: its copy and transpose in ctype.
+hipError_t launch_clip_copy(const float *in, float *out, void *outc, void *outT, int nx, int ny, int zero, int ctype,
+                            hipStream_t s);
 hipError_t launch_scale(float *x, size_t n, float a, hipStream_t s);
 hipError_t launch_fill(float *x, size_t n, float a, hipStream_t s);
 hipError_t launch_kappa(const float *bw, const float *b1, float *kappa, size_t n, hipStream_t s);
+// dst = (float) src for n elements of ctype src
+hipError_t launch_to_float(const void *src, int ctype, float *dst, size_t n, hipStream_t s);
 hipError_t launch_add_counter(int *c, int add, hipStream_t s);
 hipError_t launch_set_counter(int *c, int value, hipStream_t s);
 // FP64 reduction: out[0] += sum over masked pixels of (x - ref)^2, out[1] += count, out[2] += nonfinite count

@@ -16,8 +16,18 @@
 // the g and h recursions with rho_t, then the regularizer gradient / Huber curvature stencil and the
 // clipped x-step of the next subiteration with rho_{t+1}, writing the new image and its transpose.
 //
+// Storage: the sinogram inputs, the residual block and the forward projector's image copies may be
+// float16 or bfloat16 (converted to float32 on load, rounded to nearest even on store); every sum and
+// the image state x, g, h stay float32.
+//
+// Both hot kernels exist twice: for one launch described by kernel arguments, and batched, where a
+// 1-D grid spans several independent slices (each with its own geometry and buffers) and every
+// workgroup looks its slice up in a device table of workgroup ranges.
+//
 // This file is compiled without NaN semantics (-fno-honor-nans): min/max need no canonicalising moves.
 // Finiteness checks live in ct_reduce.hip, which keeps them.
+#include <type_traits>
+
 #include "ct_internal.hpp"
 
 namespace ct {
@@ -25,13 +35,24 @@ namespace ct {
 namespace {
 
 constexpr int FP_BINS = 64;          // bins per forward workgroup (one per lane)
-constexpr int FP_WAVES = 16;         // waves per forward workgroup; each streams its own image lines
+constexpr int FP_WAVES = 16;         // waves per forward workgroup (single launches); each streams its own lines
 constexpr int FP_WIN = 128;          // LDS pixel window of one wave (floats)
 constexpr int FP_PF = FP_WIN / 64;   // prefetch registers per lane
 constexpr int BP_TX = kBpTile, BP_TY = kBpTile;
 constexpr int BP_WIN = 128;          // staged bins per view and tile in the back-projector
 
 __device__ __forceinline__ float rcp_approx(float v) { return __builtin_amdgcn_rcpf(v); }
+
+template <typename T>
+__device__ __forceinline__ float ld(const void *p, size_t i)
+{
+    return (float)static_cast<const T *>(p)[i];
+}
+template <typename T>
+__device__ __forceinline__ void st(void *p, size_t i, float v)
+{
+    static_cast<T *>(p)[i] = (T)v;
+}
 
 // Forward projection of the views vstart + vi * vstride (vi = blockIdx.y) for the 64 bins of block
 // blockIdx.x. Each wave streams a contiguous range of image lines: the pixels of line l+1 that the
@@ -40,20 +61,19 @@ __device__ __forceinline__ float rcp_approx(float v) { return __builtin_amdgcn_r
 // and read back with readlane. A bin's overlaps with its pixels are three branch-free taps from LDS (the
 // window is padded, so taps past its end read finite data with zero weight); wider footprints (oblique
 // lines) continue in a loop, and lines whose window exceeds the LDS slice read global memory.
-template <int EPI, bool ONES>
-__global__ __launch_bounds__(FP_BINS *FP_WAVES) void k_forward(GeomDev G, const float *__restrict__ img,
-                                                                const float *__restrict__ imgT, int vstart,
-                                                                int vstride, const float *__restrict__ y,
-                                                                const float *__restrict__ w, float mscale,
-                                                                float *__restrict__ out)
+template <int EPI, bool ONES, int WAVES, typename TI, typename TY, typename TO>
+__device__ __forceinline__ void fp_body(const FpLaunch &a, const int bx, const int vi, float *win)
 {
+    const GeomDev &G = a.G;
+    const int vstart = a.vstart, vstride = a.vstride;
+    const TI *__restrict__ img = static_cast<const TI *>(a.img);
+    const TI *__restrict__ imgT = static_cast<const TI *>(a.imgT);
     constexpr int PADW = FP_WIN + 4;
-    const int vi = blockIdx.y;
     const int v = vstart + vi * vstride;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nb = G.nb;
-    const int kblk = blockIdx.x * FP_BINS;
+    const int kblk = bx * FP_BINS;
     const int k = kblk + lane;
     const int kc = min(k, nb - 1);   // lanes past the last bin repeat it; their result is discarded
     const int klast = min(kblk + FP_BINS, nb);
@@ -62,16 +82,15 @@ __global__ __launch_bounds__(FP_BINS *FP_WAVES) void k_forward(GeomDev G, const 
     const int NQ = row ? G.nx : G.ny;
     const bool even = (NQ & 1) == 0;
     const int hq = NQ / 2;
-    const float *src = row ? img : imgT;
+    const TI *src = row ? img : imgT;
     const float half = 0.5f * (float)NQ;
     const float lc0 = -0.5f * (float)(NL - 1);
     const float2 *bv = G.bnd + (size_t)v * (nb + 1);
     const float2 b0 = bv[kc], b1 = bv[kc + 1];
     const float2 bF = bv[kblk], bL = bv[klast];
-    __shared__ float win[FP_WAVES * PADW];
     float *wl = win + wave * PADW;
     for (int t = lane; t < PADW; t += 64) wl[t] = ONES ? 1.f : 0.f;
-    const int l0 = (wave * NL) / FP_WAVES, l1 = ((wave + 1) * NL) / FP_WAVES;
+    const int l0 = (wave * NL) / WAVES, l1 = ((wave + 1) * NL) / WAVES;
 
     // pixels [ws, ws + wn) of line l that the block's bins can overlap (boundaries are monotone in k);
     // computed by lane (l - lb) for the 64 lines starting at lb
@@ -88,9 +107,9 @@ __global__ __launch_bounds__(FP_BINS *FP_WAVES) void k_forward(GeomDev G, const 
     auto prefetch = [&](int l, int ws) {
         if (!ONES) {
             // unconditional loads (clamped addresses): a fixed register set keeps the prefetch in flight
-            const float *line = src + (size_t)l * NQ;
+            const TI *line = src + (size_t)l * NQ;
 #pragma unroll
-            for (int j = 0; j < FP_PF; ++j) pf[j] = line[min(ws + lane + 64 * j, NQ - 1)];
+            for (int j = 0; j < FP_PF; ++j) pf[j] = (float)line[min(ws + lane + 64 * j, NQ - 1)];
         }
     };
 
@@ -148,10 +167,10 @@ __global__ __launch_bounds__(FP_BINS *FP_WAVES) void k_forward(GeomDev G, const 
                     for (int i = 3; (float)i < d; ++i)   // footprint wider than three pixels
                         s = fmaf(fminf(d - (float)i, 1.f), tp[i], s);
                 } else {
-                    const float *line = src + (size_t)l * NQ;
-                    s = (fminf(d, 1.f) - f) * (ONES ? 1.f : line[q0]);
+                    const TI *line = src + (size_t)l * NQ;
+                    s = (fminf(d, 1.f) - f) * (ONES ? 1.f : (float)line[q0]);
                     for (int i = 1; (float)i < d; ++i)
-                        s = fmaf(fminf(d - (float)i, 1.f), ONES ? 1.f : line[q0 + i], s);
+                        s = fmaf(fminf(d - (float)i, 1.f), ONES ? 1.f : (float)line[q0 + i], s);
                 }
                 acc = fmaf(s, rcp_approx(hi - lo), acc);
             }
@@ -159,20 +178,60 @@ __global__ __launch_bounds__(FP_BINS *FP_WAVES) void k_forward(GeomDev G, const 
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    float *red = win;   // reuse: [FP_WAVES][64]
+    float *red = win;   // reuse: [WAVES][64]
     red[wave * 64 + lane] = acc;
     __syncthreads();
     if (wave == 0 && k < nb) {
         float p = 0.f;
 #pragma unroll
-        for (int ww = 0; ww < FP_WAVES; ++ww) p += red[ww * 64 + lane];
+        for (int ww = 0; ww < WAVES; ++ww) p += red[ww * 64 + lane];
         p *= G.scale[(size_t)v * nb + k];
         const size_t o = (size_t)vi * nb + k;
         const size_t si = (size_t)v * nb + k;
-        if (EPI == FP_PLAIN) out[o] = p;
-        else if (EPI == FP_RESIDUAL) out[o] = mscale * w[si] * (p - y[si]);
-        else out[o] = w[si] * p;
+        if (EPI == FP_PLAIN) st<TO>(a.out, o, p);
+        else if (EPI == FP_RESIDUAL) st<TO>(a.out, o, a.mscale * ld<TY>(a.w, si) * (p - ld<TY>(a.y, si)));
+        else st<TO>(a.out, o, ld<TY>(a.w, si) * p);
     }
+}
+
+template <int EPI, bool ONES, int WAVES, typename TI, typename TY, typename TO>
+__global__ __launch_bounds__(FP_BINS *WAVES) void k_forward(FpLaunch a)
+{
+    __shared__ float win[WAVES * (FP_WIN + 4)];
+    fp_body<EPI, ONES, WAVES, TI, TY, TO>(a, blockIdx.x, blockIdx.y, win);
+}
+
+// Slice of workgroup b in a batched grid: the table holds ascending, contiguous workgroup ranges.
+template <bool FP>
+__device__ __forceinline__ int find_slice(const SliceDev *__restrict__ tab, int ns, int b)
+{
+    int s = 0;
+    while (s + 1 < ns && b >= (FP ? tab[s].fp_end : tab[s].bp_end)) ++s;
+    return s;
+}
+
+// Batched forward projection of subset m with the residual epilogue, every slice reading image buffer par.
+template <int WAVES, typename T>
+__global__ __launch_bounds__(FP_BINS *WAVES) void k_forward_batch(const SliceDev *__restrict__ tab, int ns, int m,
+                                                                   int par)
+{
+    __shared__ float win[WAVES * (FP_WIN + 4)];
+    const int s = find_slice<true>(tab, ns, blockIdx.x);
+    const SliceDev &S = tab[s];
+    FpLaunch a;
+    a.G = S.G;
+    a.img = S.xc[par];
+    a.imgT = S.xt[par];
+    a.y = S.y;
+    a.w = S.w;
+    a.out = S.r;
+    a.vstart = m;
+    a.vstride = S.M;
+    a.nv = S.nvm;
+    a.mscale = (float)S.M;
+    const int local = blockIdx.x - S.fp_begin;
+    const int nbx = (S.G.nb + FP_BINS - 1) / FP_BINS;
+    fp_body<FP_RESIDUAL, false, WAVES, T, T, T>(a, local % nbx, local / nbx, win);
 }
 
 // Back-projection of one pixel for one view: bins whose interval meets the pixel [e0, e0 + 1] on line
@@ -266,29 +325,43 @@ __device__ __forceinline__ int2 tile_window(const GeomDev &G, int v, int i0, int
 // (double-buffered: the next view's loads are in flight while the current one is evaluated). The
 // tile's bin windows of a chunk of views are computed up front, one view per thread. The two partial
 // sums are added in a fixed order, then half 0 carries out the update of its pixel.
-template <int MODE>
-__global__ __launch_bounds__(2 * BP_TX *BP_TY) void k_back_update(GeomDev G, const float *__restrict__ r,
-                                                                  int vstart, int vstride, int nv,
-                                                                  float *__restrict__ out_back, UpdateArgs U)
+constexpr int BP_NT = BP_TX * BP_TY;
+constexpr int BP_WCHUNK = 2 * BP_NT;   // views whose windows are computed per chunk (one per thread)
+
+struct BpShared {
+    float tile_t[BP_TX][BP_TY + 1];
+    float2 s_ab[2][2][BP_WIN + 1];
+    float s_rs[2][2][BP_WIN];
+    float s_part[BP_NT];
+    int4 s_desc[BP_WCHUNK];   // per view of the chunk: bin window k0, k1; view index; row-sweep flag
+    float4 s_im[BP_WCHUNK];   // per view of the chunk: inverse-map coefficients
+};
+
+template <int MODE, typename TR, typename TXC>
+__device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const int by, BpShared &sh)
 {
-    constexpr int NT = BP_TX * BP_TY;
-    constexpr int WCHUNK = 2 * NT;   // views whose windows are computed per chunk (one per thread)
+    constexpr int NT = BP_NT;
+    constexpr int WCHUNK = BP_WCHUNK;
+    const GeomDev &G = a.G;
+    const UpdateArgs &U = a.U;
+    const int vstart = a.vstart, vstride = a.vstride, nv = a.nv;
+    const TR *__restrict__ r = static_cast<const TR *>(a.r);
     const int hv = __builtin_amdgcn_readfirstlane(threadIdx.x / NT);   // view parity of this half (wave-uniform)
     const int tid = threadIdx.x % NT;
     const int tx = tid % BP_TX, ty = tid / BP_TX;
-    const int j = blockIdx.x * BP_TX + tx, i = blockIdx.y * BP_TY + ty;
+    const int j = bx * BP_TX + tx, i = by * BP_TY + ty;
     const int nx = G.nx, ny = G.ny, nb = G.nb;
-    __shared__ float tile_t[BP_TX][BP_TY + 1];
-    __shared__ float2 s_ab[2][2][BP_WIN + 1];
-    __shared__ float s_rs[2][2][BP_WIN];
-    __shared__ float s_part[NT];
-    __shared__ int4 s_desc[WCHUNK];   // per view of the chunk: bin window k0, k1; view index; row-sweep flag
-    __shared__ float4 s_im[WCHUNK];   // per view of the chunk: inverse-map coefficients
+    auto &tile_t = sh.tile_t;
+    auto &s_ab = sh.s_ab;
+    auto &s_rs = sh.s_rs;
+    auto &s_part = sh.s_part;
+    auto &s_desc = sh.s_desc;
+    auto &s_im = sh.s_im;
     const bool inside = i < ny && j < nx;
     float zeta = 0.f;
     if (MODE != BP_XSTEP) {
-        const int ti0 = blockIdx.y * BP_TY, ti1 = min(ti0 + BP_TY, ny);
-        const int tj0 = blockIdx.x * BP_TX, tj1 = min(tj0 + BP_TX, nx);
+        const int ti0 = by * BP_TY, ti1 = min(ti0 + BP_TY, ny);
+        const int tj0 = bx * BP_TX, tj1 = min(tj0 + BP_TX, nx);
         // pixel coordinates in both sweep orientations: row sweep lines are rows (l = i, q = j)
         const float lc_r = (float)i - 0.5f * (float)(ny - 1), e0_r = (float)j - 0.5f * (float)nx;
         const float lc_c = (float)j - 0.5f * (float)(nx - 1), e0_c = (float)i - 0.5f * (float)ny;
@@ -320,7 +393,7 @@ __global__ __launch_bounds__(2 * BP_TX *BP_TY) void k_back_update(GeomDev G, con
                     const unsigned t = (unsigned)tid;
                     if (tid <= n) ab = G.bnd[v * (unsigned)(nb + 1) + (unsigned)kw0 + t];
                     if (tid < n) {
-                        rv = r[(unsigned)(c0 + ci) * (unsigned)nb + (unsigned)kw0 + t];
+                        rv = (float)r[(unsigned)(c0 + ci) * (unsigned)nb + (unsigned)kw0 + t];
                         sv = G.scale[v * (unsigned)nb + (unsigned)kw0 + t];
                     }
                 }
@@ -362,9 +435,9 @@ __global__ __launch_bounds__(2 * BP_TX *BP_TY) void k_back_update(GeomDev G, con
                     } else {
                         const float2 *bv = G.bnd + (size_t)v * (nb + 1);
                         const float *sv = G.scale + (size_t)v * nb;
-                        const float *rv = r + (size_t)(c0 + ci) * nb;
+                        const TR *rv = r + (size_t)(c0 + ci) * nb;
                         zeta += bp_view(G, im, lc, e0, kw0, kw1, [&](int k) { return bv[k]; },
-                                        [&](int k) { return rv[k] * sv[k]; });
+                                        [&](int k) { return (float)rv[k] * sv[k]; });
                     }
                 }
                 if (it + 1 < niter) stage_store(buf ^ 1, kw0_n, kw1_n, ab_n, r_n, sc_n);
@@ -379,18 +452,18 @@ __global__ __launch_bounds__(2 * BP_TX *BP_TY) void k_back_update(GeomDev G, con
     if (hv == 0 && inside) {   // half 1 only takes part in the barriers from here on
         const size_t idx = (size_t)i * nx + j;
         if (MODE == BP_BACK) {
-            out_back[idx] = zeta;
+            a.out_back[idx] = zeta;
         } else {
             const float xc = U.x[idx];
             const float d = U.dl[idx];
             float g = U.gv[idx], hh = U.h[idx];
             const long long t = (U.tbase ? (long long)(*U.tbase) : 0ll) + U.tofs;
-            if (MODE == BP_INIT || MODE == BP_INIT_XSTEP) {
+            if (MODE == BP_INIT) {
                 g = zeta;
                 hh = U.algorithm == 1 ? fmaf(d, xc, -zeta) : zeta;
                 U.gv[idx] = g;
                 U.h[idx] = hh;
-            } else if (MODE == BP_FULL || MODE == BP_DUAL) {
+            } else if (MODE == BP_FULL) {
                 const float rho = U.rho[t];
                 const float a = U.alpha;
                 const float inv1 = 1.f / (rho + 1.f);
@@ -401,7 +474,7 @@ __global__ __launch_bounds__(2 * BP_TX *BP_TY) void k_back_update(GeomDev G, con
                 U.gv[idx] = g;
                 U.h[idx] = hh;
             }
-            if (MODE == BP_FULL || MODE == BP_XSTEP || MODE == BP_INIT_XSTEP) {
+            if (MODE == BP_FULL || MODE == BP_XSTEP) {
                 const long long tx1 = MODE == BP_FULL ? t + 1 : t;
                 const float rho1 = U.rho[tx1];
                 const float s = U.algorithm == 1 ? rho1 * fmaf(d, xc, -hh) + (1.f - rho1) * g
@@ -425,17 +498,64 @@ __global__ __launch_bounds__(2 * BP_TX *BP_TY) void k_back_update(GeomDev G, con
                 const float den = fmaf(rho1, d, dr);
                 xn = den > 0.f ? fmaxf(xc - (s + gr) / den, 0.f) : xc;
                 U.x_next[idx] = xn;
+                if (!std::is_same<TXC, float>::value) st<TXC>(U.xc_next, idx, xn);
             }
         }
     }
-    if (MODE == BP_FULL || MODE == BP_XSTEP || MODE == BP_INIT_XSTEP) {
+    if (MODE == BP_FULL || MODE == BP_XSTEP) {
         // transpose through LDS: write xT_next[j][i] in runs of BP_TY along i
         if (hv == 0) tile_t[tx][ty] = xn;
         __syncthreads();
-        const int jj = blockIdx.x * BP_TX + ty;   // swapped roles
-        const int ii = blockIdx.y * BP_TY + tx;
-        if (hv == 0 && jj < nx && ii < ny) U.xT_next[(size_t)jj * ny + ii] = tile_t[ty][tx];
+        const int jj = bx * BP_TX + ty;   // swapped roles
+        const int ii = by * BP_TY + tx;
+        if (hv == 0 && jj < nx && ii < ny) st<TXC>(U.xT_next, (size_t)jj * ny + ii, tile_t[ty][tx]);
     }
+}
+
+// Eight waves per SIMD (four workgroups per CU): the register budget is held to that occupancy.
+template <int MODE, typename TR, typename TXC>
+__global__ __launch_bounds__(2 * BP_TX *BP_TY) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_back_update(BpLaunch a)
+{
+    __shared__ BpShared sh;
+    bp_body<MODE, TR, TXC>(a, blockIdx.x, blockIdx.y, sh);
+}
+
+// Batched fused back-projection / relaxed update of subset m: every slice reads image buffer par and
+// its residual block, and writes image buffer par ^ 1 (and its copies).
+template <typename T>
+__global__ __launch_bounds__(2 * BP_TX *BP_TY) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_update_batch(const SliceDev *__restrict__ tab, int ns, int m,
+                                                                    int par, BatchUpdate u)
+{
+    __shared__ BpShared sh;
+    const int s = find_slice<false>(tab, ns, blockIdx.x);
+    const SliceDev &S = tab[s];
+    BpLaunch a;
+    a.G = S.G;
+    a.r = S.r;
+    a.vstart = m;
+    a.vstride = S.M;
+    a.nv = S.nvm;
+    a.U.x = S.x[par];
+    a.U.x_next = S.x[par ^ 1];
+    a.U.xc_next = S.xc[par ^ 1];
+    a.U.xT_next = S.xt[par ^ 1];
+    a.U.gv = S.gv;
+    a.U.h = S.h;
+    a.U.dl = S.dl;
+    a.U.kappa = S.kappa;
+    a.U.rho = u.rho;
+    a.U.tbase = u.tbase;
+    a.U.tofs = u.tofs;
+    a.U.alpha = u.alpha;
+    a.U.algorithm = u.algorithm;
+    a.U.potential = u.potential;
+    a.U.delta = u.delta;
+    a.U.beta_ax = u.beta_ax;
+    a.U.beta_dg = u.beta_dg;
+    a.U.huber = u.huber;
+    const int local = blockIdx.x - S.bp_begin;
+    const int tilesx = (S.G.nx + BP_TX - 1) / BP_TX;
+    bp_body<BP_FULL, T, T>(a, local % tilesx, local / tilesx, sh);
 }
 
 __global__ void k_transpose(const float *__restrict__ x, float *__restrict__ xT, int nx, int ny)
@@ -449,8 +569,9 @@ __global__ void k_transpose(const float *__restrict__ x, float *__restrict__ xT,
     if (ii < ny && jj < nx) xT[(size_t)jj * ny + ii] = tile[tx][ty];
 }
 
-__global__ void k_clip_copy(const float *__restrict__ in, float *__restrict__ out, float *__restrict__ outT, int nx,
-                            int ny, int zero)
+template <typename TXC>
+__global__ void k_clip_copy(const float *__restrict__ in, float *__restrict__ out, void *__restrict__ outc,
+                            void *__restrict__ outT, int nx, int ny, int zero)
 {
     __shared__ float tile[16][17];
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
@@ -459,11 +580,19 @@ __global__ void k_clip_copy(const float *__restrict__ in, float *__restrict__ ou
     if (i < ny && j < nx) {
         v = zero ? 0.f : fmaxf(in[(size_t)i * nx + j], 0.f);
         out[(size_t)i * nx + j] = v;
+        if (outc) st<TXC>(outc, (size_t)i * nx + j, v);
     }
     tile[ty][tx] = v;
     __syncthreads();
     int ii = blockIdx.y * 16 + tx, jj = blockIdx.x * 16 + ty;
-    if (ii < ny && jj < nx) outT[(size_t)jj * ny + ii] = tile[tx][ty];
+    if (ii < ny && jj < nx) st<TXC>(outT, (size_t)jj * ny + ii, tile[tx][ty]);
+}
+
+template <typename T>
+__global__ void k_to_float(const void *__restrict__ src, float *__restrict__ dst, size_t n)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = ld<T>(src, i);
 }
 
 __global__ void k_scale(float *x, size_t n, float a)
@@ -489,42 +618,108 @@ __global__ void k_set_counter(int *c, int value) { c[0] = value; }
 
 }  // namespace
 
-hipError_t launch_forward(const GeomDev &G, const float *img, const float *imgT, int ones, int vstart, int vstride,
-                          int nv, int epi, const float *y, const float *w, float mscale, float *out, hipStream_t s)
+int forward_workgroups(const GeomDev &G, int nv, int) { return ((G.nb + FP_BINS - 1) / FP_BINS) * nv; }
+
+int update_workgroups(const GeomDev &G) { return ((G.nx + BP_TX - 1) / BP_TX) * ((G.ny + BP_TY - 1) / BP_TY); }
+
+// Storage-typed instantiations: float32 keeps every epilogue; 16-bit storage needs the subset residual
+// (image copy, y, w and r in 16 bits) and the weighted ones projection for D_L (w in 16 bits, output
+// float32, so that the majorizer is computed from float32 sums).
+hipError_t launch_forward(const FpLaunch &a, int ones, int epi, int dtype, hipStream_t s)
 {
-    if (nv <= 0) return hipSuccess;
-    dim3 grid((G.nb + FP_BINS - 1) / FP_BINS, nv), block(FP_BINS * FP_WAVES);
-#define CT_FP_LAUNCH(E, O)                                                                                     \
-    hipLaunchKernelGGL((k_forward<E, O>), grid, block, 0, s, G, img, imgT, vstart, vstride, y, w, mscale, out)
-    if (ones) {
-        if (epi == FP_PLAIN) CT_FP_LAUNCH(FP_PLAIN, true);
-        else if (epi == FP_RESIDUAL) CT_FP_LAUNCH(FP_RESIDUAL, true);
-        else CT_FP_LAUNCH(FP_WEIGHTED, true);
+    if (a.nv <= 0) return hipSuccess;
+    dim3 grid((a.G.nb + FP_BINS - 1) / FP_BINS, a.nv), block(FP_BINS * FP_WAVES);
+#define CT_FP(E, O, TI, TY, TO) hipLaunchKernelGGL((k_forward<E, O, FP_WAVES, TI, TY, TO>), grid, block, 0, s, a)
+    if (dtype == CT_F32) {
+        if (ones) {
+            if (epi == FP_PLAIN) CT_FP(FP_PLAIN, true, float, float, float);
+            else if (epi == FP_RESIDUAL) CT_FP(FP_RESIDUAL, true, float, float, float);
+            else CT_FP(FP_WEIGHTED, true, float, float, float);
+        } else {
+            if (epi == FP_PLAIN) CT_FP(FP_PLAIN, false, float, float, float);
+            else if (epi == FP_RESIDUAL) CT_FP(FP_RESIDUAL, false, float, float, float);
+            else CT_FP(FP_WEIGHTED, false, float, float, float);
+        }
+    } else if (dtype == CT_F16) {
+        if (!ones && epi == FP_RESIDUAL) CT_FP(FP_RESIDUAL, false, _Float16, _Float16, _Float16);
+        else if (ones && epi == FP_WEIGHTED) CT_FP(FP_WEIGHTED, true, float, _Float16, float);
+        else return hipErrorInvalidValue;
+    } else if (dtype == CT_BF16) {
+        if (!ones && epi == FP_RESIDUAL) CT_FP(FP_RESIDUAL, false, __bf16, __bf16, __bf16);
+        else if (ones && epi == FP_WEIGHTED) CT_FP(FP_WEIGHTED, true, float, __bf16, float);
+        else return hipErrorInvalidValue;
     } else {
-        if (epi == FP_PLAIN) CT_FP_LAUNCH(FP_PLAIN, false);
-        else if (epi == FP_RESIDUAL) CT_FP_LAUNCH(FP_RESIDUAL, false);
-        else CT_FP_LAUNCH(FP_WEIGHTED, false);
+        return hipErrorInvalidValue;
     }
-#undef CT_FP_LAUNCH
+#undef CT_FP
     return hipGetLastError();
 }
 
-hipError_t launch_back_update(const GeomDev &G, int mode, const float *r, int vstart, int vstride, int nv,
-                              float *out_back, const UpdateArgs &U, hipStream_t s)
+// rtype: type of r (BP_BACK: float32 or storage type; update modes: storage type). ctype: type of the
+// image copies written by the x-step.
+hipError_t launch_back_update(const BpLaunch &a, int mode, int rtype, int ctype, hipStream_t s)
 {
-    dim3 grid((G.nx + BP_TX - 1) / BP_TX, (G.ny + BP_TY - 1) / BP_TY), block(2 * BP_TX * BP_TY);
-#define CT_BP_CASE(M)                                                                                          \
-    case M: hipLaunchKernelGGL(k_back_update<M>, grid, block, 0, s, G, r, vstart, vstride, nv, out_back, U); break;
-    switch (mode) {
-        CT_BP_CASE(BP_BACK)
-        CT_BP_CASE(BP_INIT)
-        CT_BP_CASE(BP_FULL)
-        CT_BP_CASE(BP_DUAL)
-        CT_BP_CASE(BP_XSTEP)
-        CT_BP_CASE(BP_INIT_XSTEP)
-    default: return hipErrorInvalidValue;
+    dim3 grid((a.G.nx + BP_TX - 1) / BP_TX, (a.G.ny + BP_TY - 1) / BP_TY), block(2 * BP_TX * BP_TY);
+#define CT_BP(M, TR, TC) hipLaunchKernelGGL((k_back_update<M, TR, TC>), grid, block, 0, s, a)
+#define CT_BP_ALL(T)                                                                                           \
+    if (mode == BP_INIT) CT_BP(BP_INIT, T, T);                                                                 \
+    else if (mode == BP_FULL) CT_BP(BP_FULL, T, T);                                                            \
+    else if (mode == BP_XSTEP) CT_BP(BP_XSTEP, T, T);                                                          \
+    else return hipErrorInvalidValue;
+    if (mode == BP_BACK) {
+        if (rtype == CT_F32) CT_BP(BP_BACK, float, float);
+        else if (rtype == CT_F16) CT_BP(BP_BACK, _Float16, float);
+        else if (rtype == CT_BF16) CT_BP(BP_BACK, __bf16, float);
+        else return hipErrorInvalidValue;
+    } else {
+        if (rtype != ctype) return hipErrorInvalidValue;
+        if (ctype == CT_F32) {
+            CT_BP_ALL(float)
+        } else if (ctype == CT_F16) {
+            CT_BP_ALL(_Float16)
+        } else if (ctype == CT_BF16) {
+            CT_BP_ALL(__bf16)
+        } else {
+            return hipErrorInvalidValue;
+        }
     }
-#undef CT_BP_CASE
+#undef CT_BP_ALL
+#undef CT_BP
+    return hipGetLastError();
+}
+
+hipError_t launch_forward_batch(const SliceDev *tab, int ns, int nwg_fp, int m, int par, int dtype, int fp_waves,
+                                hipStream_t s)
+{
+    if (ns <= 0 || nwg_fp <= 0) return hipSuccess;
+#define CT_FPB(W, T) hipLaunchKernelGGL((k_forward_batch<W, T>), dim3(nwg_fp), dim3(FP_BINS * W), 0, s, tab, ns, m, par)
+#define CT_FPB_W(T)                                                                                            \
+    if (fp_waves == 8) CT_FPB(8, T);                                                                           \
+    else if (fp_waves == 16) CT_FPB(16, T);                                                                    \
+    else return hipErrorInvalidValue;
+    if (dtype == CT_F32) {
+        CT_FPB_W(float)
+    } else if (dtype == CT_F16) {
+        CT_FPB_W(_Float16)
+    } else if (dtype == CT_BF16) {
+        CT_FPB_W(__bf16)
+    } else {
+        return hipErrorInvalidValue;
+    }
+#undef CT_FPB_W
+#undef CT_FPB
+    return hipGetLastError();
+}
+
+hipError_t launch_update_batch(const SliceDev *tab, int ns, int nwg_bp, int m, int par, const BatchUpdate &u,
+                               int dtype, hipStream_t s)
+{
+    if (ns <= 0 || nwg_bp <= 0) return hipSuccess;
+    dim3 grid(nwg_bp), block(2 * BP_TX * BP_TY);
+    if (dtype == CT_F32) hipLaunchKernelGGL(k_update_batch<float>, grid, block, 0, s, tab, ns, m, par, u);
+    else if (dtype == CT_F16) hipLaunchKernelGGL(k_update_batch<_Float16>, grid, block, 0, s, tab, ns, m, par, u);
+    else if (dtype == CT_BF16) hipLaunchKernelGGL(k_update_batch<__bf16>, grid, block, 0, s, tab, ns, m, par, u);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -535,10 +730,26 @@ hipError_t launch_transpose(const float *x, float *xT, int nx, int ny, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_clip_copy(const float *in, float *out, float *outT, int nx, int ny, int zero, hipStream_t s)
+hipError_t launch_clip_copy(const float *in, float *out, void *outc, void *outT, int nx, int ny, int zero, int ctype,
+                            hipStream_t s)
 {
     dim3 grid((nx + 15) / 16, (ny + 15) / 16);
-    hipLaunchKernelGGL(k_clip_copy, grid, dim3(256), 0, s, in, out, outT, nx, ny, zero);
+    if (ctype == CT_F32) hipLaunchKernelGGL(k_clip_copy<float>, grid, dim3(256), 0, s, in, out, outc, outT, nx, ny, zero);
+    else if (ctype == CT_F16)
+        hipLaunchKernelGGL(k_clip_copy<_Float16>, grid, dim3(256), 0, s, in, out, outc, outT, nx, ny, zero);
+    else if (ctype == CT_BF16)
+        hipLaunchKernelGGL(k_clip_copy<__bf16>, grid, dim3(256), 0, s, in, out, outc, outT, nx, ny, zero);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_to_float(const void *src, int ctype, float *dst, size_t n, hipStream_t s)
+{
+    dim3 grid((unsigned)((n + 255) / 256));
+    if (ctype == CT_F32) hipLaunchKernelGGL(k_to_float<float>, grid, dim3(256), 0, s, src, dst, n);
+    else if (ctype == CT_F16) hipLaunchKernelGGL(k_to_float<_Float16>, grid, dim3(256), 0, s, src, dst, n);
+    else if (ctype == CT_BF16) hipLaunchKernelGGL(k_to_float<__bf16>, grid, dim3(256), 0, s, src, dst, n);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -230,3 +230,31 @@ def test_relaxation_speeds_up_early_iterations():
         assert all(f <= 60 and tr[f - 1] < th for f, th in zip(first[alpha], (100.0, 30.0, 10.0)))
     for f_relaxed, f_plain in zip(first[1.999], first[1.0]):
         assert f_relaxed <= 0.7 * f_plain
+
+
+# ---------------------------------------------------------------- weight scaling -------------------
+
+@pytest.mark.parametrize("kappa", [False, True])
+def test_iterates_invariant_under_joint_scaling_of_weights_and_beta(kappa):
+    """Scaling W and beta by one constant c scales the cost by c; in Algorithm 1 it scales D_L, zeta, g, h,
+    grad R and D_R alike, so the x-step (numerator over denominator) and every x iterate are unchanged.
+    With c a power of two the FP64 arithmetic is scaled exactly, so the iterates agree to rounding-free
+    precision. With certainty weights kappa = sqrt(A'w / A'1) the regularizer already scales with W
+    (kappa_j kappa_k scales by c), so beta stays. (Half-precision storage relies on this to bring
+    count-sized weights into range.)"""
+    g, _, y, w = small_problem(M=4, seed=3)
+    w = w * 4000.0
+    c = 2.0 ** -6
+    x0 = np.zeros((g.ny, g.nx))
+    p1 = oracle.params(alpha=1.999, niters=6, nsubsets=g.nsubsets, beta=2.0, delta=0.05, kappa=kappa)
+    p2 = oracle.params(alpha=1.999, niters=6, nsubsets=g.nsubsets, beta=2.0 if kappa else 2.0 * c, delta=0.05,
+                       kappa=kappa)
+    x1, _, _ = oracle.rlalm_solve(g, p1, y, w, x0)
+    x2, _, _ = oracle.rlalm_solve(g, p2, y, w * c, x0)
+    assert np.abs(x1).max() > 0.1
+    np.testing.assert_allclose(x2, x1, rtol=0, atol=1e-13 * np.abs(x1).max())
+    # the other choice of beta changes the iterates (the test is not vacuous)
+    p3 = oracle.params(alpha=1.999, niters=6, nsubsets=g.nsubsets, beta=2.0 * c if kappa else 2.0, delta=0.05,
+                       kappa=kappa)
+    x3, _, _ = oracle.rlalm_solve(g, p3, y, w * c, x0)
+    assert np.abs(x3 - x1).max() > 1e-3 * np.abs(x1).max()
