@@ -28,7 +28,7 @@ import numpy as np
 
 __all__ = [
     "ScanGeometry", "CFG1", "CFG2", "BATCH_CLASSES", "fov_radius", "random_ellipses", "phantom_image",
-    "ray_points", "analytic_sinogram", "noisy_scan", "Scan", "MU_WATER",
+    "ray_points", "analytic_sinogram", "noisy_scan", "Scan", "MU_WATER", "UNET_SHAPES", "unet_params",
 ]
 
 MU_WATER = 0.02  # mm^-1; 1000 HU.  The HU scale puts air at 0.
@@ -240,3 +240,27 @@ def noisy_scan(g: ScanGeometry, seed: int, *, i0: float = 1e5, sigma: float = 5.
     w = (counts * counts / (counts + sigma * sigma)).astype(np.float32)
     img = phantom_image(g, ell) if truth else None
     return Scan(g, seed, y, w, img, li, ell)
+
+
+# ---- warm-start network: seeded initial weights (shapes only; the network itself lives elsewhere) -----
+
+#: Convolution shapes (c_in, c_out, kernel) of the warm-start U-Net in its canonical parameter order:
+#: encoder levels 1-3 (two 3x3 convolutions each), the 256-channel bottleneck, decoder levels 3-1 (their
+#: first convolution reads the upsampled lower level concatenated with the skip), and the 1x1 output.
+UNET_SHAPES = (
+    (1, 32, 3), (32, 32, 3), (32, 64, 3), (64, 64, 3), (64, 128, 3), (128, 128, 3), (128, 256, 3), (256, 256, 3),
+    (384, 128, 3), (128, 128, 3), (192, 64, 3), (64, 64, 3), (96, 32, 3), (32, 32, 3), (32, 1, 1),
+)
+
+
+def unet_params(seed: int, out_std: float = 1e-3) -> np.ndarray:
+    """Seeded initial weights, float32, flat in canonical order: per layer the weight [c_out][c_in][k][k]
+    (He-normal, std sqrt(2 / (c_in k^2))) then the bias [c_out] (zero). The 1x1 output layer is drawn with
+    std ``out_std`` so that the untrained network starts close to its residual identity."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for i, (ci, co, k) in enumerate(UNET_SHAPES):
+        std = out_std if i == len(UNET_SHAPES) - 1 else math.sqrt(2.0 / (ci * k * k))
+        parts.append(rng.normal(0.0, std, co * ci * k * k))
+        parts.append(np.zeros(co))
+    return np.concatenate(parts).astype(np.float32)
