@@ -103,6 +103,9 @@ ct_status ct_back(const ct_geom *g, int subset, const float *r, float *x, void *
  */
 ct_status ct_fbp(const ct_geom *g, const void *y, float *x, void *stream);
 
+/* Warm-start network (ct_unet.h). */
+typedef struct ct_unet ct_unet;
+
 /* Subset processing order (the paper leaves it open). */
 typedef enum { CT_ORDER_SEQUENTIAL = 0, CT_ORDER_BITREV = 1 } ct_subset_order;
 
@@ -117,7 +120,8 @@ typedef struct {
     int algorithm;       /* 1: Algorithm 1 (proposed relaxation), 2: Algorithm 2 (simple relaxation) */
     int subset_order;    /* ct_subset_order                                                          */
     int kappa;           /* 0: kappa = 1; 1: certainty weights kappa_j = sqrt(A'w / A'1)             */
-    int start;           /* 0: x holds x0 on entry; 1: zero image; 2: FBP-like image (ct_fbp)       */
+    int start;           /* 0: x holds x0 on entry; 1: zero image; 2: FBP-like image (ct_fbp);
+                            3: learned start mu_water * max(unet(A'(w y) / D_L / mu_water), 0)       */
     int init_full;       /* 0: initial gradient from the last subset (Algorithm 1 as written);
                             1: full gradient                                                         */
     double dl_scale;     /* multiplies D_L (1 = the majorizer diag{A'WA1})                            */
@@ -129,6 +133,8 @@ typedef struct {
                             projection kernel and update kernel 50 times each, back to back between
                             one hipEvent pair per kernel (the result is already in x; only solve-owned
                             workspace is rewritten); read with ct_rlalm_kernel_times                  */
+    const ct_unet *unet; /* network of start == 3 (its max sizes must cover the image; ny, nx
+                            multiples of 8); NULL otherwise                                           */
 } ct_rlalm_params;
 
 /* Fill p with the defaults: alpha 1.999, 20 iterations, continuation, hyperbola delta 1e-4 beta 1024,

@@ -62,7 +62,7 @@ def conv3x3(x, W, b):
     z = np.broadcast_to(b[None, :, None, None], (n, W.shape[0], h, w)).copy()
     for dy in range(3):
         for dx in range(3):
-            z += np.einsum("oi,nihw->nohw", W[:, :, dy, dx], xp[:, :, dy:dy + h, dx:dx + w])
+            z += np.einsum("oi,nihw->nohw", W[:, :, dy, dx], xp[:, :, dy:dy + h, dx:dx + w], optimize=True)
     return z
 
 
@@ -75,8 +75,8 @@ def conv3x3_backward(x, W, dz):
     dW = np.zeros_like(W)
     for dy in range(3):
         for dx in range(3):
-            dW[:, :, dy, dx] = np.einsum("nohw,nihw->oi", dz, xp[:, :, dy:dy + h, dx:dx + w])
-            dxp[:, :, dy:dy + h, dx:dx + w] += np.einsum("oi,nohw->nihw", W[:, :, dy, dx], dz)
+            dW[:, :, dy, dx] = np.einsum("nohw,nihw->oi", dz, xp[:, :, dy:dy + h, dx:dx + w], optimize=True)
+            dxp[:, :, dy:dy + h, dx:dx + w] += np.einsum("oi,nohw->nihw", W[:, :, dy, dx], dz, optimize=True)
     return dxp[:, :, 1:-1, 1:-1], dW, dz.sum(axis=(0, 2, 3))
 
 

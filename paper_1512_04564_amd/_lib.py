@@ -19,7 +19,9 @@ STATUS_NAMES = {0: "CT_OK", 1: "CT_ERR_INVALID_ARG", 2: "CT_ERR_OOM", 3: "CT_ERR
 #: Every entry point declared in include/ct.h.
 EXPORTS = ("ct_geom_create", "ct_geom_destroy", "ct_forward", "ct_back", "ct_fbp", "ct_rlalm_params_default",
            "ct_rlalm_solve", "ct_rlalm_solve_batched", "ct_rlalm_prepare", "ct_rlalm_init", "ct_rlalm_iterate",
-           "ct_rlalm_kernel_times", "ct_last_error")
+           "ct_rlalm_kernel_times", "ct_last_error", "ct_unet_num_params", "ct_unet_create", "ct_unet_destroy",
+           "ct_unet_set_params", "ct_unet_get_params", "ct_unet_forward", "ct_unet_gradient", "ct_unet_train_step",
+           "ct_unet_input")
 
 
 class GeomDesc(ctypes.Structure):
@@ -37,7 +39,7 @@ class RlalmParams(ctypes.Structure):
                 ("subset_order", ctypes.c_int), ("kappa", ctypes.c_int), ("start", ctypes.c_int),
                 ("init_full", ctypes.c_int), ("dl_scale", ctypes.c_double), ("x_ref", ctypes.c_void_p),
                 ("mu_water", ctypes.c_double), ("fov_radius", ctypes.c_double), ("use_graph", ctypes.c_int),
-                ("time_kernels", ctypes.c_int)]
+                ("time_kernels", ctypes.c_int), ("unet", ctypes.c_void_p)]
 
 
 class KernelTimes(ctypes.Structure):
@@ -88,9 +90,22 @@ def load() -> ctypes.CDLL:
     L.ct_rlalm_iterate.argtypes = [vp, ctypes.POINTER(RlalmParams), vp, vp, vp, vp, vp, vp, vp, ll, ll, vp]
     L.ct_rlalm_kernel_times.argtypes = [vp, ctypes.POINTER(KernelTimes)]
     L.ct_last_error.restype = ctypes.c_char_p
+    fp, u8p, dp = ctypes.POINTER(ctypes.c_float), vp, ctypes.POINTER(ctypes.c_double)
+    L.ct_unet_num_params.argtypes = []
+    L.ct_unet_create.argtypes = [vp, i, i, i, ctypes.POINTER(vp)]
+    L.ct_unet_destroy.argtypes = [vp]
+    L.ct_unet_destroy.restype = None
+    L.ct_unet_set_params.argtypes = [vp, vp]
+    L.ct_unet_get_params.argtypes = [vp, vp]
+    L.ct_unet_forward.argtypes = [vp, vp, vp, i, i, i, vp]
+    L.ct_unet_gradient.argtypes = [vp, vp, vp, u8p, i, i, i, dp, vp, vp]
+    L.ct_unet_train_step.argtypes = [vp, vp, vp, u8p, i, i, i, ctypes.c_float, dp, vp]
+    L.ct_unet_input.argtypes = [vp, vp, vp, vp, ctypes.c_double, vp, vp]
     for name in EXPORTS:
-        if name not in ("ct_geom_destroy", "ct_rlalm_params_default", "ct_last_error"):
+        if name not in ("ct_geom_destroy", "ct_rlalm_params_default", "ct_last_error", "ct_unet_destroy",
+                        "ct_unet_num_params"):
             getattr(L, name).restype = ctypes.c_int
+    L.ct_unet_num_params.restype = ctypes.c_size_t
     _lib = L
     return L
 

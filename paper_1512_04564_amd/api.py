@@ -95,13 +95,14 @@ class Params:
     algorithm: int = 1
     subset_order: str = "sequential"  # or "bitrev"
     kappa: bool = False
-    start: str = "given"             # or "zero", "fbp"
+    start: str = "given"             # or "zero", "fbp", "learned" (needs unet)
     init_full: bool = False
     dl_scale: float = 1.0
     mu_water: float = 0.02
     fov_radius: float = 0.0
     use_graph: bool = True
     time_kernels: bool = False
+    unet: object = None              # unet.UNet for start="learned"
 
     def to_c(self, x_ref: torch.Tensor | None = None) -> RlalmParams:
         p = RlalmParams()
@@ -117,7 +118,8 @@ class Params:
         p.algorithm = self.algorithm
         p.subset_order = {"sequential": 0, "bitrev": 1}[self.subset_order]
         p.kappa = int(self.kappa)
-        p.start = {"given": 0, "zero": 1, "fbp": 2}[self.start]
+        p.start = {"given": 0, "zero": 1, "fbp": 2, "learned": 3}[self.start]
+        p.unet = self.unet.handle.value if self.unet is not None else None
         p.init_full = int(self.init_full)
         p.dl_scale = self.dl_scale
         p.x_ref = x_ref.data_ptr() if x_ref is not None else None

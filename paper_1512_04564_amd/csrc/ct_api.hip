@@ -91,7 +91,8 @@ ct_status check_params(const ct_rlalm_params *p)
     if (p->subset_order != CT_ORDER_SEQUENTIAL && p->subset_order != CT_ORDER_BITREV)
         return fail(CT_ERR_INVALID_ARG, "unknown subset order");
     if (!(p->dl_scale > 0)) return fail(CT_ERR_INVALID_ARG, "dl_scale must be > 0");
-    if (p->start < 0 || p->start > 2) return fail(CT_ERR_INVALID_ARG, "start must be 0, 1 or 2");
+    if (p->start < 0 || p->start > 3) return fail(CT_ERR_INVALID_ARG, "start must be 0, 1, 2 or 3");
+    if (p->start == 3 && !p->unet) return fail(CT_ERR_INVALID_ARG, "start == 3 needs a network (unet)");
     return CT_OK;
 }
 
@@ -837,6 +838,7 @@ ct_status ct_rlalm_solve(ct_geom *g, const ct_rlalm_params *p, const void *y, co
         CT_HIP_CHECK(launch_fbp(g, y, g->desc.storage, W.r, g->cs, x, s));
     }
     CT_TRY(do_prepare(g, p, w, W.dl, p->kappa ? W.kappa : nullptr, s));
+    if (p->start == 3) CT_TRY(learned_start(g, p->unet, y, w, W.dl, p->dl_scale, p->mu_water, x, W.xa, W.xb, s));
     Ctx c = make_ctx(g, p, y, w, W.dl, W.kappa, W.gv, W.h);
     CT_TRY(do_init(c, x, p->start == 1, s));
     int fin = -1;
@@ -886,6 +888,8 @@ ct_status ct_rlalm_solve_batched(ct_geom *const *gs, int n, const ct_rlalm_param
         if (i == 0) CT_TRY(upload_rho(g, p, nsub + 2, s));
         if (p->start == 2) CT_HIP_CHECK(launch_fbp(g, y[i], g->desc.storage, W.r, g->cs, x[i], s));
         CT_TRY(do_prepare(g, p, w[i], W.dl, p->kappa ? W.kappa : nullptr, s));
+        if (p->start == 3)
+            CT_TRY(learned_start(g, p->unet, y[i], w[i], W.dl, p->dl_scale, p->mu_water, x[i], W.xa, W.xb, s));
         cs.push_back(make_ctx(g, p, y[i], w[i], W.dl, W.kappa, W.gv, W.h));
     }
     // every slice reads the rho table and subiteration counter of slice 0

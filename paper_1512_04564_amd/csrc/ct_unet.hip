@@ -1,0 +1,1064 @@
+// Learned warm start: a BF16 U-Net on the gfx950 matrix cores (include/ct_unet.h).
+//
+// Layout. Activations and their gradients are bfloat16 NHWC ([n][h][w][c], channels fastest); sums are
+// float32. 3x3 convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16 (D[16 x 16] += A[16 x 32] *
+// B[32 x 16]; lane l holds A[l%16][8(l/16) .. +7], B[8(l/16) .. +7][l%16] and D[4(l/16) + j][l%16]):
+//   forward        D[c_out][pixel] = sum over (tap, c_in) of W[c_out][tap][c_in] * in[pixel + tap][c_in]
+//   input gradient the same kernel on the output gradient with the weights stored [c_in][8 - tap][c_out]
+//   weight gradient D[c_out][c_in] (one tap) = sum over pixels of dz[pixel][c_out] in[pixel + tap][c_in],
+//                  split over pixel ranges (fixed-order reduction, no atomics); operand tiles are
+//                  transposed through LDS so that every fragment is one 16-byte LDS read.
+// The forward and input-gradient kernels read each operand fragment with one 16-byte load straight
+// from memory (8 consecutive channels of one pixel, or of one weight row); the decoder's first
+// convolution reads its concatenated input from two tensors, the upsampled one at half resolution
+// (nearest neighbour: pixel (y, x) reads (y/2, x/2)), so neither the concatenation nor the upsampled
+// tensor is materialised. The one-channel input layer and the 1x1 output layer are plain FP32 VALU
+// kernels (9 and 32 multiply-adds per pixel). Parameters are kept in float32 (canonical layout) with
+// Adam's moments; the bfloat16 weight copies in both GEMM layouts are refreshed after every update.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ct_internal.hpp"
+#include "../../include/ct_unet.h"
+
+namespace ct {
+namespace {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kLayers = 15;
+// (c_in, c_out, kernel) in canonical order
+constexpr int kShape[kLayers][3] = {{1, 32, 3},    {32, 32, 3},   {32, 64, 3},   {64, 64, 3},   {64, 128, 3},
+                                    {128, 128, 3}, {128, 256, 3}, {256, 256, 3}, {384, 128, 3}, {128, 128, 3},
+                                    {192, 64, 3},  {64, 64, 3},   {96, 32, 3},   {32, 32, 3},   {32, 1, 1}};
+
+// Input channels [0, c0) come from src0 (c0 channels; half resolution when up0), [c0, c0 + c1) from
+// src1 (c1 channels, full resolution).
+struct ConvSrc {
+    const bf16 *src0;
+    int c0, up0;
+    const bf16 *src1;
+    int c1;
+};
+
+__device__ __forceinline__ const bf16 *src_ptr(const ConvSrc &S, int ci0, int n, int y, int x, int h, int w)
+{
+    if (ci0 < S.c0) {
+        if (S.up0) return S.src0 + (((size_t)n * (h >> 1) + (y >> 1)) * (w >> 1) + (x >> 1)) * S.c0 + ci0;
+        return S.src0 + (((size_t)n * h + y) * w + x) * S.c0 + ci0;
+    }
+    return S.src1 + (((size_t)n * h + y) * w + x) * S.c1 + (ci0 - S.c0);
+}
+
+// 3x3 convolution, wave tile 32 output channels x 64 pixels, four waves per workgroup on consecutive
+// pixel blocks. FWD: out = relu(conv + bias). !FWD (input gradient): out = conv * (mask > 0) (mask
+// optional). Requires c_in, c_out multiples of 32. The pixel count n*h*w is arbitrary (deep levels of
+// small images hold a handful of pixels): lanes past the last pixel read the last pixel's data and
+// store nothing.
+template <bool FWD>
+__global__ __launch_bounds__(256) void k_conv3x3(ConvSrc S, const bf16 *__restrict__ wt, const float *__restrict__ bias,
+                                                 const bf16 *__restrict__ mask, bf16 *__restrict__ out, int n, int h,
+                                                 int w, int cout)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int cin = S.c0 + S.c1;
+    const int hw = h * w, npix = n * hw;
+    const int p0 = (blockIdx.x * 4 + wave) * 64;
+    if (p0 >= npix) return;
+    const int co0 = blockIdx.y * 32;
+    const int g = lane >> 4, r = lane & 15;
+    int pn[4], py[4], px[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int p = min(p0 + 16 * s + r, npix - 1);
+        pn[s] = p / hw;
+        const int rem = p - pn[s] * hw;
+        py[s] = rem / w;
+        px[s] = rem - py[s] * w;
+    }
+    f32x4 acc[2][4];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc[m][s] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16x8 zero8 = {};
+    for (int tap = 0; tap < 9; ++tap) {
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        int ny_[4], nx_[4];
+        bool ok[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int yy = py[s] + dy, xx = px[s] + dx;
+            ok[s] = yy >= 0 && yy < h && xx >= 0 && xx < w;
+            ny_[s] = ok[s] ? yy : py[s];   // in-range address for masked lanes
+            nx_[s] = ok[s] ? xx : px[s];
+        }
+        for (int ci0 = 0; ci0 < cin; ci0 += 32) {
+            bf16x8 a[2], b[4];
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+                a[m] = *reinterpret_cast<const bf16x8 *>(wt + ((size_t)(co0 + 16 * m + r) * 9 + tap) * cin + ci0 + 8 * g);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const bf16x8 v = *reinterpret_cast<const bf16x8 *>(src_ptr(S, ci0, pn[s], ny_[s], nx_[s], h, w) + 8 * g);
+                b[s] = ok[s] ? v : zero8;
+            }
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    acc[m][s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[s], acc[m][s], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const int co = co0 + 16 * m + 4 * g;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if (p0 + 16 * s + r >= npix) continue;
+            const size_t o = (size_t)(p0 + 16 * s + r) * cout + co;
+            bf16x4 v;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                float t = acc[m][s][j];
+                if (FWD) t = fmaxf(t + bias[co + j], 0.f);
+                else if (mask) t = (float)mask[o + j] > 0.f ? t : 0.f;
+                v[j] = (bf16)t;
+            }
+            *reinterpret_cast<bf16x4 *>(out + o) = v;
+        }
+    }
+}
+
+// Weight gradient partials of a 3x3 convolution: part[split][c_out][tap][c_in] over the pixels
+// [split * pps, min((split + 1) * pps, npix)) (pps a multiple of 32; the last chunk of 32 may be
+// partial, its missing pixels count as zero). One wave per (split, tap, 32 x 32 channel block); grid
+// (splits, 9, (c_out / 32) * (c_in / 32)).
+__global__ __launch_bounds__(64) void k_conv3x3_wgrad(ConvSrc S, const bf16 *__restrict__ dz, int cout, int n, int h,
+                                                      int w, int pps, float *__restrict__ part)
+{
+    constexpr int LD = 40;   // padded LDS row (bf16): 80 bytes keeps rows 16-byte aligned
+    __shared__ __attribute__((aligned(16))) bf16 sA[32 * LD];   // [c_out][pixel]
+    __shared__ __attribute__((aligned(16))) bf16 sB[32 * LD];   // [c_in][pixel]
+    const int lane = threadIdx.x;
+    const int cin = S.c0 + S.c1;
+    const int split = blockIdx.x, tap = blockIdx.y;
+    const int nci = cin / 32;
+    const int co0 = (blockIdx.z / nci) * 32, ci0 = (blockIdx.z % nci) * 32;
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const int hw = h * w, npix = n * hw;
+    const int pb = split * pps, pe = min(pb + pps, npix);
+    const int g = lane >> 4, r = lane & 15;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) acc[m][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16x8 zero8 = {};
+    for (int pc = pb; pc < pe; pc += 32) {
+        // 32 pixels x 32 channels of each operand: 128 16-byte pieces, two per lane
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int idx = lane + 64 * t;
+            const int q = idx >> 2, c8 = (idx & 3) * 8;
+            const bool in = pc + q < pe;
+            const int p = in ? pc + q : pe - 1;
+            const bf16x8 va0 = *reinterpret_cast<const bf16x8 *>(dz + (size_t)p * cout + co0 + c8);
+            const int pn = p / hw, rem = p - pn * hw, py = rem / w, px = rem - py * w;
+            const int yy = py + dy, xx = px + dx;
+            const bool ok = in && yy >= 0 && yy < h && xx >= 0 && xx < w;
+            const bf16x8 vb0 = *reinterpret_cast<const bf16x8 *>(
+                src_ptr(S, ci0, pn, ok ? yy : py, ok ? xx : px, h, w) + c8);
+            const bf16x8 va = in ? va0 : zero8;
+            const bf16x8 vb = ok ? vb0 : zero8;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                sA[(c8 + i) * LD + q] = va[i];
+                sB[(c8 + i) * LD + q] = vb[i];
+            }
+        }
+        __syncthreads();
+        bf16x8 a[2], b[2];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) a[m] = *reinterpret_cast<const bf16x8 *>(sA + (16 * m + r) * LD + 8 * g);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) b[q] = *reinterpret_cast<const bf16x8 *>(sB + (16 * q + r) * LD + 8 * g);
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) acc[m][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[q], acc[m][q], 0, 0, 0);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int co = co0 + 16 * m + 4 * g + j, ci = ci0 + 16 * q + r;
+                part[(((size_t)split * cout + co) * 9 + tap) * cin + ci] = acc[m][q][j];
+            }
+}
+
+// grad[co][ci][dy][dx] (canonical) = sum over splits of part[split][co][tap][ci]
+__global__ void k_wgrad_reduce(const float *__restrict__ part, int nsplit, int cout, int cin, float *__restrict__ grad)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;   // canonical index
+    const size_t total = (size_t)cout * cin * 9;
+    if (i >= total) return;
+    const int tap = (int)(i % 9);
+    const int ci = (int)((i / 9) % cin);
+    const int co = (int)(i / (9 * (size_t)cin));
+    const size_t stride = (size_t)cout * 9 * cin;
+    const size_t o = ((size_t)co * 9 + tap) * cin + ci;
+    float s = 0.f;
+    for (int k = 0; k < nsplit; ++k) s += part[k * stride + o];
+    grad[i] = s;
+}
+
+// Bias gradient partials: part[split][c] = sum over the split's pixels of dz[p][c] (blockDim = c).
+__global__ void k_bias_part(const bf16 *__restrict__ dz, int c, int npix, int pps, float *__restrict__ part)
+{
+    const int ch = threadIdx.x;
+    const int pb = blockIdx.x * pps, pe = min(pb + pps, npix);
+    float s = 0.f;
+    for (int p = pb; p < pe; ++p) s += (float)dz[(size_t)p * c + ch];
+    part[(size_t)blockIdx.x * c + ch] = s;
+}
+
+// out[i] = sum over k of part[k * n + i]
+__global__ void k_sum_parts(const float *__restrict__ part, int nsplit, int n, float *__restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int k = 0; k < nsplit; ++k) s += part[(size_t)k * n + i];
+    out[i] = s;
+}
+
+// Input layer (one channel, 32 outputs): out[p][co] = relu(b[co] + sum_tap W[co][tap] x[p + tap]).
+__global__ void k_conv_in(const float *__restrict__ x, const float *__restrict__ W, const float *__restrict__ b,
+                          bf16 *__restrict__ out, int n, int h, int w)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int hw = h * w;
+    if (p >= n * hw) return;
+    const int pn = p / hw, rem = p - pn * hw, py = rem / w, px = rem - py * w;
+    float v[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int yy = py + t / 3 - 1, xx = px + t % 3 - 1;
+        v[t] = (yy >= 0 && yy < h && xx >= 0 && xx < w) ? x[(size_t)pn * hw + yy * w + xx] : 0.f;
+    }
+    for (int c8 = 0; c8 < 32; c8 += 8) {
+        bf16x8 o;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int co = c8 + i;
+            float z = b[co];
+#pragma unroll
+            for (int t = 0; t < 9; ++t) z = fmaf(W[co * 9 + t], v[t], z);
+            o[i] = (bf16)fmaxf(z, 0.f);
+        }
+        *reinterpret_cast<bf16x8 *>(out + (size_t)p * 32 + c8) = o;
+    }
+}
+
+// Input layer weight / bias gradient partials: thread t < 288 accumulates (co, tap) = (t / 9, t % 9),
+// threads 288..319 the bias of co = t - 288; part[split][320].
+__global__ __launch_bounds__(320) void k_conv_in_wgrad(const float *__restrict__ x, const bf16 *__restrict__ dz, int n,
+                                                       int h, int w, int pps, float *__restrict__ part)
+{
+    const int t = threadIdx.x;
+    const int hw = h * w, npix = n * hw;
+    const int pb = blockIdx.x * pps, pe = min(pb + pps, npix);
+    const bool isb = t >= 288;
+    const int co = isb ? t - 288 : t / 9, tap = isb ? 4 : t % 9;
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    float s = 0.f;
+    for (int p = pb; p < pe; ++p) {
+        const int pn = p / hw, rem = p - pn * hw, py = rem / w, px = rem - py * w;
+        const int yy = py + dy, xx = px + dx;
+        const float xv = isb ? 1.f : ((yy >= 0 && yy < h && xx >= 0 && xx < w) ? x[(size_t)pn * hw + yy * w + xx] : 0.f);
+        s = fmaf((float)dz[(size_t)p * 32 + co], xv, s);
+    }
+    part[(size_t)blockIdx.x * 320 + t] = s;
+}
+
+// Output layer: out[p] = x[p] + b + sum_c W[c] a[p][c]. With a target: dy[p] = gscale (out - target)
+// on masked pixels (0 elsewhere) and lpart[block] = sum over the block's masked pixels of
+// (1000 (out - target))^2 in FP64.
+__global__ __launch_bounds__(256) void k_conv_out(const bf16 *__restrict__ a, const float *__restrict__ x,
+                                                  const float *__restrict__ W, const float *__restrict__ b,
+                                                  float *__restrict__ out, const float *__restrict__ target,
+                                                  const unsigned char *__restrict__ mask, float gscale,
+                                                  float *__restrict__ dy, double *__restrict__ lpart, int npix, int hw)
+{
+    __shared__ double red[256];
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    double l = 0.0;
+    if (p < npix) {
+        float o = x[p] + b[0];
+        for (int c8 = 0; c8 < 32; c8 += 8) {
+            const bf16x8 v = *reinterpret_cast<const bf16x8 *>(a + (size_t)p * 32 + c8);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) o = fmaf(W[c8 + i], (float)v[i], o);
+        }
+        out[p] = o;
+        if (target) {
+            const bool m = mask[p % hw] != 0;
+            const float d = o - target[p];
+            dy[p] = m ? gscale * d : 0.f;
+            if (m) l = 1e6 * (double)d * (double)d;
+        }
+    }
+    if (target) {
+        red[threadIdx.x] = l;
+        __syncthreads();
+        for (int k = 128; k > 0; k >>= 1) {
+            if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) lpart[blockIdx.x] = red[0];
+    }
+}
+
+// Output layer backward: dz[p][c] = dy[p] W[c] (a[p][c] > 0); gradient partials part[split][33]
+// (32 weights, then the bias): thread c < 32 sums dy[p] a[p][c], thread 32 sums dy[p].
+__global__ void k_conv_out_back(const float *__restrict__ dy, const float *__restrict__ W, const bf16 *__restrict__ a,
+                                bf16 *__restrict__ dz, int npix)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    const float d = dy[p];
+    for (int c8 = 0; c8 < 32; c8 += 8) {
+        const bf16x8 v = *reinterpret_cast<const bf16x8 *>(a + (size_t)p * 32 + c8);
+        bf16x8 o;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) o[i] = (bf16)((float)v[i] > 0.f ? d * W[c8 + i] : 0.f);
+        *reinterpret_cast<bf16x8 *>(dz + (size_t)p * 32 + c8) = o;
+    }
+}
+
+__global__ void k_conv_out_wgrad(const float *__restrict__ dy, const bf16 *__restrict__ a, int npix, int pps,
+                                 float *__restrict__ part)
+{
+    const int t = threadIdx.x;   // 0..32
+    const int pb = blockIdx.x * pps, pe = min(pb + pps, npix);
+    float s = 0.f;
+    for (int p = pb; p < pe; ++p) s = fmaf(dy[p], t < 32 ? (float)a[(size_t)p * 32 + t] : 1.f, s);
+    part[(size_t)blockIdx.x * 33 + t] = s;
+}
+
+// 2x2 average pooling, NHWC bf16: one thread per (output pixel, 8 channels).
+__global__ void k_pool(const bf16 *__restrict__ in, bf16 *__restrict__ out, int n, int ho, int wo, int c)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c8n = c / 8;
+    const size_t total = (size_t)n * ho * wo * c8n;
+    if (i >= total) return;
+    const int c8 = (int)(i % c8n) * 8;
+    const size_t po = i / c8n;
+    const int x = (int)(po % wo), y = (int)((po / wo) % ho), nn = (int)(po / ((size_t)wo * ho));
+    const int wi = 2 * wo;
+    float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const bf16x8 v = *reinterpret_cast<const bf16x8 *>(
+                in + (((size_t)nn * 2 * ho + 2 * y + a) * wi + 2 * x + b) * c + c8);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) s[k] += (float)v[k];
+        }
+    bf16x8 o;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = (bf16)(0.25f * s[k]);
+    *reinterpret_cast<bf16x8 *>(out + po * c + c8) = o;
+}
+
+// Gradient through the nearest upsampling into a ReLU output: dz[n][y][x][c] = (sum over the 2x2
+// block of dcat[.][.][.][c]) * (act[n][y][x][c] > 0), c < c0; dcat has ccat channels at 2x resolution.
+__global__ void k_up_back(const bf16 *__restrict__ dcat, int ccat, const bf16 *__restrict__ act, bf16 *__restrict__ dz,
+                          int n, int hl, int wl, int c0)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c8n = c0 / 8;
+    const size_t total = (size_t)n * hl * wl * c8n;
+    if (i >= total) return;
+    const int c8 = (int)(i % c8n) * 8;
+    const size_t pl = i / c8n;
+    const int x = (int)(pl % wl), y = (int)((pl / wl) % hl), nn = (int)(pl / ((size_t)wl * hl));
+    const int wh = 2 * wl;
+    float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const bf16x8 v = *reinterpret_cast<const bf16x8 *>(
+                dcat + (((size_t)nn * 2 * hl + 2 * y + a) * wh + 2 * x + b) * ccat + c8);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) s[k] += (float)v[k];
+        }
+    const bf16x8 av = *reinterpret_cast<const bf16x8 *>(act + pl * c0 + c8);
+    bf16x8 o;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = (bf16)((float)av[k] > 0.f ? s[k] : 0.f);
+    *reinterpret_cast<bf16x8 *>(dz + pl * c0 + c8) = o;
+}
+
+// Encoder output gradient: dz = (skip part of dcat + pooling backward of dpool) * (act > 0).
+// act / dz: [n][h][w][c]; dcat: [n][h][w][ccat], skip channels at [c0, c0 + c); dpool: [n][h/2][w/2][c].
+__global__ void k_skip_combine(const bf16 *__restrict__ dcat, int ccat, int c0, const bf16 *__restrict__ dpool,
+                               const bf16 *__restrict__ act, bf16 *__restrict__ dz, int n, int h, int w, int c)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c8n = c / 8;
+    const size_t total = (size_t)n * h * w * c8n;
+    if (i >= total) return;
+    const int c8 = (int)(i % c8n) * 8;
+    const size_t p = i / c8n;
+    const int x = (int)(p % w), y = (int)((p / w) % h), nn = (int)(p / ((size_t)w * h));
+    const bf16x8 vs = *reinterpret_cast<const bf16x8 *>(dcat + p * ccat + c0 + c8);
+    const bf16x8 vp = *reinterpret_cast<const bf16x8 *>(
+        dpool + (((size_t)nn * (h / 2) + y / 2) * (w / 2) + x / 2) * c + c8);
+    const bf16x8 va = *reinterpret_cast<const bf16x8 *>(act + p * c + c8);
+    bf16x8 o;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = (bf16)((float)va[k] > 0.f ? (float)vs[k] + 0.25f * (float)vp[k] : 0.f);
+    *reinterpret_cast<bf16x8 *>(dz + p * c + c8) = o;
+}
+
+__global__ void k_adam(float *__restrict__ th, float *__restrict__ m, float *__restrict__ v, const float *__restrict__ g,
+                       size_t n, float lr, float bc1, float bc2)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = 0.9f * m[i] + 0.1f * gi;
+    const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    th[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + 1e-8f);
+}
+
+// bfloat16 copies of one 3x3 layer's canonical weights: wf[co][tap][ci] and wb[ci][8 - tap][co].
+__global__ void k_pack(const float *__restrict__ th, int cout, int cin, bf16 *__restrict__ wf, bf16 *__restrict__ wb)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)cout * cin * 9) return;
+    const int tap = (int)(i % 9);
+    const int ci = (int)((i / 9) % cin);
+    const int co = (int)(i / (9 * (size_t)cin));
+    const bf16 v = (bf16)th[i];
+    wf[((size_t)co * 9 + tap) * cin + ci] = v;
+    wb[((size_t)ci * 9 + (8 - tap)) * cout + co] = v;
+}
+
+// y * w into a float32 sinogram (storage-typed inputs)
+template <typename T>
+__global__ void k_wy(const T *__restrict__ y, const T *__restrict__ w, float *__restrict__ out, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)y[i] * (float)w[i];
+}
+
+__global__ void k_normalise(const float *__restrict__ bp, const float *__restrict__ dl, float inv_mu, float *__restrict__ x,
+                            size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = dl[i] > 0.f ? bp[i] / dl[i] * inv_mu : 0.f;
+}
+
+__global__ void k_start(const float *__restrict__ o, float mu, float *__restrict__ x, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = mu * fmaxf(o[i], 0.f);
+}
+
+inline unsigned blocks(size_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+}  // namespace ct
+
+using namespace ct;
+
+struct ct_unet {
+    int max_n = 0, max_h = 0, max_w = 0;
+    int device = 0;
+    size_t off[kLayers + 1] = {};   // canonical offsets of each layer's weights (bias follows)
+    float *theta = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+    bf16 *wf[kLayers] = {}, *wb[kLayers] = {};
+    long long step = 0;
+    // activations (bf16 NHWC) per level
+    bf16 *e1a = nullptr, *e1b = nullptr, *d1a = nullptr, *d1b = nullptr;
+    bf16 *p1 = nullptr, *e2a = nullptr, *e2b = nullptr, *d2a = nullptr, *d2b = nullptr;
+    bf16 *p2 = nullptr, *e3a = nullptr, *e3b = nullptr, *d3a = nullptr, *d3b = nullptr;
+    bf16 *p3 = nullptr, *ba = nullptr, *bb = nullptr;
+    float *out = nullptr;   // network output (training)
+    // gradients
+    bool train_alloc = false;
+    bf16 *dzA[4] = {}, *dzB[4] = {}, *dcat[3] = {}, *dpool[3] = {};
+    float *dy = nullptr, *part = nullptr;
+    size_t part_cap = 0;
+    double *lpart = nullptr;
+    size_t lpart_cap = 0;
+};
+
+namespace {
+
+template <typename T>
+ct_status ualloc(T **p, size_t n)
+{
+    hipError_t e = hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(e == hipErrorOutOfMemory ? CT_ERR_OOM : CT_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    return CT_OK;
+}
+
+template <typename T>
+void ufree(T **p)
+{
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+}
+
+size_t n_params()
+{
+    size_t s = 0;
+    for (auto &L : kShape) s += (size_t)L[1] * L[0] * L[2] * L[2] + L[1];
+    return s;
+}
+
+ct_status pack_weights(ct_unet *u, hipStream_t s)
+{
+    for (int l = 1; l < kLayers - 1; ++l) {
+        const int ci = kShape[l][0], co = kShape[l][1];
+        const size_t nw = (size_t)co * ci * 9;
+        hipLaunchKernelGGL(k_pack, dim3(blocks(nw, 256)), dim3(256), 0, s, u->theta + u->off[l], co, ci, u->wf[l], u->wb[l]);
+        CT_HIP_CHECK(hipGetLastError());
+    }
+    return CT_OK;
+}
+
+ct_status check_shape(const ct_unet *u, int n, int h, int w)
+{
+    if (n < 1 || n > u->max_n || h < 8 || w < 8 || h > u->max_h || w > u->max_w || h % 8 || w % 8)
+        return fail(CT_ERR_INVALID_ARG, "batch shape must be 1..max_n images of 8..max size, multiples of 8");
+    return CT_OK;
+}
+
+int splits_for(size_t npix, size_t tiles)
+{
+    // enough workgroups to fill the chip, at least 1024 pixels per split
+    size_t sp = std::max<size_t>(1, std::min<size_t>(npix / 1024, (2048 + tiles - 1) / tiles));
+    return (int)std::min<size_t>(sp, 512);
+}
+
+// Split geometry of a weight-gradient launch: pixels per split (multiple of 32) and split count.
+void wgrad_splits(size_t npix, int cin, int cout, int *pps, int *nsp)
+{
+    const size_t tiles = (size_t)9 * (cout / 32) * (cin / 32);
+    const int ns = splits_for(npix, tiles);
+    *pps = (int)(((npix + ns - 1) / ns + 31) / 32 * 32);
+    *nsp = (int)((npix + *pps - 1) / *pps);
+}
+
+constexpr int kBiasPps = 512, kOutPps = 4096, kInPps = 2048;
+constexpr int kLevel[kLayers] = {0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0, 0};
+
+// Largest partial-sum request of any backward launch for batches up to max_n x max_h x max_w. Every
+// request grows with the pixel count, so the maximum batch bounds all smaller ones.
+size_t part_need(const ct_unet *u)
+{
+    const size_t P1 = (size_t)u->max_n * u->max_h * u->max_w;
+    size_t need = 0;
+    for (int l = 1; l < kLayers - 1; ++l) {
+        const size_t np = P1 >> (2 * kLevel[l]);
+        // the split count of any smaller batch is at most splits_for() at the maximum one
+        const size_t ns = (size_t)splits_for(np, (size_t)9 * (kShape[l][1] / 32) * (kShape[l][0] / 32));
+        need = std::max(need, ns * kShape[l][1] * 9 * kShape[l][0]);
+        need = std::max(need, ((np + kBiasPps - 1) / kBiasPps) * (size_t)kShape[l][1]);
+    }
+    need = std::max(need, ((P1 + kOutPps - 1) / kOutPps) * 33);
+    need = std::max(need, ((P1 + kInPps - 1) / kInPps) * 320);
+    return need;
+}
+
+ct_status alloc_train(ct_unet *u)
+{
+    if (u->train_alloc) return CT_OK;
+    u->part_cap = part_need(u);
+    CT_TRY(ualloc(&u->part, u->part_cap));
+    const size_t P1 = (size_t)u->max_n * u->max_h * u->max_w;
+    const int ch[4] = {32, 64, 128, 256};
+    for (int l = 0; l < 4; ++l) {
+        const size_t P = P1 >> (2 * l);
+        CT_TRY(ualloc(&u->dzA[l], P * ch[l]));
+        CT_TRY(ualloc(&u->dzB[l], P * ch[l]));
+    }
+    const int ccat[3] = {96, 192, 384};
+    const int cpool[3] = {32, 64, 128};
+    for (int l = 0; l < 3; ++l) {
+        CT_TRY(ualloc(&u->dcat[l], (P1 >> (2 * l)) * ccat[l]));
+        CT_TRY(ualloc(&u->dpool[l], (P1 >> (2 * (l + 1))) * cpool[l]));
+    }
+    CT_TRY(ualloc(&u->dy, P1));
+    u->train_alloc = true;
+    return CT_OK;
+}
+
+// The partial-sum buffer is sized once (alloc_train) for the largest request at the maximum batch, so
+// that it is never reallocated while earlier kernels on the stream may still read it.
+ct_status ensure_part(ct_unet *u, size_t n)
+{
+    if (n <= u->part_cap) return CT_OK;
+    return fail(CT_ERR_HIP, "internal: partial-sum buffer too small");
+}
+
+ConvSrc one(const bf16 *src, int c) { return ConvSrc{src, c, 0, nullptr, 0}; }
+ConvSrc cat(const bf16 *low, int cl, const bf16 *skip, int cs) { return ConvSrc{low, cl, 1, skip, cs}; }
+
+hipError_t conv_fwd(const ct_unet *u, int l, const ConvSrc &S, bf16 *out, int n, int h, int w, hipStream_t s)
+{
+    const int cout = kShape[l][1];
+    const size_t npix = (size_t)n * h * w;
+    dim3 grid(blocks(npix, 256), cout / 32);
+    hipLaunchKernelGGL(k_conv3x3<true>, grid, dim3(256), 0, s, S, u->wf[l], u->theta + u->off[l] + (size_t)cout * kShape[l][0] * 9,
+                       nullptr, out, n, h, w, cout);
+    return hipGetLastError();
+}
+
+// input gradient of layer l (3x3, c_in % 32 == 0) from dz, optionally masked by act
+hipError_t conv_dgrad(const ct_unet *u, int l, const bf16 *dz, const bf16 *act, bf16 *out, int n, int h, int w,
+                      hipStream_t s)
+{
+    const int cin = kShape[l][0], cout = kShape[l][1];
+    const size_t npix = (size_t)n * h * w;
+    dim3 grid(blocks(npix, 256), cin / 32);
+    hipLaunchKernelGGL(k_conv3x3<false>, grid, dim3(256), 0, s, one(dz, cout), u->wb[l], nullptr, act, out, n, h, w, cin);
+    return hipGetLastError();
+}
+
+
+
+// weight and bias gradients of 3x3 layer l (c_in % 32 == 0) into u->grad
+ct_status conv_wgrad(ct_unet *u, int l, const ConvSrc &S, const bf16 *dz, int n, int h, int w, hipStream_t s)
+{
+    const int cin = kShape[l][0], cout = kShape[l][1];
+    const size_t npix = (size_t)n * h * w;
+    int pps, nsp;
+    wgrad_splits(npix, cin, cout, &pps, &nsp);
+    CT_TRY(ensure_part(u, (size_t)nsp * cout * 9 * cin));
+    hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(nsp, 9, (cout / 32) * (cin / 32)), dim3(64), 0, s, S, dz, cout, n, h, w, pps,
+                       u->part);
+    CT_HIP_CHECK(hipGetLastError());
+    const size_t nw = (size_t)cout * cin * 9;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(nw, 256)), dim3(256), 0, s, u->part, nsp, cout, cin, u->grad + u->off[l]);
+    CT_HIP_CHECK(hipGetLastError());
+    // bias
+    const int bps = kBiasPps;
+    const int nb = (int)((npix + bps - 1) / bps);
+    CT_TRY(ensure_part(u, (size_t)nb * cout));
+    hipLaunchKernelGGL(k_bias_part, dim3(nb), dim3(cout), 0, s, dz, cout, (int)npix, bps, u->part);
+    CT_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_parts, dim3(blocks(cout, 256)), dim3(256), 0, s, u->part, nb, cout, u->grad + u->off[l] + nw);
+    CT_HIP_CHECK(hipGetLastError());
+    return CT_OK;
+}
+
+const float *bias_of(const ct_unet *u, int l)
+{
+    return u->theta + u->off[l] + (size_t)kShape[l][1] * kShape[l][0] * kShape[l][2] * kShape[l][2];
+}
+
+// Forward pass up to the last 3x3 layer (the output layer is run_output).
+ct_status run_forward(ct_unet *u, const float *x, int n, int h, int w, hipStream_t s)
+{
+    const size_t P1 = (size_t)n * h * w;
+    const int h2 = h / 2, w2 = w / 2, h3 = h / 4, w3 = w / 4, h4 = h / 8, w4 = w / 8;
+    hipLaunchKernelGGL(k_conv_in, dim3(blocks(P1, 256)), dim3(256), 0, s, x, u->theta + u->off[0], bias_of(u, 0), u->e1a, n,
+                       h, w);
+    CT_HIP_CHECK(hipGetLastError());
+    CT_HIP_CHECK(conv_fwd(u, 1, one(u->e1a, 32), u->e1b, n, h, w, s));
+    hipLaunchKernelGGL(k_pool, dim3(blocks(P1 / 4 * 4, 256)), dim3(256), 0, s, u->e1b, u->p1, n, h2, w2, 32);
+    CT_HIP_CHECK(hipGetLastError());
+    CT_HIP_CHECK(conv_fwd(u, 2, one(u->p1, 32), u->e2a, n, h2, w2, s));
+    CT_HIP_CHECK(conv_fwd(u, 3, one(u->e2a, 64), u->e2b, n, h2, w2, s));
+    hipLaunchKernelGGL(k_pool, dim3(blocks(P1 / 16 * 8, 256)), dim3(256), 0, s, u->e2b, u->p2, n, h3, w3, 64);
+    CT_HIP_CHECK(hipGetLastError());
+    CT_HIP_CHECK(conv_fwd(u, 4, one(u->p2, 64), u->e3a, n, h3, w3, s));
+    CT_HIP_CHECK(conv_fwd(u, 5, one(u->e3a, 128), u->e3b, n, h3, w3, s));
+    hipLaunchKernelGGL(k_pool, dim3(blocks(P1 / 64 * 16, 256)), dim3(256), 0, s, u->e3b, u->p3, n, h4, w4, 128);
+    CT_HIP_CHECK(hipGetLastError());
+    CT_HIP_CHECK(conv_fwd(u, 6, one(u->p3, 128), u->ba, n, h4, w4, s));
+    CT_HIP_CHECK(conv_fwd(u, 7, one(u->ba, 256), u->bb, n, h4, w4, s));
+    CT_HIP_CHECK(conv_fwd(u, 8, cat(u->bb, 256, u->e3b, 128), u->d3a, n, h3, w3, s));
+    CT_HIP_CHECK(conv_fwd(u, 9, one(u->d3a, 128), u->d3b, n, h3, w3, s));
+    CT_HIP_CHECK(conv_fwd(u, 10, cat(u->d3b, 128, u->e2b, 64), u->d2a, n, h2, w2, s));
+    CT_HIP_CHECK(conv_fwd(u, 11, one(u->d2a, 64), u->d2b, n, h2, w2, s));
+    CT_HIP_CHECK(conv_fwd(u, 12, cat(u->d2b, 64, u->e1b, 32), u->d1a, n, h, w, s));
+    CT_HIP_CHECK(conv_fwd(u, 13, one(u->d1a, 32), u->d1b, n, h, w, s));
+    return CT_OK;
+}
+
+// Output layer; with a target also the loss gradient dy (gscale = 2e6 / masked pixel count) and one
+// FP64 loss partial per 256 pixels (their count is returned through nlpart).
+ct_status run_output(ct_unet *u, const float *x, float *out, int n, int h, int w, const float *target,
+                     const unsigned char *mask, float gscale, int *nlpart, hipStream_t s)
+{
+    const size_t P1 = (size_t)n * h * w;
+    const int nbl = (int)blocks(P1, 256);   // <= lpart_cap (sized for the maximum batch at creation)
+    if (nlpart) *nlpart = nbl;
+    hipLaunchKernelGGL(k_conv_out, dim3(blocks(P1, 256)), dim3(256), 0, s, u->d1b, x, u->theta + u->off[14],
+                       bias_of(u, 14), out, target, mask, gscale, u->dy, u->lpart, (int)P1, h * w);
+    CT_HIP_CHECK(hipGetLastError());
+    return CT_OK;
+}
+
+ct_status run_backward(ct_unet *u, const float *x, int n, int h, int w, hipStream_t s)
+{
+    const size_t P1 = (size_t)n * h * w;
+    const int h2 = h / 2, w2 = w / 2, h3 = h / 4, w3 = w / 4, h4 = h / 8, w4 = w / 8;
+    // output layer
+    hipLaunchKernelGGL(k_conv_out_back, dim3(blocks(P1, 256)), dim3(256), 0, s, u->dy, u->theta + u->off[14], u->d1b,
+                       u->dzA[0], (int)P1);
+    CT_HIP_CHECK(hipGetLastError());
+    {
+        const int pps = kOutPps;
+        const int nsp = (int)((P1 + pps - 1) / pps);
+        CT_TRY(ensure_part(u, (size_t)nsp * 33));
+        hipLaunchKernelGGL(k_conv_out_wgrad, dim3(nsp), dim3(33), 0, s, u->dy, u->d1b, (int)P1, pps, u->part);
+        CT_HIP_CHECK(hipGetLastError());
+        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, u->part, nsp, 33, u->grad + u->off[14]);
+        CT_HIP_CHECK(hipGetLastError());
+    }
+    // decoder level 1
+    CT_TRY(conv_wgrad(u, 13, one(u->d1a, 32), u->dzA[0], n, h, w, s));
+    CT_HIP_CHECK(conv_dgrad(u, 13, u->dzA[0], u->d1a, u->dzB[0], n, h, w, s));
+    CT_TRY(conv_wgrad(u, 12, cat(u->d2b, 64, u->e1b, 32), u->dzB[0], n, h, w, s));
+    CT_HIP_CHECK(conv_dgrad(u, 12, u->dzB[0], nullptr, u->dcat[0], n, h, w, s));
+    hipLaunchKernelGGL(k_up_back, dim3(blocks(P1 / 4 * 8, 256)), dim3(256), 0, s, u->dcat[0], 96, u->d2b, u->dzA[1], n, h2,
+                       w2, 64);
+    CT_HIP_CHECK(hipGetLastError());
+    // decoder level 2
+    CT_TRY(conv_wgrad(u, 11, one(u->d2a, 64), u->dzA[1], n, h2, w2, s));
+    CT_HIP_CHECK(conv_dgrad(u, 11, u->dzA[1], u->d2a, u->dzB[1], n, h2, w2, s));
+    CT_TRY(conv_wgrad(u, 10, cat(u->d3b, 128, u->e2b, 64), u->dzB[1], n, h2, w2, s));
+    CT_HIP_CHECK(conv_dgrad(u, 10, u->dzB[1], nullptr, u->dcat[1], n, h2, w2, s));
+    hipLaunchKernelGGL(k_up_back, dim3(blocks(P1 / 16 * 16, 256)), dim3(256), 0, s, u->dcat[1], 192, u->d3b, u->dzA[2], n,
+                       h3, w3, 128);
+    CT_HIP_CHECK(hipGetLastError());
+    // decoder level 3
+    CT_TRY(conv_wgrad(u, 9, one(u->d3a, 128), u->dzA[2], n, h3, w3, s));
+    CT_HIP_CHECK(conv_dgrad(u, 9, u->dzA[2], u->d3a, u->dzB[2], n, h3, w3, s));
+    CT_TRY(conv_wgrad(u, 8, cat(u->bb, 256, u->e3b, 128), u->dzB[2], n, h3, w3, s));
+    CT_HIP_CHECK(conv_dgrad(u, 8, u->dzB[2], nullptr, u->dcat[2], n, h3, w3, s));
+    hipLaunchKernelGGL(k_up_back, dim3(blocks(P1 / 64 * 32, 256)), dim3(256), 0, s, u->dcat[2], 384, u->bb, u->dzA[3], n,
+                       h4, w4, 256);
+    CT_HIP_CHECK(hipGetLastError());
+    // bottleneck
+    CT_TRY(conv_wgrad(u, 7, one(u->ba, 256), u->dzA[3], n, h4, w4, s));
+    CT_HIP_CHECK(conv_dgrad(u, 7, u->dzA[3], u->ba, u->dzB[3], n, h4, w4, s));
+    CT_TRY(conv_wgrad(u, 6, one(u->p3, 128), u->dzB[3], n, h4, w4, s));
+    CT_HIP_CHECK(conv_dgrad(u, 6, u->dzB[3], nullptr, u->dpool[2], n, h4, w4, s));
+    // encoder level 3
+    hipLaunchKernelGGL(k_skip_combine, dim3(blocks(P1 / 16 * 16, 256)), dim3(256), 0, s, u->dcat[2], 384, 256, u->dpool[2],
+                       u->e3b, u->dzA[2], n, h3, w3, 128);
+    CT_HIP_CHECK(hipGetLastError());
+    CT_TRY(conv_wgrad(u, 5, one(u->e3a, 128), u->dzA[2], n, h3, w3, s));
+    CT_HIP_CHECK(conv_dgrad(u, 5, u->dzA[2], u->e3a, u->dzB[2], n, h3, w3, s));
+    CT_TRY(conv_wgrad(u, 4, one(u->p2, 64), u->dzB[2], n, h3, w3, s));
+    CT_HIP_CHECK(conv_dgrad(u, 4, u->dzB[2], nullptr, u->dpool[1], n, h3, w3, s));
+    // encoder level 2
+    hipLaunchKernelGGL(k_skip_combine, dim3(blocks(P1 / 4 * 8, 256)), dim3(256), 0, s, u->dcat[1], 192, 128, u->dpool[1],
+                       u->e2b, u->dzA[1], n, h2, w2, 64);
+    CT_HIP_CHECK(hipGetLastError());
+    CT_TRY(conv_wgrad(u, 3, one(u->e2a, 64), u->dzA[1], n, h2, w2, s));
+    CT_HIP_CHECK(conv_dgrad(u, 3, u->dzA[1], u->e2a, u->dzB[1], n, h2, w2, s));
+    CT_TRY(conv_wgrad(u, 2, one(u->p1, 32), u->dzB[1], n, h2, w2, s));
+    CT_HIP_CHECK(conv_dgrad(u, 2, u->dzB[1], nullptr, u->dpool[0], n, h2, w2, s));
+    // encoder level 1
+    hipLaunchKernelGGL(k_skip_combine, dim3(blocks(P1 * 4, 256)), dim3(256), 0, s, u->dcat[0], 96, 64, u->dpool[0], u->e1b,
+                       u->dzA[0], n, h, w, 32);
+    CT_HIP_CHECK(hipGetLastError());
+    CT_TRY(conv_wgrad(u, 1, one(u->e1a, 32), u->dzA[0], n, h, w, s));
+    CT_HIP_CHECK(conv_dgrad(u, 1, u->dzA[0], u->e1a, u->dzB[0], n, h, w, s));
+    {
+        const int pps = kInPps;
+        const int nsp = (int)((P1 + pps - 1) / pps);
+        CT_TRY(ensure_part(u, (size_t)nsp * 320));
+        hipLaunchKernelGGL(k_conv_in_wgrad, dim3(nsp), dim3(320), 0, s, x, u->dzB[0], n, h, w, pps, u->part);
+        CT_HIP_CHECK(hipGetLastError());
+        // weights 0..287 (canonical [co][1][3][3] == [co][tap]), then biases 288..319
+        hipLaunchKernelGGL(k_sum_parts, dim3(2), dim3(256), 0, s, u->part, nsp, 320, u->grad + u->off[0]);
+        CT_HIP_CHECK(hipGetLastError());
+    }
+    return CT_OK;
+}
+
+// Loss and gradient of one batch: forward with the loss epilogue, then backward. Returns the loss
+// partial count through nlp (the caller reduces u->lpart when it wants the loss).
+ct_status loss_and_grad(ct_unet *u, const float *x, const float *target, const unsigned char *mask, int n, int h,
+                        int w, int *nlp, hipStream_t s)
+{
+    CT_TRY(alloc_train(u));
+    CT_TRY(run_forward(u, x, n, h, w, s));
+    // masked pixel count (FP64-exact on the host from a one-off copy of the mask)
+    std::vector<unsigned char> hm((size_t)h * w);
+    CT_HIP_CHECK(hipMemcpyAsync(hm.data(), mask, hm.size(), hipMemcpyDeviceToHost, s));
+    CT_HIP_CHECK(hipStreamSynchronize(s));
+    size_t cnt = 0;
+    for (unsigned char c : hm) cnt += c != 0;
+    if (cnt == 0) return fail(CT_ERR_INVALID_ARG, "mask selects no pixel");
+    const float gscale = (float)(2.0e6 / ((double)cnt * n));
+    CT_TRY(run_output(u, x, u->out, n, h, w, target, mask, gscale, nlp, s));
+    CT_TRY(run_backward(u, x, n, h, w, s));
+    return CT_OK;
+}
+
+ct_status read_loss(ct_unet *u, int nlp, int n, int h, int w, const unsigned char *mask, double *loss, hipStream_t s)
+{
+    std::vector<double> lp((size_t)nlp);
+    CT_HIP_CHECK(hipMemcpyAsync(lp.data(), u->lpart, lp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    std::vector<unsigned char> hm((size_t)h * w);
+    CT_HIP_CHECK(hipMemcpyAsync(hm.data(), mask, hm.size(), hipMemcpyDeviceToHost, s));
+    CT_HIP_CHECK(hipStreamSynchronize(s));
+    double sum = 0.0;
+    for (double v : lp) sum += v;
+    size_t cnt = 0;
+    for (unsigned char c : hm) cnt += c != 0;
+    *loss = sum / ((double)cnt * n);
+    return CT_OK;
+}
+
+hipStream_t as_s(void *p) { return reinterpret_cast<hipStream_t>(p); }
+
+}  // namespace
+
+extern "C" {
+
+size_t ct_unet_num_params(void) { return n_params(); }
+
+void ct_unet_destroy(ct_unet *u)
+{
+    if (!u) return;
+    (void)hipDeviceSynchronize();
+    ufree(&u->theta);
+    ufree(&u->m);
+    ufree(&u->v);
+    ufree(&u->grad);
+    for (int l = 0; l < kLayers; ++l) {
+        ufree(&u->wf[l]);
+        ufree(&u->wb[l]);
+    }
+    bf16 **acts[] = {&u->e1a, &u->e1b, &u->d1a, &u->d1b, &u->p1, &u->e2a, &u->e2b, &u->d2a, &u->d2b,
+                     &u->p2, &u->e3a, &u->e3b, &u->d3a, &u->d3b, &u->p3, &u->ba, &u->bb};
+    for (bf16 **a : acts) ufree(a);
+    for (int l = 0; l < 4; ++l) {
+        ufree(&u->dzA[l]);
+        ufree(&u->dzB[l]);
+    }
+    for (int l = 0; l < 3; ++l) {
+        ufree(&u->dcat[l]);
+        ufree(&u->dpool[l]);
+    }
+    ufree(&u->out);
+    ufree(&u->dy);
+    ufree(&u->part);
+    ufree(&u->lpart);
+    delete u;
+}
+
+ct_status ct_unet_set_params(ct_unet *u, const float *theta)
+{
+    if (!u || !theta) return fail(CT_ERR_INVALID_ARG, "NULL argument");
+    const size_t np = n_params();
+    CT_HIP_CHECK(hipMemcpy(u->theta, theta, np * sizeof(float), hipMemcpyHostToDevice));
+    CT_HIP_CHECK(hipMemset(u->m, 0, np * sizeof(float)));
+    CT_HIP_CHECK(hipMemset(u->v, 0, np * sizeof(float)));
+    u->step = 0;
+    CT_TRY(pack_weights(u, nullptr));
+    CT_HIP_CHECK(hipDeviceSynchronize());
+    return CT_OK;
+}
+
+ct_status ct_unet_create(const float *theta, int max_n, int max_h, int max_w, ct_unet **out)
+{
+    if (!out || !theta) return fail(CT_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    if (max_n < 1 || max_h < 8 || max_w < 8 || max_h % 8 || max_w % 8 || (size_t)max_n * max_h * max_w > (1ull << 31) / 96)
+        return fail(CT_ERR_INVALID_ARG, "max sizes must be >= 8, multiples of 8, and bounded");
+    ct_unet *u = new (std::nothrow) ct_unet();
+    if (!u) return fail(CT_ERR_OOM, "host allocation failed");
+    u->max_n = max_n;
+    u->max_h = max_h;
+    u->max_w = max_w;
+    (void)hipGetDevice(&u->device);
+    size_t o = 0;
+    for (int l = 0; l < kLayers; ++l) {
+        u->off[l] = o;
+        o += (size_t)kShape[l][1] * kShape[l][0] * kShape[l][2] * kShape[l][2] + kShape[l][1];
+    }
+    u->off[kLayers] = o;
+    auto fail_out = [&](ct_status st) {
+        ct_unet_destroy(u);
+        return st;
+    };
+    ct_status st;
+#define U_TRY(e)                                                                                                      \
+    if ((st = (e)) != CT_OK) return fail_out(st);
+    U_TRY(ualloc(&u->theta, o));
+    U_TRY(ualloc(&u->m, o));
+    U_TRY(ualloc(&u->v, o));
+    U_TRY(ualloc(&u->grad, o));
+    for (int l = 1; l < kLayers - 1; ++l) {
+        const size_t nw = (size_t)kShape[l][0] * kShape[l][1] * 9;
+        U_TRY(ualloc(&u->wf[l], nw));
+        U_TRY(ualloc(&u->wb[l], nw));
+    }
+    const size_t P1 = (size_t)max_n * max_h * max_w;
+    const size_t P2 = P1 / 4, P3 = P1 / 16, P4 = P1 / 64;
+    U_TRY(ualloc(&u->e1a, P1 * 32));
+    U_TRY(ualloc(&u->e1b, P1 * 32));
+    U_TRY(ualloc(&u->d1a, P1 * 32));
+    U_TRY(ualloc(&u->d1b, P1 * 32));
+    U_TRY(ualloc(&u->p1, P2 * 32));
+    U_TRY(ualloc(&u->e2a, P2 * 64));
+    U_TRY(ualloc(&u->e2b, P2 * 64));
+    U_TRY(ualloc(&u->d2a, P2 * 64));
+    U_TRY(ualloc(&u->d2b, P2 * 64));
+    U_TRY(ualloc(&u->p2, P3 * 64));
+    U_TRY(ualloc(&u->e3a, P3 * 128));
+    U_TRY(ualloc(&u->e3b, P3 * 128));
+    U_TRY(ualloc(&u->d3a, P3 * 128));
+    U_TRY(ualloc(&u->d3b, P3 * 128));
+    U_TRY(ualloc(&u->p3, P4 * 128));
+    U_TRY(ualloc(&u->ba, P4 * 256));
+    U_TRY(ualloc(&u->bb, P4 * 256));
+    U_TRY(ualloc(&u->out, P1));
+    u->lpart_cap = blocks(P1, 256);
+    U_TRY(ualloc(&u->lpart, u->lpart_cap));
+    U_TRY(ct_unet_set_params(u, theta));
+#undef U_TRY
+    *out = u;
+    return CT_OK;
+}
+
+ct_status ct_unet_get_params(const ct_unet *u, float *theta)
+{
+    if (!u || !theta) return fail(CT_ERR_INVALID_ARG, "NULL argument");
+    CT_HIP_CHECK(hipDeviceSynchronize());
+    CT_HIP_CHECK(hipMemcpy(theta, u->theta, n_params() * sizeof(float), hipMemcpyDeviceToHost));
+    return CT_OK;
+}
+
+ct_status ct_unet_forward(ct_unet *u, const float *x, float *out, int n, int h, int w, void *stream)
+{
+    if (!u || !x || !out) return fail(CT_ERR_INVALID_ARG, "NULL argument");
+    if (x == out) return fail(CT_ERR_INVALID_ARG, "x and out may not alias");
+    CT_TRY(check_shape(u, n, h, w));
+    hipStream_t s = as_s(stream);
+    CT_TRY(run_forward(u, x, n, h, w, s));
+    CT_TRY(run_output(u, x, out, n, h, w, nullptr, nullptr, 0.f, nullptr, s));
+    return CT_OK;
+}
+
+ct_status ct_unet_gradient(ct_unet *u, const float *x, const float *target, const unsigned char *mask, int n, int h,
+                           int w, double *loss, float *grad, void *stream)
+{
+    if (!u || !x || !target || !mask) return fail(CT_ERR_INVALID_ARG, "NULL argument");
+    CT_TRY(check_shape(u, n, h, w));
+    hipStream_t s = as_s(stream);
+    int nlp = 0;
+    CT_TRY(loss_and_grad(u, x, target, mask, n, h, w, &nlp, s));
+    if (loss) CT_TRY(read_loss(u, nlp, n, h, w, mask, loss, s));
+    if (grad) {
+        CT_HIP_CHECK(hipMemcpyAsync(grad, u->grad, n_params() * sizeof(float), hipMemcpyDeviceToHost, s));
+        CT_HIP_CHECK(hipStreamSynchronize(s));
+    }
+    return CT_OK;
+}
+
+ct_status ct_unet_train_step(ct_unet *u, const float *x, const float *target, const unsigned char *mask, int n, int h,
+                             int w, float lr, double *loss, void *stream)
+{
+    if (!u || !x || !target || !mask) return fail(CT_ERR_INVALID_ARG, "NULL argument");
+    if (!(lr > 0.f)) return fail(CT_ERR_INVALID_ARG, "lr must be > 0");
+    CT_TRY(check_shape(u, n, h, w));
+    hipStream_t s = as_s(stream);
+    int nlp = 0;
+    CT_TRY(loss_and_grad(u, x, target, mask, n, h, w, &nlp, s));
+    if (loss) CT_TRY(read_loss(u, nlp, n, h, w, mask, loss, s));
+    u->step += 1;
+    const float bc1 = (float)(1.0 - std::pow(0.9, (double)u->step));
+    const float bc2 = (float)(1.0 - std::pow(0.999, (double)u->step));
+    const size_t np = n_params();
+    hipLaunchKernelGGL(k_adam, dim3(blocks(np, 256)), dim3(256), 0, s, u->theta, u->m, u->v, u->grad, np, lr, bc1, bc2);
+    CT_HIP_CHECK(hipGetLastError());
+    CT_TRY(pack_weights(u, s));
+    return CT_OK;
+}
+
+ct_status ct_unet_input(ct_geom *g, const void *y, const void *w, const float *dl, double mu_water, float *x_in,
+                        void *stream)
+{
+    if (!g || !y || !w || !dl || !x_in) return fail(CT_ERR_INVALID_ARG, "NULL argument");
+    if (!(mu_water > 0)) return fail(CT_ERR_INVALID_ARG, "mu_water must be > 0");
+    return unet_input(g, y, w, dl, 1.0 / mu_water, x_in, as_s(stream));
+}
+
+}  // extern "C"
+
+namespace ct {
+
+// x_in = factor * A'(w y) / dl (0 where dl = 0)
+ct_status unet_input(ct_geom *g, const void *y, const void *w, const float *dl, double factor, float *x_in, hipStream_t s)
+{
+    CT_TRY(ensure_workspace(g, g->desc.nviews, 4));
+    Workspace &W = g->ws;
+    const size_t ns = (size_t)g->desc.nviews * g->desc.nb;
+    const int dt = g->desc.storage;
+    if (dt == CT_F32)
+        hipLaunchKernelGGL(k_wy<float>, dim3(blocks(ns, 256)), dim3(256), 0, s, (const float *)y, (const float *)w, W.r, ns);
+    else if (dt == CT_F16)
+        hipLaunchKernelGGL(k_wy<_Float16>, dim3(blocks(ns, 256)), dim3(256), 0, s, (const _Float16 *)y, (const _Float16 *)w,
+                           W.r, ns);
+    else
+        hipLaunchKernelGGL(k_wy<__bf16>, dim3(blocks(ns, 256)), dim3(256), 0, s, (const __bf16 *)y, (const __bf16 *)w, W.r,
+                           ns);
+    CT_HIP_CHECK(hipGetLastError());
+    BpLaunch a;
+    a.G = g->dev;
+    a.r = W.r;
+    a.vstart = 0;
+    a.vstride = 1;
+    a.nv = g->desc.nviews;
+    a.out_back = W.tmp;
+    CT_HIP_CHECK(launch_back_update(a, BP_BACK, CT_F32, CT_F32, s));
+    hipLaunchKernelGGL(k_normalise, dim3(blocks(W.npix, 256)), dim3(256), 0, s, W.tmp, dl, (float)factor, x_in, W.npix);
+    CT_HIP_CHECK(hipGetLastError());
+    return CT_OK;
+}
+
+// Learned start of a solve: x = mu_water * max(network(A'(w y) / (D_L / dl_scale) / mu_water), 0), with dl
+// the solve's (scaled) majorizer. a and b: two [ny][nx] float32 scratch images.
+ct_status learned_start(ct_geom *g, const ct_unet *uc, const void *y, const void *w, const float *dl, double dl_scale,
+                        double mu_water, float *x, float *a, float *b, hipStream_t s)
+{
+    ct_unet *u = const_cast<ct_unet *>(uc);
+    CT_TRY(unet_input(g, y, w, dl, dl_scale / mu_water, a, s));
+    CT_TRY(ct_unet_forward(u, a, b, 1, g->desc.ny, g->desc.nx, s));
+    hipLaunchKernelGGL(k_start, dim3(blocks(g->ws.npix, 256)), dim3(256), 0, s, b, (float)mu_water, x, g->ws.npix);
+    CT_HIP_CHECK(hipGetLastError());
+    return CT_OK;
+}
+
+}  // namespace ct

@@ -1,5 +1,6 @@
-"""The C ABI library loads on any host and exports every entry point that include/ct.h declares.
-No compute calls are made here (no GPU needed)."""
+"""The C ABI library loads on any host and exports every entry point that the headers under include/
+declare. No GPU compute calls are made here."""
+import glob
 import os
 import re
 import subprocess
@@ -7,13 +8,15 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "ct.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(ct_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(ct_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
@@ -57,3 +60,9 @@ def test_invalid_descriptor_is_rejected_without_touching_the_gpu():
     d.dsd = 400.0   # dsd < dso
     assert L.ct_geom_create(ctypes.byref(d), ctypes.byref(h)) == _lib.CT_ERR_INVALID_ARG
     assert L.ct_geom_create(None, ctypes.byref(h)) == _lib.CT_ERR_INVALID_ARG
+
+
+def test_network_parameter_count_is_host_only_and_matches_the_reference():
+    from oracle import unet
+    from paper_1512_04564_amd import _lib
+    assert _lib.load().ct_unet_num_params() == unet.n_params() == 1946305
