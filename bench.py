@@ -33,6 +33,8 @@ sys.path.insert(0, ROOT)
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 XSTAR = os.path.join(ROOT, "tests", "golden", "xstar_cfg2_seed100.npz")
+UNET_WEIGHTS = os.path.join(ROOT, "paper_1512_04564_amd", "weights", "unet_512.npz")
+MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix-core peak
 KERNEL_SRC = os.path.join(ROOT, "paper_1512_04564_amd", "csrc", "ct_kernels.hip")
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic_k_back_update_cfg2.json")
 COPY_BYTES = 256 * 2 ** 20   # calibration copy of the counter workload (bytes read = bytes written)
@@ -55,6 +57,56 @@ def measured_traffic():
     if t.get("kernel_source_sha256") != kernel_source_hash():
         return None
     return t["bytes_per_launch"]
+
+
+def write_traffic(fetch_dir, write_dir):
+    """Write the traffic record of the fused update kernel from the two counter runs of --pmc-workload
+    (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, CSV output): average KiB per dispatch of the kernel, scaled
+    by the counters' reading for the workload's device copy of COPY_BYTES (the non-library dispatch that
+    writes the most), and stamped with the kernel source's hash."""
+    import csv
+    import glob
+
+    def rows(d, counter):
+        out = []
+        for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            out += [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        return out
+
+    def mean_of(rs, key):
+        v = [float(r["Counter_Value"]) for r in rs if key in r["Kernel_Name"]]
+        return sum(v) / len(v), len(v)
+
+    def library(r):
+        return "ct::" in r["Kernel_Name"]
+
+    rf, rw = rows(fetch_dir, "FETCH_SIZE"), rows(write_dir, "WRITE_SIZE")
+    fu, n = mean_of(rf, "k_back_update<2")
+    wu, _ = mean_of(rw, "k_back_update<2")
+    ffw, _ = mean_of(rf, "k_forward<1, false")
+    wfw, _ = mean_of(rw, "k_forward<1, false")
+    cw = max((r for r in rw if not library(r)), key=lambda r: float(r["Counter_Value"]))
+    cf = max((r for r in rf if r["Kernel_Name"] == cw["Kernel_Name"]), key=lambda r: float(r["Counter_Value"]))
+    kib = COPY_BYTES / 1024.0
+    ff, wf = kib / float(cf["Counter_Value"]), kib / float(cw["Counter_Value"])
+    rec = {
+        "kernel": "k_back_update<BP_FULL>",
+        "workload": "512x512, 888 bins, 984 views, 41 subsets (24-view subset per launch)",
+        "kernel_source_sha256": kernel_source_hash(),
+        "fetch_kib_per_dispatch": round(fu, 1),
+        "write_kib_per_dispatch": round(wu, 1),
+        "dispatches_averaged": n,
+        "copy_calibration": {"bytes_copied": COPY_BYTES, "kernel": cw["Kernel_Name"][:120],
+                             "fetch_kib": float(cf["Counter_Value"]), "write_kib": float(cw["Counter_Value"]),
+                             "fetch_factor": round(ff, 4), "write_factor": round(wf, 4)},
+        "bytes_per_launch": int(round((fu * ff + wu * wf) * 1024)),
+        "forward_kernel_bytes_per_launch": int(round((ffw * ff + wfw * wf) * 1024)),
+        "commands": [f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {fetch_dir} -o p -- python3 bench.py --pmc-workload",
+                     f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {write_dir} -o p -- python3 bench.py --pmc-workload"],
+    }
+    with open(TRAFFIC, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec, indent=1))
 
 
 def pmc_workload():
@@ -102,6 +154,16 @@ def dd_work_counts(g):
     return dict(nnz=nnz, bin_lines=g.nviews * g.nb * max(g.nx, g.ny), pix_views=g.nviews * g.nx * g.ny)
 
 
+def unet_flops(ny, nx):
+    """Algorithmic flops of one network forward pass on an ny x nx image: 2 c_in c_out k^2 per output
+    pixel of every convolution, at its level's resolution (levels: encoder 1-3 at full, 1/2, 1/4; the
+    bottleneck at 1/8; decoder 3-1 back up; the 1x1 output at full resolution)."""
+    from paper_1512_04564_amd import synth
+    level = [0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0, 0]
+    return sum(2.0 * ci * co * k * k * (ny >> level[i]) * (nx >> level[i])
+               for i, (ci, co, k) in enumerate(synth.UNET_SHAPES))
+
+
 def oracle_baseline(g, s, iters):
     """The FP64 CPU oracle as it stands: `iters` outer iterations of Algorithm 1 (after D_L and init)."""
     import oracle
@@ -128,9 +190,14 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven 32-slice batch")
     ap.add_argument("--batch-iters", type=int, default=20)
     ap.add_argument("--pmc-workload", action="store_true", help="run the short counter workload and exit")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the traffic record from the two counter runs and exit (no GPU)")
     args = ap.parse_args()
     if args.pmc_workload:
         pmc_workload()
+        return
+    if args.write_traffic:
+        write_traffic(*args.write_traffic)
         return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU design is described "
@@ -149,8 +216,11 @@ def main():
     x = torch.zeros((g.ny, g.nx), device=dev)
     stream = torch.cuda.current_stream()
 
+    net = None
+
     def solve(alpha, niters, xref=None, trace=False, start="zero"):
-        p = api.Params(alpha=alpha, niters=niters, subset_order=ORDER, start=start, fov_radius=synth.fov_radius(g))
+        p = api.Params(alpha=alpha, niters=niters, subset_order=ORDER, start=start, fov_radius=synth.fov_radius(g),
+                       unet=net if start == "learned" else None)
         return api.rlalm_solve(G, p, y, w, x, x_ref=xref, trace=trace)
 
     def timed(fn, reps):
@@ -264,12 +334,31 @@ def main():
                    "speedup_vs_one_by_one": round(t_seq / t_batch, 3), "launch_shape": cfg}
         del Gb, xs_b
 
-    # time to 1 HU against the oracle's converged reference, when it is available (zero and FBP-like starts)
+    # learned warm start: network inference rate (the trained parameters are committed by train_unet.py)
+    net = None
+    unet_line = None
+    if os.path.exists(UNET_WEIGHTS):
+        from paper_1512_04564_amd import unet
+        net = unet.UNet(np.load(UNET_WEIGHTS)["theta"], 1, g.ny, g.nx)
+        xin = unet.network_input(G, y)[None].contiguous()
+        xo = torch.empty_like(xin)
+        net.forward(xin, out=xo)
+        t_inf = timed(lambda: net.forward(xin, out=xo), 20)
+        fl = unet_flops(g.ny, g.nx)
+        unet_line = {"ms_forward_512": round(t_inf * 1e3, 4), "gflop_per_forward": round(fl / 1e9, 2),
+                     "tflops": round(fl / t_inf / 1e12, 1), "bound": "mfma", "peak_tflops": MFMA_BF16_PEAK_TFLOPS,
+                     "frac": round(fl / t_inf / 1e12 / MFMA_BF16_PEAK_TFLOPS, 4)}
+
+    # time to 1 HU against the oracle's converged reference, when it is available (zero, FBP-like and
+    # learned starts)
     t1hu = None
     if os.path.exists(XSTAR):
         xstar = torch.as_tensor(np.load(XSTAR)["x"], device=dev)
         t1hu = {}
-        for alpha, start in ((1.999, "zero"), (1.999, "fbp"), (1.0, "zero"), (1.0, "fbp")):
+        cases = [(1.999, "zero"), (1.999, "fbp"), (1.0, "zero"), (1.0, "fbp")]
+        if net is not None:
+            cases.insert(2, (1.999, "learned"))
+        for alpha, start in cases:
             rows = solve(alpha, args.niters, xref=xstar, trace=True, start=start)
             hit = [r["iter"] for r in rows if r["rmsd_hu"] <= 1.0]
             best = min(r["rmsd_hu"] for r in rows)
@@ -304,6 +393,7 @@ def main():
         "unrelaxed_iters_per_s": round(iters_per_s_unrelaxed, 2),
         "storage_iters_per_s": storage,
         "batched": batched,
+        "unet": unet_line,
         "wall_s": round(wall, 3),
         "time_to_1hu": t1hu,
         "roofline": roofline,

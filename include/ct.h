@@ -121,7 +121,7 @@ typedef struct {
     int subset_order;    /* ct_subset_order                                                          */
     int kappa;           /* 0: kappa = 1; 1: certainty weights kappa_j = sqrt(A'w / A'1)             */
     int start;           /* 0: x holds x0 on entry; 1: zero image; 2: FBP-like image (ct_fbp);
-                            3: learned start mu_water * max(unet(A'(w y) / D_L / mu_water), 0)       */
+                            3: learned start mu_water * max(unet(FBP(y) / mu_water), 0)              */
     int init_full;       /* 0: initial gradient from the last subset (Algorithm 1 as written);
                             1: full gradient                                                         */
     double dl_scale;     /* multiplies D_L (1 = the majorizer diag{A'WA1})                            */

@@ -1,9 +1,9 @@
 /*
  * ct_unet.h -- C ABI of the learned warm start of libctrlalm: a BF16 U-Net (4 levels, 32/64/128/256
  * channels, 3x3 convolutions on the gfx950 matrix cores with FP32 accumulation) that maps the
- * normalised back-projection A'(w .* y) ./ D_L of a scan to a start image for the relaxed OS-LALM
- * solve (ct_rlalm_params.start = 3). Algorithm 1 of the paper takes any x0 in Omega and leaves the
- * start open (its experiments start from FBP); this start is an extension, not the paper's.
+ * FBP-like image of a scan (ct_fbp, in units of mu_water) to a start image for the relaxed OS-LALM
+ * solve (ct_rlalm_params.start = 3). Algorithm 1 of the paper takes any x0 in Omega and its experiments
+ * start from FBP; the network refines that FBP image (an extension, not the paper's).
  *
  * Network (canonical order of the parameters; each layer: weight [c_out][c_in][k][k] float32, then
  * bias [c_out]):
@@ -64,12 +64,11 @@ ct_status ct_unet_train_step(ct_unet *u, const float *x, const float *target, co
                              int w, float lr, double *loss, void *stream);
 
 /*
- * Network input of a scan: x_in = A'(w .* y) ./ D_L / mu_water over all views (0 where D_L = 0),
- * DEVICE float32 [ny][nx]. y, w in the geometry's storage type; dl = ct_rlalm_prepare's D_L (dl_scale 1).
- * Uses the handle's workspace (do not overlap with a solve on the same handle).
+ * Network input of a scan: x_in = FBP-like image of y (ct_fbp) / mu_water, DEVICE float32 [ny][nx]; y in
+ * the geometry's storage type. Flat detector only (CT_ERR_UNSUPPORTED otherwise). Uses the handle's
+ * workspace (do not overlap with a solve on the same handle).
  */
-ct_status ct_unet_input(ct_geom *g, const void *y, const void *w, const float *dl, double mu_water, float *x_in,
-                        void *stream);
+ct_status ct_unet_input(ct_geom *g, const void *y, double mu_water, float *x_in, void *stream);
 
 #ifdef __cplusplus
 }

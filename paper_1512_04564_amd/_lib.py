@@ -100,7 +100,7 @@ def load() -> ctypes.CDLL:
     L.ct_unet_forward.argtypes = [vp, vp, vp, i, i, i, vp]
     L.ct_unet_gradient.argtypes = [vp, vp, vp, u8p, i, i, i, dp, vp, vp]
     L.ct_unet_train_step.argtypes = [vp, vp, vp, u8p, i, i, i, ctypes.c_float, dp, vp]
-    L.ct_unet_input.argtypes = [vp, vp, vp, vp, ctypes.c_double, vp, vp]
+    L.ct_unet_input.argtypes = [vp, vp, ctypes.c_double, vp, vp]
     for name in EXPORTS:
         if name not in ("ct_geom_destroy", "ct_rlalm_params_default", "ct_last_error", "ct_unet_destroy",
                         "ct_unet_num_params"):

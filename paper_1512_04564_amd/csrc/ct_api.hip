@@ -838,7 +838,10 @@ ct_status ct_rlalm_solve(ct_geom *g, const ct_rlalm_params *p, const void *y, co
         CT_HIP_CHECK(launch_fbp(g, y, g->desc.storage, W.r, g->cs, x, s));
     }
     CT_TRY(do_prepare(g, p, w, W.dl, p->kappa ? W.kappa : nullptr, s));
-    if (p->start == 3) CT_TRY(learned_start(g, p->unet, y, w, W.dl, p->dl_scale, p->mu_water, x, W.xa, W.xb, s));
+    if (p->start == 3) {
+        if (g->desc.det != CT_DET_FLAT) return fail(CT_ERR_UNSUPPORTED, "the learned start supports the flat detector only");
+        CT_TRY(learned_start(g, p->unet, y, p->mu_water, x, W.xa, W.xb, s));
+    }
     Ctx c = make_ctx(g, p, y, w, W.dl, W.kappa, W.gv, W.h);
     CT_TRY(do_init(c, x, p->start == 1, s));
     int fin = -1;
@@ -869,8 +872,8 @@ ct_status ct_rlalm_solve_batched(ct_geom *const *gs, int n, const ct_rlalm_param
         if (gs[i]->desc.nsubsets != gs[0]->desc.nsubsets || gs[i]->desc.storage != gs[0]->desc.storage)
             return fail(CT_ERR_INVALID_ARG, "all slices must share nsubsets and storage");
         if (gs[i]->device != gs[0]->device) return fail(CT_ERR_INVALID_ARG, "all slices must be on one device");
-        if (p->start == 2 && gs[i]->desc.det != CT_DET_FLAT)
-            return fail(CT_ERR_UNSUPPORTED, "the FBP-like start supports the flat detector only");
+        if ((p->start == 2 || p->start == 3) && gs[i]->desc.det != CT_DET_FLAT)
+            return fail(CT_ERR_UNSUPPORTED, "the FBP-like and learned starts support the flat detector only");
         for (int j = 0; j < i; ++j)
             if (gs[j] == gs[i]) return fail(CT_ERR_INVALID_ARG, "each slice needs its own handle");
     }
@@ -888,8 +891,7 @@ ct_status ct_rlalm_solve_batched(ct_geom *const *gs, int n, const ct_rlalm_param
         if (i == 0) CT_TRY(upload_rho(g, p, nsub + 2, s));
         if (p->start == 2) CT_HIP_CHECK(launch_fbp(g, y[i], g->desc.storage, W.r, g->cs, x[i], s));
         CT_TRY(do_prepare(g, p, w[i], W.dl, p->kappa ? W.kappa : nullptr, s));
-        if (p->start == 3)
-            CT_TRY(learned_start(g, p->unet, y[i], w[i], W.dl, p->dl_scale, p->mu_water, x[i], W.xa, W.xb, s));
+        if (p->start == 3) CT_TRY(learned_start(g, p->unet, y[i], p->mu_water, x[i], W.xa, W.xb, s));
         cs.push_back(make_ctx(g, p, y[i], w[i], W.dl, W.kappa, W.gv, W.h));
     }
     // every slice reads the rho table and subiteration counter of slice 0

@@ -216,10 +216,10 @@ hipError_t launch_kappa(const float *bw, const float *b1, float *kappa, size_t n
 hipError_t launch_to_float(const void *src, int ctype, float *dst, size_t n, hipStream_t s);
 hipError_t launch_add_counter(int *c, int add, hipStream_t s);
 hipError_t launch_set_counter(int *c, int value, hipStream_t s);
-// Learned start (ct_unet.hip): x = mu_water * max(network(factor-normalised A'(w y) / dl), 0).
-ct_status unet_input(ct_geom *g, const void *y, const void *w, const float *dl, double factor, float *x_in, hipStream_t s);
-ct_status learned_start(ct_geom *g, const ct_unet *u, const void *y, const void *w, const float *dl, double dl_scale,
-                        double mu_water, float *x, float *a, float *b, hipStream_t s);
+// Learned start (ct_unet.hip): x = mu_water * max(network(FBP(y) / mu_water), 0).
+ct_status unet_input(ct_geom *g, const void *y, double factor, float *x_in, hipStream_t s);
+ct_status learned_start(ct_geom *g, const ct_unet *u, const void *y, double mu_water, float *x, float *a, float *b,
+                        hipStream_t s);
 // FP64 reduction: out[0] += sum over masked pixels of (x - ref)^2, out[1] += count, out[2] += nonfinite count
 hipError_t launch_trace_reduce(const float *x, const float *ref, const float *gv, const float *h, int nx, int ny,
                                float dx, float dy, float radius, double *out, hipStream_t s);

@@ -1,5 +1,7 @@
 // Learned warm start: a BF16 U-Net on the gfx950 matrix cores (include/ct_unet.h).
 //
+// The network maps the FBP-like image of a scan (units of mu_water) to a start image for the solve.
+//
 // Layout. Activations and their gradients are bfloat16 NHWC ([n][h][w][c], channels fastest); sums are
 // float32. 3x3 convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16 (D[16 x 16] += A[16 x 32] *
 // B[32 x 16]; lane l holds A[l%16][8(l/16) .. +7], B[8(l/16) .. +7][l%16] and D[4(l/16) + j][l%16]):
@@ -460,19 +462,10 @@ __global__ void k_pack(const float *__restrict__ th, int cout, int cin, bf16 *__
     wb[((size_t)ci * 9 + (8 - tap)) * cout + co] = v;
 }
 
-// y * w into a float32 sinogram (storage-typed inputs)
-template <typename T>
-__global__ void k_wy(const T *__restrict__ y, const T *__restrict__ w, float *__restrict__ out, size_t n)
+__global__ void k_scale_copy(const float *__restrict__ in, float a, float *__restrict__ out, size_t n)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = (float)y[i] * (float)w[i];
-}
-
-__global__ void k_normalise(const float *__restrict__ bp, const float *__restrict__ dl, float inv_mu, float *__restrict__ x,
-                            size_t n)
-{
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) x[i] = dl[i] > 0.f ? bp[i] / dl[i] * inv_mu : 0.f;
+    if (i < n) out[i] = a * in[i];
 }
 
 __global__ void k_start(const float *__restrict__ o, float mu, float *__restrict__ x, size_t n)
@@ -1007,54 +1000,37 @@ ct_status ct_unet_train_step(ct_unet *u, const float *x, const float *target, co
     return CT_OK;
 }
 
-ct_status ct_unet_input(ct_geom *g, const void *y, const void *w, const float *dl, double mu_water, float *x_in,
-                        void *stream)
+ct_status ct_unet_input(ct_geom *g, const void *y, double mu_water, float *x_in, void *stream)
 {
-    if (!g || !y || !w || !dl || !x_in) return fail(CT_ERR_INVALID_ARG, "NULL argument");
+    if (!g || !y || !x_in) return fail(CT_ERR_INVALID_ARG, "NULL argument");
     if (!(mu_water > 0)) return fail(CT_ERR_INVALID_ARG, "mu_water must be > 0");
-    return unet_input(g, y, w, dl, 1.0 / mu_water, x_in, as_s(stream));
+    if (g->desc.det != CT_DET_FLAT) return fail(CT_ERR_UNSUPPORTED, "the network input needs the flat-detector FBP");
+    return unet_input(g, y, 1.0 / mu_water, x_in, as_s(stream));
 }
 
 }  // extern "C"
 
 namespace ct {
 
-// x_in = factor * A'(w y) / dl (0 where dl = 0)
-ct_status unet_input(ct_geom *g, const void *y, const void *w, const float *dl, double factor, float *x_in, hipStream_t s)
+// x_in = factor * FBP-like image of y (flat detector)
+ct_status unet_input(ct_geom *g, const void *y, double factor, float *x_in, hipStream_t s)
 {
     CT_TRY(ensure_workspace(g, g->desc.nviews, 4));
     Workspace &W = g->ws;
-    const size_t ns = (size_t)g->desc.nviews * g->desc.nb;
-    const int dt = g->desc.storage;
-    if (dt == CT_F32)
-        hipLaunchKernelGGL(k_wy<float>, dim3(blocks(ns, 256)), dim3(256), 0, s, (const float *)y, (const float *)w, W.r, ns);
-    else if (dt == CT_F16)
-        hipLaunchKernelGGL(k_wy<_Float16>, dim3(blocks(ns, 256)), dim3(256), 0, s, (const _Float16 *)y, (const _Float16 *)w,
-                           W.r, ns);
-    else
-        hipLaunchKernelGGL(k_wy<__bf16>, dim3(blocks(ns, 256)), dim3(256), 0, s, (const __bf16 *)y, (const __bf16 *)w, W.r,
-                           ns);
-    CT_HIP_CHECK(hipGetLastError());
-    BpLaunch a;
-    a.G = g->dev;
-    a.r = W.r;
-    a.vstart = 0;
-    a.vstride = 1;
-    a.nv = g->desc.nviews;
-    a.out_back = W.tmp;
-    CT_HIP_CHECK(launch_back_update(a, BP_BACK, CT_F32, CT_F32, s));
-    hipLaunchKernelGGL(k_normalise, dim3(blocks(W.npix, 256)), dim3(256), 0, s, W.tmp, dl, (float)factor, x_in, W.npix);
+    CT_HIP_CHECK(launch_fbp(g, y, g->desc.storage, W.r, g->cs, W.tmp, s));
+    hipLaunchKernelGGL(k_scale_copy, dim3(blocks(W.npix, 256)), dim3(256), 0, s, W.tmp, (float)factor, x_in, W.npix);
     CT_HIP_CHECK(hipGetLastError());
     return CT_OK;
 }
 
-// Learned start of a solve: x = mu_water * max(network(A'(w y) / (D_L / dl_scale) / mu_water), 0), with dl
-// the solve's (scaled) majorizer. a and b: two [ny][nx] float32 scratch images.
-ct_status learned_start(ct_geom *g, const ct_unet *uc, const void *y, const void *w, const float *dl, double dl_scale,
-                        double mu_water, float *x, float *a, float *b, hipStream_t s)
+// Learned start of a solve: x = mu_water * max(network(FBP(y) / mu_water), 0). a and b: two [ny][nx]
+// float32 scratch images.
+ct_status learned_start(ct_geom *g, const ct_unet *uc, const void *y, double mu_water, float *x, float *a, float *b,
+                        hipStream_t s)
 {
     ct_unet *u = const_cast<ct_unet *>(uc);
-    CT_TRY(unet_input(g, y, w, dl, dl_scale / mu_water, a, s));
+    if (g->desc.det != CT_DET_FLAT) return fail(CT_ERR_UNSUPPORTED, "the learned start needs the flat-detector FBP");
+    CT_TRY(unet_input(g, y, 1.0 / mu_water, a, s));
     CT_TRY(ct_unet_forward(u, a, b, 1, g->desc.ny, g->desc.nx, s));
     hipLaunchKernelGGL(k_start, dim3(blocks(g->ws.npix, 256)), dim3(256), 0, s, b, (float)mu_water, x, g->ws.npix);
     CT_HIP_CHECK(hipGetLastError());

@@ -1,0 +1,133 @@
+"""Train the learned warm start on the GPU and save its parameters.
+
+Training data: seeded synthetic 512^2 scans (the benchmark geometry and noise model, seeds from 10000 on,
+disjoint from every evaluation seed). Network input: the FBP-like image in units of mu_water
+(ct_unet_input).
+Target: the relaxed OS-LALM image after `--target-iters` iterations from the FBP-like start (bit-reversed
+subset order, alpha 1.999), computed by the library on the GPU. Loss: mean squared error in HU over the
+field-of-view disk; Adam with a cosine learning-rate decay.
+
+Scans are generated in worker processes before the GPU is initialised. Progress is printed as it goes.
+
+Usage: python -m paper_1512_04564_amd.train_unet [--n-train 256] [--epochs 24] [--out PATH]
+"""
+from __future__ import annotations
+
+import argparse
+import math
+import multiprocessing as mp
+import os
+import time
+
+import numpy as np
+
+from . import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_OUT = os.path.join(HERE, "weights", "unet_512.npz")
+TRAIN_SEED0 = 10000
+
+
+def _scan(seed):
+    s = synth.noisy_scan(synth.CFG2, seed, truth=False)
+    return s.y, s.w
+
+
+def bf16_round(a: np.ndarray) -> np.ndarray:
+    """Round float32 values to the nearest bfloat16 (ties to even), kept as float32."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+def save(path, theta, meta):
+    """Parameters of the 3x3 layers (which the network reads in bfloat16) are stored bfloat16-rounded."""
+    th = np.array(theta, dtype=np.float32)
+    o = 0
+    for i, (ci, co, k) in enumerate(synth.UNET_SHAPES):
+        nw = co * ci * k * k
+        if 0 < i < len(synth.UNET_SHAPES) - 1:
+            th[o:o + nw] = bf16_round(th[o:o + nw])
+        o += nw + co
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    np.savez_compressed(path, theta=th, **{k: np.asarray(v) for k, v in meta.items()})
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n-train", type=int, default=256)
+    ap.add_argument("--target-iters", type=int, default=100)
+    ap.add_argument("--epochs", type=int, default=24)
+    ap.add_argument("--batch", type=int, default=4)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--workers", type=int, default=16)
+    ap.add_argument("--init-seed", type=int, default=1)
+    ap.add_argument("--out", default=DEFAULT_OUT)
+    args = ap.parse_args()
+
+    t0 = time.time()
+    seeds = list(range(TRAIN_SEED0, TRAIN_SEED0 + args.n_train))
+    with mp.get_context("fork").Pool(args.workers) as pool:
+        scans = []
+        for i, r in enumerate(pool.imap(_scan, seeds, chunksize=4)):
+            scans.append(r)
+            if (i + 1) % 32 == 0:
+                print(f"scans {i + 1}/{len(seeds)} ({time.time() - t0:.0f} s)", flush=True)
+
+    import torch
+    from . import api, unet
+
+    g = synth.CFG2
+    dev = torch.device("cuda:0")
+    G = api.Geometry(g)
+    mu = synth.MU_WATER
+    X = torch.empty((args.n_train, g.ny, g.nx), device=dev)
+    T = torch.empty_like(X)
+    p = api.Params(alpha=1.999, niters=args.target_iters, subset_order="bitrev", start="fbp")
+    for i, (y, w) in enumerate(scans):
+        yd, wd = torch.as_tensor(y, device=dev), torch.as_tensor(w, device=dev)
+        unet.network_input(G, yd, mu, out=X[i])
+        x = torch.empty((g.ny, g.nx), device=dev)
+        api.rlalm_solve(G, p, yd, wd, x)
+        T[i] = x / mu
+        if (i + 1) % 32 == 0:
+            torch.cuda.synchronize()
+            print(f"targets {i + 1}/{args.n_train} ({time.time() - t0:.0f} s)", flush=True)
+    del scans
+    yy, xx = np.mgrid[:g.ny, :g.nx]
+    r = np.hypot((xx - (g.nx - 1) / 2) * g.dx, (yy - (g.ny - 1) / 2) * g.dy)
+    mask = torch.as_tensor((r <= synth.fov_radius(g)).astype(np.uint8), device=dev)
+    mb = mask.bool()
+    base = float(((X - T)[:, mb] * 1000.0).pow(2).mean())
+    print(f"input vs target: RMS {math.sqrt(base):.2f} HU over the field of view", flush=True)
+
+    net = unet.UNet(synth.unet_params(args.init_seed), args.batch, g.ny, g.nx)
+    steps_per_epoch = args.n_train // args.batch
+    total = steps_per_epoch * args.epochs
+    rng = np.random.Generator(np.random.PCG64(12345))
+    step = 0
+    history = []
+    for ep in range(args.epochs):
+        perm = rng.permutation(args.n_train)
+        losses = []
+        for b in range(steps_per_epoch):
+            idx = torch.as_tensor(perm[b * args.batch:(b + 1) * args.batch], device=dev)
+            lr = 0.5 * args.lr * (1.0 + math.cos(math.pi * step / total))
+            want = b == steps_per_epoch - 1 or b % 16 == 0
+            loss = net.train_step(X[idx].contiguous(), T[idx].contiguous(), mask, max(lr, 1e-6), want_loss=want)
+            if want:
+                losses.append(loss)
+            step += 1
+        history.append(float(np.mean(losses)))
+        print(f"epoch {ep + 1}/{args.epochs}: loss {history[-1]:.1f} HU^2 (RMS {math.sqrt(history[-1]):.2f} HU), "
+              f"{time.time() - t0:.0f} s", flush=True)
+    theta = net.params()
+    meta = dict(n_train=args.n_train, seeds_from=TRAIN_SEED0, target_iters=args.target_iters, epochs=args.epochs,
+                batch=args.batch, lr=args.lr, loss_history=np.array(history), input_rms_hu=math.sqrt(base),
+                seconds=time.time() - t0)
+    save(args.out, theta, meta)
+    print(f"saved {args.out} ({time.time() - t0:.0f} s)", flush=True)
+
+
+if __name__ == "__main__":
+    main()

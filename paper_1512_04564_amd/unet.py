@@ -1,5 +1,7 @@
 """Python front end of the learned warm start (include/ct_unet.h): argument marshalling only.
 
+The network refines the FBP-like image of a scan (units of mu_water) into a start image for the solve.
+
 Images are float32 CUDA tensors ``[n][h][w]`` (h, w multiples of 8) in units of mu_water; masks are
 uint8 CUDA tensors ``[h][w]``; parameters cross as host float32 arrays in the canonical order.
 """
@@ -92,12 +94,11 @@ class UNet:
         return loss.value if want_loss else None
 
 
-def network_input(g, y: torch.Tensor, w: torch.Tensor, dl: torch.Tensor, mu_water: float = 0.02,
-                  out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-    """A'(w y) / D_L / mu_water for the scan (y, w) on geometry ``g`` (api.Geometry)."""
+def network_input(g, y: torch.Tensor, mu_water: float = 0.02, out: torch.Tensor | None = None,
+                  stream=None) -> torch.Tensor:
+    """FBP-like image of the sinogram y on geometry ``g`` (api.Geometry), in units of mu_water."""
     if out is None:
         out = torch.empty((g.ny, g.nx), dtype=torch.float32, device=y.device)
-    check(g._lib.ct_unet_input(g.handle, _dev(y, "y", g.sino_dtype, 2), _dev(w, "w", g.sino_dtype, 2),
-                               _dev(dl, "dl", torch.float32, 2), ctypes.c_double(mu_water),
+    check(g._lib.ct_unet_input(g.handle, _dev(y, "y", g.sino_dtype, 2), ctypes.c_double(mu_water),
                                _dev(out, "out", torch.float32, 2), _stream(stream)))
     return out
