@@ -349,25 +349,46 @@ def main():
                      "tflops": round(fl / t_inf / 1e12, 1), "bound": "mfma", "peak_tflops": MFMA_BF16_PEAK_TFLOPS,
                      "frac": round(fl / t_inf / 1e12 / MFMA_BF16_PEAK_TFLOPS, 4)}
 
-    # time to 1 HU against the oracle's converged reference, when it is available (zero, FBP-like and
-    # learned starts)
+    # time to 1 HU against the oracle's converged reference x*, when it is available. Wall time of a whole
+    # solve (D_L, start image, initialisation, K iterations) for the first K whose iterate is within 1 HU
+    # RMS of x* over the field of view. Relaxed OS-LALM with 41 subsets of 24 views diverges on this
+    # workload at alpha 1.999 (the oracle does too), so the starts are compared with 12 subsets (82 views
+    # each), the paper's subset count for the relaxed method; the 41-subset runs are reported as measured.
+    g12 = g.replace(nsubsets=12)
+    G12 = api.Geometry(g12)
+
+    def solve12(alpha, niters, xref=None, trace=False, start="zero"):
+        p = api.Params(alpha=alpha, niters=niters, subset_order=ORDER, start=start, fov_radius=synth.fov_radius(g),
+                       unet=net if start == "learned" else None)
+        return api.rlalm_solve(G12, p, y, w, x, x_ref=xref, trace=trace)
+
+    solve12(1.999, 10)
+    iters_per_s_12 = 20 / timed(lambda: solve12(1.999, 20), 2)
     t1hu = None
     if os.path.exists(XSTAR):
         xstar = torch.as_tensor(np.load(XSTAR)["x"], device=dev)
         t1hu = {}
-        cases = [(1.999, "zero"), (1.999, "fbp"), (1.0, "zero"), (1.0, "fbp")]
+        cases = [(12, 1.999, "zero"), (12, 1.999, "fbp"), (12, 1.0, "zero"), (12, 1.0, "fbp"),
+                 (41, 1.999, "fbp"), (41, 1.0, "fbp")]
         if net is not None:
-            cases.insert(2, (1.999, "learned"))
-        for alpha, start in cases:
-            rows = solve(alpha, args.niters, xref=xstar, trace=True, start=start)
+            cases.insert(2, (12, 1.999, "learned"))
+            cases.insert(5, (12, 1.0, "learned"))
+        for M_, alpha, start in cases:
+            fn = solve12 if M_ == 12 else solve
+            try:
+                rows = fn(alpha, args.niters, xref=xstar, trace=True, start=start)
+            except api.CtError as e:   # a diverged solve ends non-finite
+                t1hu[f"subsets={M_},alpha={alpha},start={start}"] = {"error": str(e)[:80]}
+                continue
             hit = [r["iter"] for r in rows if r["rmsd_hu"] <= 1.0]
             best = min(r["rmsd_hu"] for r in rows)
             entry = {"iters": hit[0] if hit else None, "best_rmsd_hu": round(best, 3),
-                     "rmsd_hu_at": {str(r["iter"]): round(r["rmsd_hu"], 2) for r in rows if r["iter"] in (1, 5, 10, 20, 50, 100)}}
+                     "rmsd_hu_at": {str(r["iter"]): round(r["rmsd_hu"], 2) for r in rows
+                                    if r["iter"] in (1, 2, 5, 10, 20, 50, 100)}}
             if hit:
-                solve(alpha, hit[0], start=start)
-                entry["seconds"] = round(timed(lambda: solve(alpha, hit[0], start=start), 3), 5)
-            t1hu[f"alpha={alpha},start={start}"] = entry
+                fn(alpha, hit[0], start=start)
+                entry["seconds"] = round(timed(lambda: fn(alpha, hit[0], start=start), 3), 5)
+            t1hu[f"subsets={M_},alpha={alpha},start={start}"] = entry
 
     cpu = None
     if not args.no_cpu:
@@ -391,6 +412,7 @@ def main():
                                "solve, seed 100",
                    "iters_per_step": args.niters, "subsets": M, "alpha": 1.999, "subset_order": ORDER},
         "unrelaxed_iters_per_s": round(iters_per_s_unrelaxed, 2),
+        "iters_per_s_12_subsets": round(iters_per_s_12, 2),
         "storage_iters_per_s": storage,
         "batched": batched,
         "unet": unet_line,
