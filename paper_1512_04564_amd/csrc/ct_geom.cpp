@@ -9,7 +9,10 @@
 // (pixel units), theta_k being the angle between the ray through the bin centre and the line normal.
 //
 // The kernels evaluate U_k(l) = fmaf(lc, B_k, A_k) from the FP32 (A_k, B_k) stored here, in the forward
-// and in the back-projector alike, so both see bit-identical boundaries.
+// and in the back-projector alike, so both see bit-identical boundaries. Along every line of a view the
+// boundaries are ordered the same way (the image lies between source and detector, so the boundary rays
+// cross each line in their own order); sgn[v] = +1 when U_k increases with k, -1 otherwise, lets the
+// back-projector work with increasing boundaries s U_k (a sign flip, exact).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -63,6 +66,7 @@ ct_status build_geometry(ct_geom *g)
     std::vector<float> scale((size_t)nv * nb);
     std::vector<float4> inv(nv);
     std::vector<double2> cs(nv);
+    std::vector<float> sgn(nv);
     g->rowsweep.assign(nv, 0);
     for (int v = 0; v < nv; ++v) {
         View64 o = view64(d, v);
@@ -84,6 +88,24 @@ ct_status build_geometry(ct_geom *g)
             }
             bnd[(size_t)v * (nb + 1) + k] = make_float2((float)A, (float)B);
         }
+        // boundary order of the view, and every footprint positive in the kernels' FP32 evaluation at the
+        // first and last line (U_k is affine in the line coordinate, so the extremes bound the rest)
+        {
+            const float2 *b = &bnd[(size_t)v * (nb + 1)];
+            const int NL = o.row ? d.ny : d.nx;
+            const float s = b[1].x > b[0].x ? 1.f : -1.f;   // order at the central line (lc = 0)
+            sgn[v] = s;
+            for (int side = 0; side < 2; ++side) {
+                const float lc = (side ? 0.5f : -0.5f) * (float)(NL - 1);
+                float up = std::fmaf(lc, b[0].y, b[0].x);
+                for (int k = 1; k <= nb; ++k) {
+                    const float un = std::fmaf(lc, b[k].y, b[k].x);
+                    if (!(s * (un - up) > 1e-6f))
+                        return fail(CT_ERR_UNSUPPORTED, "detector bins too narrow for the projector's FP32 boundary table");
+                    up = un;
+                }
+            }
+        }
         for (int k = 0; k < nb; ++k) {
             double u = ((double)k + 0.5 - 0.5 * nb + d.u_offset) * d.du;
             double cx, cy;
@@ -103,6 +125,8 @@ ct_status build_geometry(ct_geom *g)
     CT_HIP_CHECK(hipMalloc(&g->inv, inv.size() * sizeof(float4)));
     CT_HIP_CHECK(hipMalloc(&g->d_rowsweep, nv * sizeof(int)));
     CT_HIP_CHECK(hipMalloc(&g->cs, nv * sizeof(double2)));
+    CT_HIP_CHECK(hipMalloc(&g->sgn, nv * sizeof(float)));
+    CT_HIP_CHECK(hipMemcpy(g->sgn, sgn.data(), nv * sizeof(float), hipMemcpyHostToDevice));
     CT_HIP_CHECK(hipMemcpy(g->cs, cs.data(), nv * sizeof(double2), hipMemcpyHostToDevice));
     CT_HIP_CHECK(hipMemcpy(g->bnd, bnd.data(), bnd.size() * sizeof(float2), hipMemcpyHostToDevice));
     CT_HIP_CHECK(hipMemcpy(g->scale, scale.data(), scale.size() * sizeof(float), hipMemcpyHostToDevice));
@@ -121,6 +145,7 @@ ct_status build_geometry(ct_geom *g)
     G.scale = g->scale;
     G.inv = g->inv;
     G.rowsweep = g->d_rowsweep;
+    G.sgn = g->sgn;
     return CT_OK;
 }
 
@@ -131,7 +156,9 @@ void free_geometry(ct_geom *g)
     if (g->inv) (void)hipFree(g->inv);
     if (g->d_rowsweep) (void)hipFree(g->d_rowsweep);
     if (g->cs) (void)hipFree(g->cs);
+    if (g->sgn) (void)hipFree(g->sgn);
     g->cs = nullptr;
+    g->sgn = nullptr;
     g->bnd = nullptr;
     g->scale = nullptr;
     g->inv = nullptr;

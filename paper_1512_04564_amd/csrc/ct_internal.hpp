@@ -40,6 +40,7 @@ ct_status fail(ct_status st, const std::string &msg);
 //       the view's own pixel units, is u = dsd * (e na + lc nl) / (e da + lc dl + dso);
 //       bin index kf = u / du + nb/2 - u_offset (arc: atan of the same ratio).
 //   rowsweep[v] = 1 for row-sweep views.
+//   sgn[v] = +1 if U_k increases with k along the lines of view v, -1 if it decreases.
 constexpr int kBpTile = 16;   // back-projection tile edge (pixels)
 
 struct GeomDev {
@@ -52,6 +53,7 @@ struct GeomDev {
     const float *scale;
     const float4 *inv;
     const int *rowsweep;
+    const float *sgn;
 };
 
 struct Workspace {
@@ -97,6 +99,7 @@ struct ct_geom {
     float4 *inv = nullptr;
     int *d_rowsweep = nullptr;
     double2 *cs = nullptr;  // per view (cos beta, sin beta) in FP64, for the FBP-like start
+    float *sgn = nullptr;   // per view boundary order (+1 increasing, -1 decreasing)
     ct::GeomDev dev{};
     ct::Workspace ws;
     ct::GraphCache graphs;
@@ -121,7 +124,8 @@ enum FpEpilogue { FP_PLAIN = 0, FP_RESIDUAL = 1, FP_WEIGHTED = 2 };
 
 // One forward projection: views v = vstart + vi * vstride, vi in [0, nv), of the image img (row-sweep
 // views) / its transpose imgT (column-sweep views). Epilogues: PLAIN out = A x (float32); RESIDUAL
-// out = mscale * w (A x - y) (storage type); WEIGHTED out = w * A 1 (float32, ones image).
+// out = mscale * w (A x - y) * scale (storage type; multiplied by the bin scale for the back-projector's
+// solver modes); WEIGHTED out = w * A 1 (float32, ones image).
 struct FpLaunch {
     GeomDev G;
     const void *img = nullptr, *imgT = nullptr;
@@ -154,7 +158,8 @@ struct UpdateArgs {
 };
 
 // One back-projection (BP_BACK: out_back = A' r, r float32 or storage type) or fused back-projection
-// and relaxed update (the other modes) over views vstart + vi * vstride, vi in [0, nv).
+// and relaxed update (the other modes, whose r is the RESIDUAL epilogue's, already multiplied by the bin
+// scale) over views vstart + vi * vstride, vi in [0, nv).
 struct BpLaunch {
     GeomDev G;
     const void *r = nullptr;

@@ -39,7 +39,6 @@ constexpr int FP_WAVES = 16;         // waves per forward workgroup (single laun
 constexpr int FP_WIN = 128;          // LDS pixel window of one wave (floats)
 constexpr int FP_PF = FP_WIN / 64;   // prefetch registers per lane
 constexpr int BP_TX = kBpTile, BP_TY = kBpTile;
-constexpr int BP_WIN = 128;          // staged bins per view and tile in the back-projector
 
 __device__ __forceinline__ float rcp_approx(float v) { return __builtin_amdgcn_rcpf(v); }
 
@@ -71,7 +70,7 @@ __device__ __forceinline__ void fp_body(const FpLaunch &a, const int bx, const i
     constexpr int PADW = FP_WIN + 4;
     const int v = vstart + vi * vstride;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform: line loop in SGPRs
     const int nb = G.nb;
     const int kblk = bx * FP_BINS;
     const int k = kblk + lane;
@@ -185,11 +184,13 @@ __device__ __forceinline__ void fp_body(const FpLaunch &a, const int bx, const i
         float p = 0.f;
 #pragma unroll
         for (int ww = 0; ww < WAVES; ++ww) p += red[ww * 64 + lane];
-        p *= G.scale[(size_t)v * nb + k];
+        const float sc = G.scale[(size_t)v * nb + k];
+        p *= sc;
         const size_t o = (size_t)vi * nb + k;
         const size_t si = (size_t)v * nb + k;
         if (EPI == FP_PLAIN) st<TO>(a.out, o, p);
-        else if (EPI == FP_RESIDUAL) st<TO>(a.out, o, a.mscale * ld<TY>(a.w, si) * (p - ld<TY>(a.y, si)));
+        // the residual is stored multiplied by the bin scale, the factor the back-projector applies to it
+        else if (EPI == FP_RESIDUAL) st<TO>(a.out, o, (a.mscale * ld<TY>(a.w, si) * (p - ld<TY>(a.y, si))) * sc);
         else st<TO>(a.out, o, ld<TY>(a.w, si) * p);
     }
 }
@@ -281,6 +282,50 @@ __device__ __forceinline__ float bp_view(const GeomDev &G, const float4 im, floa
     return zeta;
 }
 
+// The same back-projection from a view staged in LDS with sign-flipped boundaries: sab[k - kw0] holds
+// s (A_k, B_k) for k in [kw0, kw1 + 3] (entries past the detector continue one pixel apart) and
+// srs[k - kw0] the residual of bin k times its scale for k in [kw0, kw1 + 2] (zero past kw1), s = +1 or
+// -1 the view's boundary order. The signed boundaries s U_k increase with k, so bin k covers
+// [s U_k, s U_k+1] and the pixel [s e0, s e1] (ordered); every quantity is the exact negation of the
+// unsigned one, so the weights are those of the forward projector. Taps past kb read staged entries
+// with zero residual or zero overlap, so no index needs clamping.
+__device__ __forceinline__ float bp_view_staged(const GeomDev &G, const float4 im, float lc, float e0, float s,
+                                                int kw0, int kw1, const float2 *__restrict__ sab,
+                                                const float *__restrict__ srs)
+{
+    const float nlc = lc * im.y;
+    const float dlc = fmaf(lc, im.w, G.dso);
+    const float num0 = fmaf(e0, im.x, nlc), den0 = fmaf(e0, im.z, dlc);
+    const float num1 = num0 + im.x, den1 = den0 + im.z;
+    float t0 = num0 * rcp_approx(den0), t1 = num1 * rcp_approx(den1);
+    if (G.arc) {
+        t0 = atanf(t0);
+        t1 = atanf(t1);
+    }
+    const float kf0 = fmaf(G.c_kf, t0, G.k0), kf1 = fmaf(G.c_kf, t1, G.k0);
+    const int ka = max((int)floorf(fminf(kf0, kf1) - 0.05f), kw0);
+    const int kb = min((int)floorf(fmaxf(kf0, kf1) + 0.05f), kw1);
+    if (ka > kb) return 0.f;
+    const float lo_e = s > 0.f ? e0 : -(e0 + 1.f);   // the pixel in signed coordinates
+    const float hi_e = lo_e + 1.f;
+    const float2 *b = sab + (ka - kw0);
+    const float *r = srs + (ka - kw0);
+    const float u0 = fmaf(lc, b[0].y, b[0].x), u1 = fmaf(lc, b[1].y, b[1].x);
+    const float u2 = fmaf(lc, b[2].y, b[2].x), u3 = fmaf(lc, b[3].y, b[3].x);
+    auto tap = [&](float lo, float hi, float rk) {
+        const float ov = fmaxf(fminf(hi, hi_e) - fmaxf(lo, lo_e), 0.f);
+        return rk * (ov * rcp_approx(hi - lo));
+    };
+    float zeta = tap(u0, u1, r[0]) + tap(u1, u2, r[1]) + tap(u2, u3, r[2]);
+    float up = u3;
+    for (int k = 3; k <= kb - ka; ++k) {   // pixels that meet more than three bins
+        const float un = fmaf(lc, b[k + 1].y, b[k + 1].x);
+        zeta += tap(up, un, r[k]);
+        up = un;
+    }
+    return zeta;
+}
+
 __device__ __forceinline__ void pot_terms(int potential, float delta, float t, float &dphi, float &omega)
 {
     const float z = t / delta;
@@ -321,42 +366,41 @@ __device__ __forceinline__ int2 tile_window(const GeomDev &G, int v, int i0, int
 
 // Fused back-projection and relaxed update over one 16 x 16 pixel tile. The workgroup has two halves of
 // 256 threads (one thread per pixel each); half h back-projects the views vi = h, h + 2, ..., staging
-// for each view, in LDS, the boundary coefficients and r_k * scale_k of the bins that can meet the tile
-// (double-buffered: the next view's loads are in flight while the current one is evaluated). The
-// tile's bin windows of a chunk of views are computed up front, one view per thread. The two partial
-// sums are added in a fixed order, then half 0 carries out the update of its pixel.
+// for each view, in LDS, the signed boundary coefficients and r_k * scale_k of the bins that can meet the
+// tile (double-buffered: the next view's loads are in flight while the current one is evaluated). The
+// tile's bin windows and view descriptors of a chunk of up to 64 views are computed by every wave up
+// front, one view per lane, and read with readlane. The two partial sums are added in a fixed order,
+// then half 0 carries out the update of its pixel.
 constexpr int BP_NT = BP_TX * BP_TY;
-constexpr int BP_WCHUNK = 2 * BP_NT;   // views whose windows are computed per chunk (one per thread)
+constexpr int BP_SWIN = 125;           // bins per staged window (one view, one tile)
+constexpr int BP_SLOT = 128;           // staged entries per buffer: boundaries kw0 .. kw1 + 3
 
 struct BpShared {
     float tile_t[BP_TX][BP_TY + 1];
-    float2 s_ab[2][2][BP_WIN + 1];
-    float s_rs[2][2][BP_WIN];
+    float2 s_ab[2][2][BP_SLOT];   // per half, double-buffered: signed boundaries kw0 .. kw1 + 3
+    float s_rs[2][2][BP_SLOT];    // residual x scale of bins kw0 .. kw1 + 2 (zero past kw1)
     float s_part[BP_NT];
-    int4 s_desc[BP_WCHUNK];   // per view of the chunk: bin window k0, k1; view index; row-sweep flag
-    float4 s_im[BP_WCHUNK];   // per view of the chunk: inverse-map coefficients
 };
 
 template <int MODE, typename TR, typename TXC>
 __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const int by, BpShared &sh)
 {
-    constexpr int NT = BP_NT;
-    constexpr int WCHUNK = BP_WCHUNK;
+    // the solver's residual blocks come from the forward epilogue already multiplied by the bin scale
+    constexpr bool PRESCALED = MODE == BP_INIT || MODE == BP_FULL;
     const GeomDev &G = a.G;
     const UpdateArgs &U = a.U;
     const int vstart = a.vstart, vstride = a.vstride, nv = a.nv;
     const TR *__restrict__ r = static_cast<const TR *>(a.r);
-    const int hv = __builtin_amdgcn_readfirstlane(threadIdx.x / NT);   // view parity of this half (wave-uniform)
-    const int tid = threadIdx.x % NT;
+    // Half hv = threadIdx.x / 256 of the workgroup back-projects the views of parity hv onto the 16 x 16
+    // tile, one pixel per thread; each half stages one view at a time in its LDS slots.
+    const int hv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / BP_NT));
+    const int tid = threadIdx.x % BP_NT;
+    const int lane = threadIdx.x & 63;
     const int tx = tid % BP_TX, ty = tid / BP_TX;
     const int j = bx * BP_TX + tx, i = by * BP_TY + ty;
     const int nx = G.nx, ny = G.ny, nb = G.nb;
     auto &tile_t = sh.tile_t;
-    auto &s_ab = sh.s_ab;
-    auto &s_rs = sh.s_rs;
     auto &s_part = sh.s_part;
-    auto &s_desc = sh.s_desc;
-    auto &s_im = sh.s_im;
     const bool inside = i < ny && j < nx;
     float zeta = 0.f;
     if (MODE != BP_XSTEP) {
@@ -365,82 +409,85 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
         // pixel coordinates in both sweep orientations: row sweep lines are rows (l = i, q = j)
         const float lc_r = (float)i - 0.5f * (float)(ny - 1), e0_r = (float)j - 0.5f * (float)nx;
         const float lc_c = (float)j - 0.5f * (float)(nx - 1), e0_c = (float)i - 0.5f * (float)ny;
-        for (int c0 = 0; c0 < nv; c0 += WCHUNK) {
-            const int cn = min(WCHUNK, nv - c0);   // views c0 .. c0 + cn - 1 in this chunk
-            if ((int)threadIdx.x < cn) {
-                const int v = vstart + (c0 + threadIdx.x) * vstride;
-                const int2 w = tile_window(G, v, ti0, ti1, tj0, tj1);
-                s_desc[threadIdx.x] = make_int4(w.x, w.y, v, G.rowsweep[v]);
-                s_im[threadIdx.x] = G.inv[v];
+        float2 *sab = sh.s_ab[hv][0];
+        float *srs = sh.s_rs[hv][0];
+        for (int c0 = 0; c0 < nv; c0 += 64) {
+            const int cn = min(64, nv - c0);   // views c0 .. c0 + cn - 1 of this chunk
+            // every wave holds the descriptors of the chunk's views, view c0 + q in lane q: the tile's bin
+            // window, inverse map, boundary order and sweep mode, read with readlane in the view loop
+            int2 wq = make_int2(1, 0);
+            float4 imq = make_float4(0.f, 0.f, 0.f, 0.f);
+            float sq = 1.f;
+            int rq = 0;
+            if (lane < cn) {
+                const int v = vstart + (c0 + lane) * vstride;
+                wq = tile_window(G, v, ti0, ti1, tj0, tj1);
+                imq = G.inv[v];
+                sq = G.sgn[v];
+                rq = G.rowsweep[v];
             }
-            __syncthreads();
-            // The staging loads are only issued here; the values are combined and stored after the
-            // current view's back-projection, so the loads stay in flight meanwhile.
-            auto stage_load = [&](int ci, float2 &ab, float &rv, float &sv, int &kw0, int &kw1) {
-                kw0 = 1;
-                kw1 = 0;
+            auto rl_f = [](float x, int q) {
+                return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), q));
+            };
+            // staging of view ci (entry tid): loads issued here, stored after the current view's work
+            auto stage_load = [&](int ci, float2 &ab, float &rv, float &sv) {
+                const int kw0 = __builtin_amdgcn_readlane(wq.x, ci), kw1 = __builtin_amdgcn_readlane(wq.y, ci);
+                const int n = kw1 - kw0 + 1;
+                const unsigned v = (unsigned)(vstart + (c0 + ci) * vstride);
                 ab = make_float2(0.f, 0.f);
                 rv = 0.f;
-                sv = 0.f;
-                if (ci >= cn) return;
-                const int4 dsc = s_desc[ci];
-                kw0 = __builtin_amdgcn_readfirstlane(dsc.x);
-                kw1 = __builtin_amdgcn_readfirstlane(dsc.y);
-                const unsigned v = (unsigned)__builtin_amdgcn_readfirstlane(dsc.z);
-                const int n = kw1 - kw0 + 1;
-                if (n <= BP_WIN) {
+                sv = 1.f;
+                if (n <= BP_SWIN && n > 0) {
                     // 32-bit element offsets (the geometry keeps nviews * (nb + 1) below 2^31)
-                    const unsigned t = (unsigned)tid;
-                    if (tid <= n) ab = G.bnd[v * (unsigned)(nb + 1) + (unsigned)kw0 + t];
+                    const int k = kw0 + tid;
+                    if (tid < n + 3) {
+                        const float s = rl_f(sq, ci);
+                        const float2 b = G.bnd[v * (unsigned)(nb + 1) + (unsigned)min(k, nb)];
+                        // past the detector: continue one pixel apart (zero residual, finite footprint)
+                        ab = make_float2(k > nb ? s * b.x + (float)(k - nb) : s * b.x, s * b.y);
+                    }
                     if (tid < n) {
-                        rv = (float)r[(unsigned)(c0 + ci) * (unsigned)nb + (unsigned)kw0 + t];
-                        sv = G.scale[v * (unsigned)nb + (unsigned)kw0 + t];
+                        rv = (float)r[(unsigned)(c0 + ci) * (unsigned)nb + (unsigned)k];
+                        if (!PRESCALED) sv = G.scale[v * (unsigned)nb + (unsigned)k];
                     }
                 }
             };
-            auto stage_store = [&](int buf, int kw0, int kw1, float2 ab, float rv, float sv) {
-                const int n = kw1 - kw0 + 1;
-                if (n <= BP_WIN) {
-                    if (tid <= n) s_ab[hv][buf][tid] = ab;
-                    if (tid < n) s_rs[hv][buf][tid] = rv * sv;
+            auto stage_store = [&](int buf, float2 ab, float rv, float sv) {
+                if (tid < BP_SLOT) {
+                    sab[buf * BP_SLOT + tid] = ab;
+                    srs[buf * BP_SLOT + tid] = PRESCALED ? rv : rv * sv;   // 0 past kw1
                 }
             };
-            const int niter = (cn + 1) / 2;
-            float2 ab_n;
-            float r_n, sc_n;
-            int kw0_n, kw1_n;
-            stage_load(hv, ab_n, r_n, sc_n, kw0_n, kw1_n);
-            stage_store(0, kw0_n, kw1_n, ab_n, r_n, sc_n);
+            const int niter = (cn + 1) / 2;   // half hv takes views ci = hv + 2 it < cn
+            float2 ab_n = make_float2(0.f, 0.f);
+            float r_n = 0.f, s_n = 1.f;
+            if (hv < cn) stage_load(hv, ab_n, r_n, s_n);
+            stage_store(0, ab_n, r_n, s_n);
             __syncthreads();
             for (int it = 0; it < niter; ++it) {
+                const int ci = hv + 2 * it;
                 const int buf = it & 1;
-                const int ci = 2 * it + hv;
-                const int kw0 = kw0_n, kw1 = kw1_n;
-                if (it + 1 < niter) stage_load(ci + 2, ab_n, r_n, sc_n, kw0_n, kw1_n);
-                if (inside && ci < cn && kw0 <= kw1) {
-                    const int4 dsc = s_desc[ci];
-                    const int v = __builtin_amdgcn_readfirstlane(dsc.z);
-                    const bool row = __builtin_amdgcn_readfirstlane(dsc.w) != 0;
-                    const float lc = row ? lc_r : lc_c, e0 = row ? e0_r : e0_c;
-                    const float4 imv = s_im[ci];
-                    const float4 im = make_float4(__builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, imv.x))),
-                                                  __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, imv.y))),
-                                                  __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, imv.z))),
-                                                  __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, imv.w))));
-                    if (kw1 - kw0 + 1 <= BP_WIN) {
-                        const float2 *sab = s_ab[hv][buf] - kw0;
-                        const float *srs = s_rs[hv][buf] - kw0;
-                        zeta += bp_view(G, im, lc, e0, kw0, kw1, [&](int k) { return sab[k]; },
-                                        [&](int k) { return srs[k]; });
-                    } else {
-                        const float2 *bv = G.bnd + (size_t)v * (nb + 1);
-                        const float *sv = G.scale + (size_t)v * nb;
-                        const TR *rv = r + (size_t)(c0 + ci) * nb;
-                        zeta += bp_view(G, im, lc, e0, kw0, kw1, [&](int k) { return bv[k]; },
-                                        [&](int k) { return (float)rv[k] * sv[k]; });
+                if (ci + 2 < cn) stage_load(ci + 2, ab_n, r_n, s_n);
+                if (ci < cn) {
+                    const int kw0 = __builtin_amdgcn_readlane(wq.x, ci), kw1 = __builtin_amdgcn_readlane(wq.y, ci);
+                    if (inside && kw0 <= kw1) {
+                        const float4 im = make_float4(rl_f(imq.x, ci), rl_f(imq.y, ci), rl_f(imq.z, ci), rl_f(imq.w, ci));
+                        const bool row = __builtin_amdgcn_readlane(rq, ci) != 0;
+                        const float lc = row ? lc_r : lc_c, e0 = row ? e0_r : e0_c;
+                        if (kw1 - kw0 + 1 <= BP_SWIN) {
+                            zeta += bp_view_staged(G, im, lc, e0, rl_f(sq, ci), kw0, kw1, sab + buf * BP_SLOT,
+                                                   srs + buf * BP_SLOT);
+                        } else {   // window wider than the LDS slots: read the tables directly
+                            const int v = vstart + (c0 + ci) * vstride;
+                            const float2 *bv = G.bnd + (size_t)v * (nb + 1);
+                            const float *sv = G.scale + (size_t)v * nb;
+                            const TR *rv = r + (size_t)(c0 + ci) * nb;
+                            zeta += bp_view(G, im, lc, e0, kw0, kw1, [&](int k) { return bv[k]; },
+                                            [&](int k) { return PRESCALED ? (float)rv[k] : (float)rv[k] * sv[k]; });
+                        }
                     }
                 }
-                if (it + 1 < niter) stage_store(buf ^ 1, kw0_n, kw1_n, ab_n, r_n, sc_n);
+                if (it + 1 < niter) stage_store(buf ^ 1, ab_n, r_n, s_n);
                 __syncthreads();
             }
         }
