@@ -53,6 +53,16 @@ __device__ __forceinline__ void st(void *p, size_t i, float v)
     static_cast<T *>(p)[i] = (T)v;
 }
 
+// one element of type T through a buffer resource, byte offset off, as float
+template <typename T>
+__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t rs, unsigned off)
+{
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0));
+    else
+        return (float)__builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(rs, (int)off, 0, 0));
+}
+
 // Forward projection of the views vstart + vi * vstride (vi = blockIdx.y) for the 64 bins of block
 // blockIdx.x. Each wave streams a contiguous range of image lines: the pixels of line l+1 that the
 // block's footprint covers are loaded into registers (coalesced, clamped addresses) while line l is
@@ -103,12 +113,20 @@ __device__ __forceinline__ void fp_body(const FpLaunch &a, const int bx, const i
         wn_v = lo < hi ? we - ws_v + 1 : 0;
     };
     float pf[FP_PF];
+    // Image lines are read through a buffer resource over the whole image: one scalar descriptor, a 32-bit
+    // byte offset per lane (line base included, so the hardware range check covers every read) and reads
+    // past the image returning 0. Reads past the end of a line only feed taps of zero weight (their
+    // pixels lie beyond the clamped footprint), so no per-lane clamp is needed.
+    const __amdgpu_buffer_rsrc_t img_rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<TI *>(src), 0, (int)((size_t)NL * NQ * sizeof(TI)), 0x00020000);
+    const unsigned lane_off = (unsigned)lane * (unsigned)sizeof(TI);
     auto prefetch = [&](int l, int ws) {
         if (!ONES) {
-            // unconditional loads (clamped addresses): a fixed register set keeps the prefetch in flight
-            const TI *line = src + (size_t)l * NQ;
+            const unsigned base = ((unsigned)l * (unsigned)NQ + (unsigned)ws) * (unsigned)sizeof(TI);
 #pragma unroll
-            for (int j = 0; j < FP_PF; ++j) pf[j] = (float)line[min(ws + lane + 64 * j, NQ - 1)];
+            for (int j = 0; j < FP_PF; ++j) {
+                pf[j] = buf_ld<TI>(img_rs, lane_off + base + (unsigned)(64 * j * sizeof(TI)));
+            }
         }
     };
 
