@@ -62,8 +62,8 @@ def measured_traffic():
 def write_traffic(fetch_dir, write_dir):
     """Write the traffic record of the fused update kernel from the two counter runs of --pmc-workload
     (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, CSV output): average KiB per dispatch of the kernel, scaled
-    by the counters' reading for the workload's device copy of COPY_BYTES (the non-library dispatch that
-    writes the most), and stamped with the kernel source's hash."""
+    by the counters' reading for the workload's device copy of COPY_BYTES, and stamped with the kernel
+    source's hash."""
     import csv
     import glob
 
@@ -85,8 +85,10 @@ def write_traffic(fetch_dir, write_dir):
     wu, _ = mean_of(rw, "k_back_update<2")
     ffw, _ = mean_of(rf, "k_forward<1, false")
     wfw, _ = mean_of(rw, "k_forward<1, false")
-    cw = max((r for r in rw if not library(r)), key=lambda r: float(r["Counter_Value"]))
-    cf = max((r for r in rf if r["Kernel_Name"] == cw["Kernel_Name"]), key=lambda r: float(r["Counter_Value"]))
+    # the copy reads and writes COPY_BYTES: the non-library dispatch that fetches the most (the fill that
+    # creates its source writes as much but reads nothing), and the same kernel's write count
+    cf = max((r for r in rf if not library(r)), key=lambda r: float(r["Counter_Value"]))
+    cw = max((r for r in rw if r["Kernel_Name"] == cf["Kernel_Name"]), key=lambda r: float(r["Counter_Value"]))
     kib = COPY_BYTES / 1024.0
     ff, wf = kib / float(cf["Counter_Value"]), kib / float(cw["Counter_Value"])
     rec = {
@@ -96,7 +98,7 @@ def write_traffic(fetch_dir, write_dir):
         "fetch_kib_per_dispatch": round(fu, 1),
         "write_kib_per_dispatch": round(wu, 1),
         "dispatches_averaged": n,
-        "copy_calibration": {"bytes_copied": COPY_BYTES, "kernel": cw["Kernel_Name"][:120],
+        "copy_calibration": {"bytes_copied": COPY_BYTES, "kernel": cf["Kernel_Name"][:120],
                              "fetch_kib": float(cf["Counter_Value"]), "write_kib": float(cw["Counter_Value"]),
                              "fetch_factor": round(ff, 4), "write_factor": round(wf, 4)},
         "bytes_per_launch": int(round((fu * ff + wu * wf) * 1024)),

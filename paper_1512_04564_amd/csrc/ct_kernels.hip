@@ -372,7 +372,7 @@ __device__ __forceinline__ int2 tile_window(const GeomDev &G, int v, int i0, int
     for (int c = 0; c < 4; ++c) {
         const float e = (c & 1) ? eb : ea, lc = (c & 2) ? lb : la;
         const float num = fmaf(e, im.x, lc * im.y), den = fmaf(e, im.z, fmaf(lc, im.w, G.dso));
-        float t = num / den;
+        float t = num * rcp_approx(den);   // the window's one-bin margin absorbs the reciprocal's error
         if (G.arc) t = atanf(t);
         const float kf = fmaf(G.c_kf, t, G.k0);
         kmn = fminf(kmn, kf);
