@@ -300,16 +300,38 @@ __device__ __forceinline__ float bp_view(const GeomDev &G, const float4 im, floa
     return zeta;
 }
 
-// The same back-projection from a view staged in LDS with sign-flipped boundaries: sab[k - kw0] holds
-// s (A_k, B_k) for k in [kw0, kw1 + 3] (entries past the detector continue one pixel apart) and
-// srs[k - kw0] the residual of bin k times its scale for k in [kw0, kw1 + 2] (zero past kw1), s = +1 or
-// -1 the view's boundary order. The signed boundaries s U_k increase with k, so bin k covers
-// [s U_k, s U_k+1] and the pixel [s e0, s e1] (ordered); every quantity is the exact negation of the
-// unsigned one, so the weights are those of the forward projector. Taps past kb read staged entries
-// with zero residual or zero overlap, so no index needs clamping.
-__device__ __forceinline__ float bp_view_staged(const GeomDev &G, const float4 im, float lc, float e0, float s,
-                                                int kw0, int kw1, const float2 *__restrict__ sab,
-                                                const float *__restrict__ srs)
+// Cumulative form of the same back-projection, from a view staged in LDS. For the tile's bin window
+// kw0 .. kw1 (n bins), entry e = k - kw0 (0 <= e <= n) holds s (A_k, B_k), the signed coefficients of
+// boundary k (s = +1 or -1 the view's boundary order, so that s U_k increases with k), P_e, the sum of
+// r_j * scale_j over the window's bins before k, and r_k * scale_k (0 at e = n). With
+// F(u) = P_e + r_e (u - s U_k) / (s U_k+1 - s U_k) for u in bin k (clamped to the window), the pixel's
+// value is F(s edge_hi) - F(s edge_lo): in exact arithmetic the sum over bins of the residual times
+// overlap / footprint that the forward projector's weights define, evaluated at two points instead of
+// once per bin. The bin of each edge comes from its detector coordinate; when that estimate misses the
+// bin by a hair (FP32 error, far below one bin) the neighbouring entry is taken instead.
+// Entry of the bin of the edge at signed coordinate u (detector coordinate kf, window-relative), with
+// u's endpoints ua, ub on the line lc; returns whether the estimate missed that bin.
+struct CumBin {
+    float4 q;       // s A_k, s B_k, P_e, r_e
+    float ua, ub;   // s U_k, s U_k+1 on the pixel's line
+};
+__device__ __forceinline__ CumBin cum_bin(const float4 *__restrict__ E, int e, float lc)
+{
+    CumBin c;
+    c.q = E[e];
+    const float2 b = *reinterpret_cast<const float2 *>(E + e + 1);
+    c.ua = fmaf(lc, c.q.y, c.q.x);
+    c.ub = fmaf(lc, b.y, b.x);
+    return c;
+}
+__device__ __forceinline__ float cum_value(const CumBin &c, float u)
+{
+    return fmaf(c.q.w, __builtin_amdgcn_fmed3f((u - c.ua) * rcp_approx(c.ub - c.ua), 0.f, 1.f), c.q.z);
+}
+
+// kofs = k0 - kw0: the detector coordinate measured from the window's first bin
+__device__ __forceinline__ float bp_view_cumul(const GeomDev &G, const float4 im, float lc, float e0, bool pos, int n,
+                                               float kofs, const float4 *__restrict__ E)
 {
     const float nlc = lc * im.y;
     const float dlc = fmaf(lc, im.w, G.dso);
@@ -320,28 +342,43 @@ __device__ __forceinline__ float bp_view_staged(const GeomDev &G, const float4 i
         t0 = atanf(t0);
         t1 = atanf(t1);
     }
-    const float kf0 = fmaf(G.c_kf, t0, G.k0), kf1 = fmaf(G.c_kf, t1, G.k0);
-    const int ka = max((int)floorf(fminf(kf0, kf1) - 0.05f), kw0);
-    const int kb = min((int)floorf(fmaxf(kf0, kf1) + 0.05f), kw1);
-    if (ka > kb) return 0.f;
-    const float lo_e = s > 0.f ? e0 : -(e0 + 1.f);   // the pixel in signed coordinates
-    const float hi_e = lo_e + 1.f;
-    const float2 *b = sab + (ka - kw0);
-    const float *r = srs + (ka - kw0);
-    const float u0 = fmaf(lc, b[0].y, b[0].x), u1 = fmaf(lc, b[1].y, b[1].x);
-    const float u2 = fmaf(lc, b[2].y, b[2].x), u3 = fmaf(lc, b[3].y, b[3].x);
-    auto tap = [&](float lo, float hi, float rk) {
-        const float ov = fmaxf(fminf(hi, hi_e) - fmaxf(lo, lo_e), 0.f);
-        return rk * (ov * rcp_approx(hi - lo));
-    };
-    float zeta = tap(u0, u1, r[0]) + tap(u1, u2, r[1]) + tap(u2, u3, r[2]);
-    float up = u3;
-    for (int k = 3; k <= kb - ka; ++k) {   // pixels that meet more than three bins
-        const float un = fmaf(lc, b[k + 1].y, b[k + 1].x);
-        zeta += tap(up, un, r[k]);
-        up = un;
+    const float kf0 = fmaf(G.c_kf, t0, kofs), kf1 = fmaf(G.c_kf, t1, kofs);
+    // the pixel [e0, e0 + 1] in signed coordinates; its lower edge has the lower detector coordinate
+    const float lo = pos ? e0 : -(e0 + 1.f), hi = lo + 1.f;
+    int ea = min(max((int)floorf(fminf(kf0, kf1)), 0), n - 1);
+    int eb = min(max((int)floorf(fmaxf(kf0, kf1)), 0), n - 1);
+    CumBin ca = cum_bin(E, ea, lc), cb = cum_bin(E, eb, lc);
+    const bool ma = (lo < ca.ua) | (lo > ca.ub), mb = (hi < cb.ua) | (hi > cb.ub);
+    if (ma | mb) {   // an estimate missed its edge's bin by a hair: take the neighbouring entry
+        if (ma) ca = cum_bin(E, min(max(lo < ca.ua ? ea - 1 : ea + 1, 0), n - 1), lc);
+        if (mb) cb = cum_bin(E, min(max(hi < cb.ua ? eb - 1 : eb + 1, 0), n - 1), lc);
     }
-    return zeta;
+    return cum_value(cb, hi) - cum_value(ca, lo);
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave: shifts within rows of 16 lanes, then the row totals
+// broadcast into the following rows.
+template <int CTRL, int ROWS, typename T>
+__device__ __forceinline__ T dpp_or_zero(T v)
+{
+    return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROWS, 0xF, true));
+}
+template <typename T>
+__device__ __forceinline__ T wave_prefix_sum(T v)
+{
+    v += dpp_or_zero<0x111, 0xF>(v);   // row_shr:1
+    v += dpp_or_zero<0x112, 0xF>(v);   // row_shr:2
+    v += dpp_or_zero<0x114, 0xF>(v);   // row_shr:4
+    v += dpp_or_zero<0x118, 0xF>(v);   // row_shr:8
+    v += dpp_or_zero<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_or_zero<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+    return v;
+}
+// value of the lane below (0 in lane 0)
+template <typename T>
+__device__ __forceinline__ T wave_shift_up(T v)
+{
+    return dpp_or_zero<0x138, 0xF>(v);   // wave_shr:1
 }
 
 __device__ __forceinline__ void pot_terms(int potential, float delta, float t, float &dphi, float &omega)
@@ -382,21 +419,21 @@ __device__ __forceinline__ int2 tile_window(const GeomDev &G, int v, int i0, int
     return make_int2(max((int)floorf(kmn) - 1, 0), min((int)floorf(kmx) + 1, G.nb - 1));
 }
 
-// Fused back-projection and relaxed update over one 16 x 16 pixel tile. The workgroup has two halves of
-// 256 threads (one thread per pixel each); half h back-projects the views vi = h, h + 2, ..., staging
-// for each view, in LDS, the signed boundary coefficients and r_k * scale_k of the bins that can meet the
-// tile (double-buffered: the next view's loads are in flight while the current one is evaluated). The
-// tile's bin windows and view descriptors of a chunk of up to 64 views are computed by every wave up
-// front, one view per lane, and read with readlane. The two partial sums are added in a fixed order,
-// then half 0 carries out the update of its pixel.
+// Fused back-projection and relaxed update over one 16 x 16 pixel tile. The tile's bin windows and view
+// descriptors of a chunk of up to 64 views are computed by every wave up front, one view per lane, and
+// read with readlane. The views of a chunk are staged in LDS in runs that fit the staging area: each of
+// the eight waves stages whole views (boundaries, residual x scale and their running sum over the
+// window, one wave prefix sum per view), then, after one barrier, the two halves of 256 threads (one
+// thread per pixel each) back-project the run's views of alternating parity from LDS without further
+// synchronisation. The two partial sums are added in a fixed order, then half 0 carries out the update of
+// its pixel.
 constexpr int BP_NT = BP_TX * BP_TY;
-constexpr int BP_SWIN = 125;           // bins per staged window (one view, one tile)
-constexpr int BP_SLOT = 128;           // staged entries per buffer: boundaries kw0 .. kw1 + 3
+constexpr int BP_SWIN = 125;    // widest window staged (bins); wider ones read the tables directly
+constexpr int BP_CAP = 2048;    // staged entries per workgroup (n + 1 per view of n window bins)
 
 struct BpShared {
     float tile_t[BP_TX][BP_TY + 1];
-    float2 s_ab[2][2][BP_SLOT];   // per half, double-buffered: signed boundaries kw0 .. kw1 + 3
-    float s_rs[2][2][BP_SLOT];    // residual x scale of bins kw0 .. kw1 + 2 (zero past kw1)
+    float4 ent[BP_CAP];
     float s_part[BP_NT];
 };
 
@@ -427,86 +464,79 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
         // pixel coordinates in both sweep orientations: row sweep lines are rows (l = i, q = j)
         const float lc_r = (float)i - 0.5f * (float)(ny - 1), e0_r = (float)j - 0.5f * (float)nx;
         const float lc_c = (float)j - 0.5f * (float)(nx - 1), e0_c = (float)i - 0.5f * (float)ny;
-        float2 *sab = sh.s_ab[hv][0];
-        float *srs = sh.s_rs[hv][0];
+        const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+        auto rl_f = [](float x, int q) {
+            return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), q));
+        };
         for (int c0 = 0; c0 < nv; c0 += 64) {
             const int cn = min(64, nv - c0);   // views c0 .. c0 + cn - 1 of this chunk
             // every wave holds the descriptors of the chunk's views, view c0 + q in lane q: the tile's bin
-            // window, inverse map, boundary order and sweep mode, read with readlane in the view loop
+            // window, inverse map, boundary order, sweep mode, staged entries (0: window too wide to
+            // stage) and their offset in the chunk's staging order
             int2 wq = make_int2(1, 0);
             float4 imq = make_float4(0.f, 0.f, 0.f, 0.f);
             float sq = 1.f;
-            int rq = 0;
+            int rq = 0, nq = 0;
             if (lane < cn) {
                 const int v = vstart + (c0 + lane) * vstride;
                 wq = tile_window(G, v, ti0, ti1, tj0, tj1);
                 imq = G.inv[v];
                 sq = G.sgn[v];
                 rq = G.rowsweep[v];
+                const int n = wq.y - wq.x + 1;
+                nq = n > 0 && n <= BP_SWIN ? n + 1 : 0;
             }
-            auto rl_f = [](float x, int q) {
-                return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), q));
-            };
-            // staging of view ci (entry tid): loads issued here, stored after the current view's work
-            auto stage_load = [&](int ci, float2 &ab, float &rv, float &sv) {
-                const int kw0 = __builtin_amdgcn_readlane(wq.x, ci), kw1 = __builtin_amdgcn_readlane(wq.y, ci);
-                const int n = kw1 - kw0 + 1;
-                const unsigned v = (unsigned)(vstart + (c0 + ci) * vstride);
-                ab = make_float2(0.f, 0.f);
-                rv = 0.f;
-                sv = 1.f;
-                if (n <= BP_SWIN && n > 0) {
+            const int oq_end = wave_prefix_sum(nq);
+            for (int a0 = 0; a0 < cn;) {
+                // run a0 .. a1 - 1: the views whose entries fit the staging area (at least one, since one
+                // view takes at most BP_SWIN + 1 entries)
+                const int base = __builtin_amdgcn_readlane(oq_end - nq, a0);
+                const int a1 = a0 + __popcll(__ballot(lane >= a0 && lane < cn && oq_end - base <= BP_CAP));
+                // staging: wave w takes views a0 + w, a0 + w + 8, ...; lane L the entries 2L and 2L + 1
+                for (int ci = a0 + wave; ci < a1; ci += 8) {
+                    const int ne = __builtin_amdgcn_readlane(nq, ci);
+                    if (ne == 0) continue;
+                    const int kw0 = __builtin_amdgcn_readlane(wq.x, ci);
+                    const float s = rl_f(sq, ci);
+                    const unsigned v = (unsigned)(vstart + (c0 + ci) * vstride);
+                    float4 *E = sh.ent + (__builtin_amdgcn_readlane(oq_end - nq, ci) - base);
+                    const int e0i = 2 * lane, e1i = e0i + 1;
                     // 32-bit element offsets (the geometry keeps nviews * (nb + 1) below 2^31)
-                    const int k = kw0 + tid;
-                    if (tid < n + 3) {
-                        const float s = rl_f(sq, ci);
-                        const float2 b = G.bnd[v * (unsigned)(nb + 1) + (unsigned)min(k, nb)];
-                        // past the detector: continue one pixel apart (zero residual, finite footprint)
-                        ab = make_float2(k > nb ? s * b.x + (float)(k - nb) : s * b.x, s * b.y);
-                    }
-                    if (tid < n) {
-                        rv = (float)r[(unsigned)(c0 + ci) * (unsigned)nb + (unsigned)k];
-                        if (!PRESCALED) sv = G.scale[v * (unsigned)nb + (unsigned)k];
-                    }
+                    const unsigned kb = v * (unsigned)(nb + 1) + (unsigned)(kw0 + e0i);
+                    const unsigned kr = (unsigned)(c0 + ci) * (unsigned)nb + (unsigned)(kw0 + e0i);
+                    const unsigned ks = v * (unsigned)nb + (unsigned)(kw0 + e0i);
+                    float2 b0 = make_float2(0.f, 0.f), b1 = make_float2(0.f, 0.f);
+                    float r0 = 0.f, r1 = 0.f;
+                    if (e0i < ne) b0 = G.bnd[kb];
+                    if (e1i < ne) b1 = G.bnd[kb + 1];
+                    if (e0i < ne - 1) r0 = PRESCALED ? (float)r[kr] : (float)r[kr] * G.scale[ks];
+                    if (e1i < ne - 1) r1 = PRESCALED ? (float)r[kr + 1] : (float)r[kr + 1] * G.scale[ks + 1];
+                    const float p0 = wave_shift_up(wave_prefix_sum(r0 + r1));
+                    if (e0i < ne) E[e0i] = make_float4(s * b0.x, s * b0.y, p0, r0);
+                    if (e1i < ne) E[e1i] = make_float4(s * b1.x, s * b1.y, p0 + r0, r1);
                 }
-            };
-            auto stage_store = [&](int buf, float2 ab, float rv, float sv) {
-                if (tid < BP_SLOT) {
-                    sab[buf * BP_SLOT + tid] = ab;
-                    srs[buf * BP_SLOT + tid] = PRESCALED ? rv : rv * sv;   // 0 past kw1
-                }
-            };
-            const int niter = (cn + 1) / 2;   // half hv takes views ci = hv + 2 it < cn
-            float2 ab_n = make_float2(0.f, 0.f);
-            float r_n = 0.f, s_n = 1.f;
-            if (hv < cn) stage_load(hv, ab_n, r_n, s_n);
-            stage_store(0, ab_n, r_n, s_n);
-            __syncthreads();
-            for (int it = 0; it < niter; ++it) {
-                const int ci = hv + 2 * it;
-                const int buf = it & 1;
-                if (ci + 2 < cn) stage_load(ci + 2, ab_n, r_n, s_n);
-                if (ci < cn) {
-                    const int kw0 = __builtin_amdgcn_readlane(wq.x, ci), kw1 = __builtin_amdgcn_readlane(wq.y, ci);
-                    if (inside && kw0 <= kw1) {
-                        const float4 im = make_float4(rl_f(imq.x, ci), rl_f(imq.y, ci), rl_f(imq.z, ci), rl_f(imq.w, ci));
-                        const bool row = __builtin_amdgcn_readlane(rq, ci) != 0;
-                        const float lc = row ? lc_r : lc_c, e0 = row ? e0_r : e0_c;
-                        if (kw1 - kw0 + 1 <= BP_SWIN) {
-                            zeta += bp_view_staged(G, im, lc, e0, rl_f(sq, ci), kw0, kw1, sab + buf * BP_SLOT,
-                                                   srs + buf * BP_SLOT);
-                        } else {   // window wider than the LDS slots: read the tables directly
-                            const int v = vstart + (c0 + ci) * vstride;
-                            const float2 *bv = G.bnd + (size_t)v * (nb + 1);
-                            const float *sv = G.scale + (size_t)v * nb;
-                            const TR *rv = r + (size_t)(c0 + ci) * nb;
-                            zeta += bp_view(G, im, lc, e0, kw0, kw1, [&](int k) { return bv[k]; },
-                                            [&](int k) { return PRESCALED ? (float)rv[k] : (float)rv[k] * sv[k]; });
-                        }
-                    }
-                }
-                if (it + 1 < niter) stage_store(buf ^ 1, ab_n, r_n, s_n);
                 __syncthreads();
+                for (int ci = a0 + hv; ci < a1; ci += 2) {
+                    const int kw0 = __builtin_amdgcn_readlane(wq.x, ci), kw1 = __builtin_amdgcn_readlane(wq.y, ci);
+                    if (!inside || kw0 > kw1) continue;
+                    const float4 im = make_float4(rl_f(imq.x, ci), rl_f(imq.y, ci), rl_f(imq.z, ci), rl_f(imq.w, ci));
+                    const bool row = __builtin_amdgcn_readlane(rq, ci) != 0;
+                    const float lc = row ? lc_r : lc_c, e0 = row ? e0_r : e0_c;
+                    const int ne = __builtin_amdgcn_readlane(nq, ci);
+                    if (ne > 0) {
+                        const float4 *E = sh.ent + (__builtin_amdgcn_readlane(oq_end - nq, ci) - base);
+                        zeta += bp_view_cumul(G, im, lc, e0, rl_f(sq, ci) > 0.f, ne - 1, G.k0 - (float)kw0, E);
+                    } else {   // window wider than the staging slots: read the tables directly
+                        const int v = vstart + (c0 + ci) * vstride;
+                        const float2 *bv = G.bnd + (size_t)v * (nb + 1);
+                        const float *sv = G.scale + (size_t)v * nb;
+                        const TR *rv = r + (size_t)(c0 + ci) * nb;
+                        zeta += bp_view(G, im, lc, e0, kw0, kw1, [&](int k) { return bv[k]; },
+                                        [&](int k) { return PRESCALED ? (float)rv[k] : (float)rv[k] * sv[k]; });
+                    }
+                }
+                __syncthreads();   // the next run's staging reuses the entries
+                a0 = a1;
             }
         }
         if (hv == 1) s_part[tid] = zeta;
