@@ -42,6 +42,13 @@ constexpr int BP_TX = kBpTile, BP_TY = kBpTile;
 
 __device__ __forceinline__ float rcp_approx(float v) { return __builtin_amdgcn_rcpf(v); }
 
+// Read-only geometry entry at a wave-uniform index, through the constant address space (a scalar load)
+template <typename T>
+__device__ __forceinline__ T ld_uniform(const T *p, unsigned i)
+{
+    return reinterpret_cast<const __attribute__((address_space(4))) T *>(reinterpret_cast<size_t>(p))[i];
+}
+
 template <typename T>
 __device__ __forceinline__ float ld(const void *p, size_t i)
 {
@@ -329,31 +336,39 @@ __device__ __forceinline__ float cum_value(const CumBin &c, float u)
     return fmaf(c.q.w, __builtin_amdgcn_fmed3f((u - c.ua) * rcp_approx(c.ub - c.ua), 0.f, 1.f), c.q.z);
 }
 
-// kofs = k0 - kw0: the detector coordinate measured from the window's first bin
-__device__ __forceinline__ float bp_view_cumul(const GeomDev &G, const float4 im, float lc, float e0, bool pos, int n,
-                                               float kofs, const float4 *__restrict__ E)
+// Back-projection of view onto the two pixels [ex, ex + 1] and [ex + 1, ex + 2] of line lc (val[0],
+// val[1]) from the cumulative form above: the three edges are evaluated once each. kofs = k0 - kw0 (the
+// detector coordinate from the window's first bin), n the window's bins, pos the boundary order.
+__device__ __forceinline__ void bp_line3(const GeomDev &G, const float4 im, float lc, float ex, bool pos, int n,
+                                         float kofs, const float4 *__restrict__ E, float val[2])
 {
     const float nlc = lc * im.y;
     const float dlc = fmaf(lc, im.w, G.dso);
-    const float num0 = fmaf(e0, im.x, nlc), den0 = fmaf(e0, im.z, dlc);
-    const float num1 = num0 + im.x, den1 = den0 + im.z;
-    float t0 = num0 * rcp_approx(den0), t1 = num1 * rcp_approx(den1);
-    if (G.arc) {
-        t0 = atanf(t0);
-        t1 = atanf(t1);
+    CumBin c[3];
+    float u[3];
+    int e[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const float em = ex + (float)m;
+        float t = fmaf(em, im.x, nlc) * rcp_approx(fmaf(em, im.z, dlc));
+        if (G.arc) t = atanf(t);
+        e[m] = min(max((int)floorf(fmaf(G.c_kf, t, kofs)), 0), n - 1);
+        u[m] = pos ? em : -em;   // the edge in signed coordinates
+        c[m] = cum_bin(E, e[m], lc);
     }
-    const float kf0 = fmaf(G.c_kf, t0, kofs), kf1 = fmaf(G.c_kf, t1, kofs);
-    // the pixel [e0, e0 + 1] in signed coordinates; its lower edge has the lower detector coordinate
-    const float lo = pos ? e0 : -(e0 + 1.f), hi = lo + 1.f;
-    int ea = min(max((int)floorf(fminf(kf0, kf1)), 0), n - 1);
-    int eb = min(max((int)floorf(fmaxf(kf0, kf1)), 0), n - 1);
-    CumBin ca = cum_bin(E, ea, lc), cb = cum_bin(E, eb, lc);
-    const bool ma = (lo < ca.ua) | (lo > ca.ub), mb = (hi < cb.ua) | (hi > cb.ub);
-    if (ma | mb) {   // an estimate missed its edge's bin by a hair: take the neighbouring entry
-        if (ma) ca = cum_bin(E, min(max(lo < ca.ua ? ea - 1 : ea + 1, 0), n - 1), lc);
-        if (mb) cb = cum_bin(E, min(max(hi < cb.ua ? eb - 1 : eb + 1, 0), n - 1), lc);
+    bool miss = false;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) miss |= (u[m] < c[m].ua) | (u[m] > c[m].ub);
+    if (miss) {   // an estimate missed its edge's bin by a hair: take the neighbouring entry
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+            if ((u[m] < c[m].ua) | (u[m] > c[m].ub))
+                c[m] = cum_bin(E, min(max(u[m] < c[m].ua ? e[m] - 1 : e[m] + 1, 0), n - 1), lc);
     }
-    return cum_value(cb, hi) - cum_value(ca, lo);
+    const float F0 = cum_value(c[0], u[0]), F1 = cum_value(c[1], u[1]), F2 = cum_value(c[2], u[2]);
+    // pixel m spans the signed edges u[m], u[m + 1] (ascending when pos, descending otherwise)
+    val[0] = pos ? F1 - F0 : F0 - F1;
+    val[1] = pos ? F2 - F1 : F1 - F2;
 }
 
 // Inclusive prefix sum over the 64 lanes of a wave: shifts within rows of 16 lanes, then the row totals
@@ -419,22 +434,22 @@ __device__ __forceinline__ int2 tile_window(const GeomDev &G, int v, int i0, int
     return make_int2(max((int)floorf(kmn) - 1, 0), min((int)floorf(kmx) + 1, G.nb - 1));
 }
 
-// Fused back-projection and relaxed update over one 16 x 16 pixel tile. The tile's bin windows and view
-// descriptors of a chunk of up to 64 views are computed by every wave up front, one view per lane, and
-// read with readlane. The views of a chunk are staged in LDS in runs that fit the staging area: each of
-// the eight waves stages whole views (boundaries, residual x scale and their running sum over the
-// window, one wave prefix sum per view), then, after one barrier, the two halves of 256 threads (one
-// thread per pixel each) back-project the run's views of alternating parity from LDS without further
-// synchronisation. The two partial sums are added in a fixed order, then half 0 carries out the update of
-// its pixel.
+// Fused back-projection and relaxed update over one 16 x 16 pixel tile. The workgroup's eight waves are
+// view groups: wave w back-projects the views w, w + 8, w + 16, ... onto the whole tile, each lane a 2 x 2
+// block of pixels. Each wave computes its views' bin windows and descriptors one view per lane (read
+// back with readlane) and stages its current view in its own LDS slot (boundaries, residual x scale and
+// their running sum over the window: one wave prefix sum), the next view's loads in flight meanwhile; the
+// view loop needs no workgroup barrier. On the two lines of a block the pixels share edges, so a view
+// costs six edge evaluations for four pixels. The eight partial sums are added in a fixed order, then the
+// first 256 threads carry out the update, one pixel each.
 constexpr int BP_NT = BP_TX * BP_TY;
+constexpr int BP_GROUPS = 8;    // view groups (waves) per workgroup
 constexpr int BP_SWIN = 125;    // widest window staged (bins); wider ones read the tables directly
-constexpr int BP_CAP = 2048;    // staged entries per workgroup (n + 1 per view of n window bins)
+constexpr int BP_SLOT = 128;    // staged entries per view (n + 1 for a window of n bins)
 
 struct BpShared {
     float tile_t[BP_TX][BP_TY + 1];
-    float4 ent[BP_CAP];
-    float s_part[BP_NT];
+    float4 ent[BP_GROUPS][BP_SLOT];   // per wave: the staged view, then the wave's partial sums
 };
 
 template <int MODE, typename TR, typename TXC>
@@ -446,8 +461,7 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
     const UpdateArgs &U = a.U;
     const int vstart = a.vstart, vstride = a.vstride, nv = a.nv;
     const TR *__restrict__ r = static_cast<const TR *>(a.r);
-    // Half hv = threadIdx.x / 256 of the workgroup back-projects the views of parity hv onto the 16 x 16
-    // tile, one pixel per thread; each half stages one view at a time in its LDS slots.
+    // threads 0 .. 255 (hv = 0) update pixel tid of the tile after the back-projection
     const int hv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / BP_NT));
     const int tid = threadIdx.x % BP_NT;
     const int lane = threadIdx.x & 63;
@@ -455,93 +469,128 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
     const int j = bx * BP_TX + tx, i = by * BP_TY + ty;
     const int nx = G.nx, ny = G.ny, nb = G.nb;
     auto &tile_t = sh.tile_t;
-    auto &s_part = sh.s_part;
     const bool inside = i < ny && j < nx;
     float zeta = 0.f;
     if (MODE != BP_XSTEP) {
         const int ti0 = by * BP_TY, ti1 = min(ti0 + BP_TY, ny);
         const int tj0 = bx * BP_TX, tj1 = min(tj0 + BP_TX, nx);
-        // pixel coordinates in both sweep orientations: row sweep lines are rows (l = i, q = j)
-        const float lc_r = (float)i - 0.5f * (float)(ny - 1), e0_r = (float)j - 0.5f * (float)nx;
-        const float lc_c = (float)j - 0.5f * (float)(nx - 1), e0_c = (float)i - 0.5f * (float)ny;
-        const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+        const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // view group
+        // the lane's block: tile rows 2 (lane / 8) + {0, 1}, columns 2 (lane % 8) + {0, 1}. Row sweep views:
+        // lines are the two rows, edges run along x; column sweep views: lines are the two columns.
+        const int pi = 2 * (lane >> 3), pj = 2 * (lane & 7);
+        const float lc_r = (float)(ti0 + pi) - 0.5f * (float)(ny - 1), ex_r = (float)(tj0 + pj) - 0.5f * (float)nx;
+        float acc[2][2] = {{0.f, 0.f}, {0.f, 0.f}};   // [row][column] within the block
+        float4 *E = sh.ent[wave];
         auto rl_f = [](float x, int q) {
             return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), q));
         };
-        for (int c0 = 0; c0 < nv; c0 += 64) {
-            const int cn = min(64, nv - c0);   // views c0 .. c0 + cn - 1 of this chunk
-            // every wave holds the descriptors of the chunk's views, view c0 + q in lane q: the tile's bin
-            // window, inverse map, boundary order, sweep mode, staged entries (0: window too wide to
-            // stage) and their offset in the chunk's staging order
+        const int nvw = nv > wave ? (nv - wave + BP_GROUPS - 1) / BP_GROUPS : 0;   // views of this group
+        for (int c0 = 0; c0 < nvw; c0 += 64) {
+            const int cn = min(64, nvw - c0);
+            // view wave + 8 (c0 + q) in lane q: the tile's bin window and staged entries (0: window too wide
+            // to stage); the view's inverse map, boundary order and sweep mode are read by scalar loads
             int2 wq = make_int2(1, 0);
-            float4 imq = make_float4(0.f, 0.f, 0.f, 0.f);
-            float sq = 1.f;
-            int rq = 0, nq = 0;
+            int nq = 0;
             if (lane < cn) {
-                const int v = vstart + (c0 + lane) * vstride;
+                const int v = vstart + (wave + BP_GROUPS * (c0 + lane)) * vstride;
                 wq = tile_window(G, v, ti0, ti1, tj0, tj1);
-                imq = G.inv[v];
-                sq = G.sgn[v];
-                rq = G.rowsweep[v];
                 const int n = wq.y - wq.x + 1;
                 nq = n > 0 && n <= BP_SWIN ? n + 1 : 0;
             }
-            const int oq_end = wave_prefix_sum(nq);
-            for (int a0 = 0; a0 < cn;) {
-                // run a0 .. a1 - 1: the views whose entries fit the staging area (at least one, since one
-                // view takes at most BP_SWIN + 1 entries)
-                const int base = __builtin_amdgcn_readlane(oq_end - nq, a0);
-                const int a1 = a0 + __popcll(__ballot(lane >= a0 && lane < cn && oq_end - base <= BP_CAP));
-                // staging: wave w takes views a0 + w, a0 + w + 8, ...; lane L the entries 2L and 2L + 1
-                for (int ci = a0 + wave; ci < a1; ci += 8) {
+            // staging of view ci: lane L loads entries 2L and 2L + 1; the running sum is formed on store
+            struct Fetch {
+                float2 b0, b1;
+                float r0, r1;
+            };
+            auto fetch = [&](int ci) {
+                Fetch q = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), 0.f, 0.f};
+                const int ne = __builtin_amdgcn_readlane(nq, ci);
+                if (ne == 0) return q;
+                const int kw0 = __builtin_amdgcn_readlane(wq.x, ci);
+                const unsigned vi = (unsigned)(wave + BP_GROUPS * (c0 + ci));
+                const unsigned v = (unsigned)vstart + vi * (unsigned)vstride;
+                const int e0i = 2 * lane, e1i = e0i + 1;
+                // 32-bit element offsets (the geometry keeps nviews * (nb + 1) below 2^31)
+                const unsigned kb = v * (unsigned)(nb + 1) + (unsigned)(kw0 + e0i);
+                const unsigned kr = vi * (unsigned)nb + (unsigned)(kw0 + e0i);
+                const unsigned ks = v * (unsigned)nb + (unsigned)(kw0 + e0i);
+                if (e0i < ne) q.b0 = G.bnd[kb];
+                if (e1i < ne) q.b1 = G.bnd[kb + 1];
+                if (e0i < ne - 1) q.r0 = PRESCALED ? (float)r[kr] : (float)r[kr] * G.scale[ks];
+                if (e1i < ne - 1) q.r1 = PRESCALED ? (float)r[kr + 1] : (float)r[kr + 1] * G.scale[ks + 1];
+                return q;
+            };
+            auto put = [&](int ci, const Fetch &q) {
+                const int ne = __builtin_amdgcn_readlane(nq, ci);
+                if (ne == 0) return;
+                const float s = ld_uniform(G.sgn, (unsigned)(vstart + (wave + BP_GROUPS * (c0 + ci)) * vstride));
+                const int e0i = 2 * lane, e1i = e0i + 1;
+                const float p0 = wave_shift_up(wave_prefix_sum(q.r0 + q.r1));
+                if (e0i < ne) E[e0i] = make_float4(s * q.b0.x, s * q.b0.y, p0, q.r0);
+                if (e1i < ne) E[e1i] = make_float4(s * q.b1.x, s * q.b1.y, p0 + q.r0, q.r1);
+            };
+            for (int ci = 0; ci < cn; ++ci) {
+                // LDS operations of one wave complete in order: the previous view's reads precede these
+                // stores. (Other waves of the CU run while this one waits for its loads.)
+                put(ci, fetch(ci));
+                const int kw0 = __builtin_amdgcn_readlane(wq.x, ci), kw1 = __builtin_amdgcn_readlane(wq.y, ci);
+                if (kw0 <= kw1) {
+                    const unsigned vu = (unsigned)(vstart + (wave + BP_GROUPS * (c0 + ci)) * vstride);
+                    const float *imv = reinterpret_cast<const float *>(G.inv);
+                    const float4 im = make_float4(ld_uniform(imv, 4 * vu), ld_uniform(imv, 4 * vu + 1),
+                                                  ld_uniform(imv, 4 * vu + 2), ld_uniform(imv, 4 * vu + 3));
+                    const bool row = ld_uniform(G.rowsweep, vu) != 0;
+                    const bool pos = ld_uniform(G.sgn, vu) > 0.f;
                     const int ne = __builtin_amdgcn_readlane(nq, ci);
-                    if (ne == 0) continue;
-                    const int kw0 = __builtin_amdgcn_readlane(wq.x, ci);
-                    const float s = rl_f(sq, ci);
-                    const unsigned v = (unsigned)(vstart + (c0 + ci) * vstride);
-                    float4 *E = sh.ent + (__builtin_amdgcn_readlane(oq_end - nq, ci) - base);
-                    const int e0i = 2 * lane, e1i = e0i + 1;
-                    // 32-bit element offsets (the geometry keeps nviews * (nb + 1) below 2^31)
-                    const unsigned kb = v * (unsigned)(nb + 1) + (unsigned)(kw0 + e0i);
-                    const unsigned kr = (unsigned)(c0 + ci) * (unsigned)nb + (unsigned)(kw0 + e0i);
-                    const unsigned ks = v * (unsigned)nb + (unsigned)(kw0 + e0i);
-                    float2 b0 = make_float2(0.f, 0.f), b1 = make_float2(0.f, 0.f);
-                    float r0 = 0.f, r1 = 0.f;
-                    if (e0i < ne) b0 = G.bnd[kb];
-                    if (e1i < ne) b1 = G.bnd[kb + 1];
-                    if (e0i < ne - 1) r0 = PRESCALED ? (float)r[kr] : (float)r[kr] * G.scale[ks];
-                    if (e1i < ne - 1) r1 = PRESCALED ? (float)r[kr + 1] : (float)r[kr + 1] * G.scale[ks + 1];
-                    const float p0 = wave_shift_up(wave_prefix_sum(r0 + r1));
-                    if (e0i < ne) E[e0i] = make_float4(s * b0.x, s * b0.y, p0, r0);
-                    if (e1i < ne) E[e1i] = make_float4(s * b1.x, s * b1.y, p0 + r0, r1);
-                }
-                __syncthreads();
-                for (int ci = a0 + hv; ci < a1; ci += 2) {
-                    const int kw0 = __builtin_amdgcn_readlane(wq.x, ci), kw1 = __builtin_amdgcn_readlane(wq.y, ci);
-                    if (!inside || kw0 > kw1) continue;
-                    const float4 im = make_float4(rl_f(imq.x, ci), rl_f(imq.y, ci), rl_f(imq.z, ci), rl_f(imq.w, ci));
-                    const bool row = __builtin_amdgcn_readlane(rq, ci) != 0;
-                    const float lc = row ? lc_r : lc_c, e0 = row ? e0_r : e0_c;
-                    const int ne = __builtin_amdgcn_readlane(nq, ci);
+                    // column sweep: line of column tj0 + pj at ex_r + 1/2, edges along y from lc_r - 1/2
+                    const float lc0 = row ? lc_r : ex_r + 0.5f, ex = row ? ex_r : lc_r - 0.5f;
+                    float val[2][2];   // [line][pixel along the line]
                     if (ne > 0) {
-                        const float4 *E = sh.ent + (__builtin_amdgcn_readlane(oq_end - nq, ci) - base);
-                        zeta += bp_view_cumul(G, im, lc, e0, rl_f(sq, ci) > 0.f, ne - 1, G.k0 - (float)kw0, E);
+                        const float kofs = G.k0 - (float)kw0;
+#pragma unroll
+                        for (int ln = 0; ln < 2; ++ln) {
+                            bp_line3(G, im, lc0 + (float)ln, ex, pos, ne - 1, kofs, E, val[ln]);
+                            __builtin_amdgcn_sched_barrier(0);   // one line at a time: bounds register use
+                        }
                     } else {   // window wider than the staging slots: read the tables directly
-                        const int v = vstart + (c0 + ci) * vstride;
+                        const int vi = wave + BP_GROUPS * (c0 + ci);
+                        const int v = vstart + vi * vstride;
                         const float2 *bv = G.bnd + (size_t)v * (nb + 1);
                         const float *sv = G.scale + (size_t)v * nb;
-                        const TR *rv = r + (size_t)(c0 + ci) * nb;
-                        zeta += bp_view(G, im, lc, e0, kw0, kw1, [&](int k) { return bv[k]; },
-                                        [&](int k) { return PRESCALED ? (float)rv[k] : (float)rv[k] * sv[k]; });
+                        const TR *rv = r + (size_t)vi * nb;
+#pragma unroll
+                        for (int ln = 0; ln < 2; ++ln)
+#pragma unroll
+                            for (int m = 0; m < 2; ++m)
+                                val[ln][m] = bp_view(G, im, lc0 + (float)ln, ex + (float)m, kw0, kw1,
+                                                     [&](int k) { return bv[k]; },
+                                                     [&](int k) { return PRESCALED ? (float)rv[k] : (float)rv[k] * sv[k]; });
+                    }
+                    if (row) {
+                        acc[0][0] += val[0][0];
+                        acc[0][1] += val[0][1];
+                        acc[1][0] += val[1][0];
+                        acc[1][1] += val[1][1];
+                    } else {
+                        acc[0][0] += val[0][0];
+                        acc[1][0] += val[0][1];
+                        acc[0][1] += val[1][0];
+                        acc[1][1] += val[1][1];
                     }
                 }
-                __syncthreads();   // the next run's staging reuses the entries
-                a0 = a1;
             }
         }
-        if (hv == 1) s_part[tid] = zeta;
+        // partial sums of the group, by tile pixel, in the wave's own slot (its staged reads are complete)
+        float *part = reinterpret_cast<float *>(E);
+        part[pi * BP_TX + pj] = acc[0][0];
+        part[pi * BP_TX + pj + 1] = acc[0][1];
+        part[(pi + 1) * BP_TX + pj] = acc[1][0];
+        part[(pi + 1) * BP_TX + pj + 1] = acc[1][1];
         __syncthreads();
-        if (hv == 0) zeta += s_part[tid];
+        if (hv == 0) {
+#pragma unroll
+            for (int w = 0; w < BP_GROUPS; ++w) zeta += reinterpret_cast<const float *>(sh.ent[w])[tid];
+        }
     }
     float xn = 0.f;
     if (hv == 0 && inside) {   // half 1 only takes part in the barriers from here on
