@@ -36,7 +36,7 @@ XSTAR = os.path.join(ROOT, "tests", "golden", "xstar_cfg2_seed100.npz")
 UNET_WEIGHTS = os.path.join(ROOT, "paper_1512_04564_amd", "weights", "unet_512.npz")
 MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix-core peak
 KERNEL_SRC = os.path.join(ROOT, "paper_1512_04564_amd", "csrc", "ct_kernels.hip")
-TRAFFIC = os.path.join(ROOT, "profiles", "traffic_k_back_update_cfg2.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic_projectors_512.json")
 COPY_BYTES = 256 * 2 ** 20   # calibration copy of the counter workload (bytes read = bytes written)
 ORDER = "bitrev"             # subset order of every benchmarked solve
 
@@ -47,21 +47,22 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the dominant kernel from the stored FETCH_SIZE / WRITE_SIZE counter runs,
-    scaled by the same counters' reading for a copy of known size; None once the kernels have changed."""
+def measured_traffic(kernel):
+    """HBM bytes per launch of the solve's "forward" or "update" kernel from the stored FETCH_SIZE /
+    WRITE_SIZE counter runs, scaled by the same counters' reading for a copy of known size; None once the
+    kernels have changed."""
     if not os.path.exists(TRAFFIC):
         return None
     with open(TRAFFIC) as f:
         t = json.load(f)
     if t.get("kernel_source_sha256") != kernel_source_hash():
         return None
-    return t["bytes_per_launch"]
+    return t["kernels"][kernel]["bytes_per_launch"]
 
 
 def write_traffic(fetch_dir, write_dir):
-    """Write the traffic record of the fused update kernel from the two counter runs of --pmc-workload
-    (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, CSV output): average KiB per dispatch of the kernel, scaled
+    """Write the traffic record of the solve's two kernels from the two counter runs of --pmc-workload
+    (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, CSV output): average KiB per dispatch of each kernel, scaled
     by the counters' reading for the workload's device copy of COPY_BYTES, and stamped with the kernel
     source's hash."""
     import csv
@@ -81,28 +82,25 @@ def write_traffic(fetch_dir, write_dir):
         return "ct::" in r["Kernel_Name"]
 
     rf, rw = rows(fetch_dir, "FETCH_SIZE"), rows(write_dir, "WRITE_SIZE")
-    fu, n = mean_of(rf, "k_back_update<2")
-    wu, _ = mean_of(rw, "k_back_update<2")
-    ffw, _ = mean_of(rf, "k_forward<1, false")
-    wfw, _ = mean_of(rw, "k_forward<1, false")
     # the copy reads and writes COPY_BYTES: the non-library dispatch that fetches the most (the fill that
     # creates its source writes as much but reads nothing), and the same kernel's write count
     cf = max((r for r in rf if not library(r)), key=lambda r: float(r["Counter_Value"]))
     cw = max((r for r in rw if r["Kernel_Name"] == cf["Kernel_Name"]), key=lambda r: float(r["Counter_Value"]))
     kib = COPY_BYTES / 1024.0
     ff, wf = kib / float(cf["Counter_Value"]), kib / float(cw["Counter_Value"])
+    kernels = {}
+    for name, key in (("update", "k_back_update<2, float, float>"), ("forward", "k_forward<1, false, 16, float")):
+        fk, n = mean_of(rf, key)
+        wk, _ = mean_of(rw, key)
+        kernels[name] = {"kernel": key, "fetch_kib_per_dispatch": round(fk, 1), "write_kib_per_dispatch": round(wk, 1),
+                         "dispatches_averaged": n, "bytes_per_launch": int(round((fk * ff + wk * wf) * 1024))}
     rec = {
-        "kernel": "k_back_update<BP_FULL>",
-        "workload": "512x512, 888 bins, 984 views, 41 subsets (24-view subset per launch)",
+        "workload": "512x512, 888 bins, 984 views, 41 subsets (24-view subset per launch), float32",
         "kernel_source_sha256": kernel_source_hash(),
-        "fetch_kib_per_dispatch": round(fu, 1),
-        "write_kib_per_dispatch": round(wu, 1),
-        "dispatches_averaged": n,
+        "kernels": kernels,
         "copy_calibration": {"bytes_copied": COPY_BYTES, "kernel": cf["Kernel_Name"][:120],
                              "fetch_kib": float(cf["Counter_Value"]), "write_kib": float(cw["Counter_Value"]),
                              "fetch_factor": round(ff, 4), "write_factor": round(wf, 4)},
-        "bytes_per_launch": int(round((fu * ff + wu * wf) * 1024)),
-        "forward_kernel_bytes_per_launch": int(round((ffw * ff + wfw * wf) * 1024)),
         "commands": [f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {fetch_dir} -o p -- python3 bench.py --pmc-workload",
                      f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {write_dir} -o p -- python3 bench.py --pmc-workload"],
     }
@@ -283,7 +281,7 @@ def main():
     achieved = ops[dom] / times[dom] / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
                 "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                "traffic": measured_traffic() if dom == "update" else None,
+                "traffic": measured_traffic(dom),
                 "kernel": "k_back_update<BP_FULL> (fused subset back-projection + relaxed update)" if dom == "update"
                 else "k_forward<FP_RESIDUAL> (subset forward projection + weighted residual)",
                 "ops_per_launch": ops[dom], "us_per_launch": round(times[dom] * 1e6, 2),
