@@ -145,6 +145,49 @@ __device__ __forceinline__ void fp_body(const FpLaunch &a, const int bx, const i
     windows(lb);
     if (l0 < l1) prefetch(l0, __builtin_amdgcn_readfirstlane(ws_v));
     float lc = lc0 + (float)l0;
+    // Branch-free loop when every footprint of the block is at most two pixels wide (three taps suffice:
+    // d < width + 1 < 3) and every line's window fits the LDS slice (its width is at most the span of the
+    // block's outer boundaries + 4). Both widths are linear in the line coordinate, so their maxima over the
+    // view's lines are at the first or the last line. It computes the same sums as the general loop below:
+    // a footprint that misses the line gets zero weights, and the tap index is clamped into the padded
+    // window, whose entries are finite.
+    const float lcL = lc0 + (float)(NL - 1);
+    const float fw = fmaxf(fabsf(fmaf(lc0, b1.y - b0.y, b1.x - b0.x)), fabsf(fmaf(lcL, b1.y - b0.y, b1.x - b0.x)));
+    const float bw = fmaxf(fabsf(fmaf(lc0, bL.y - bF.y, bL.x - bF.x)), fabsf(fmaf(lcL, bL.y - bF.y, bL.x - bF.x)));
+    if (__ballot(fw > 1.99f || bw + 5.f > (float)FP_WIN) == 0) {
+        for (int l = l0; l < l1; ++l, lc += 1.f) {
+            const int ws = __builtin_amdgcn_readlane(ws_v, l - lb);
+            if (!ONES) {
+#pragma unroll
+                for (int j = 0; j < FP_PF; ++j) wl[lane + 64 * j] = pf[j];
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (l + 1 < l1) {
+                if (l + 1 - lb == 64) {
+                    lb += 64;
+                    windows(lb);
+                }
+                prefetch(l + 1, __builtin_amdgcn_readlane(ws_v, l + 1 - lb));
+            }
+            const float u0 = fmaf(lc, b0.y, b0.x);
+            const float u1 = fmaf(lc, b1.y, b1.x);
+            const float lo = fminf(u0, u1), hi = fmaxf(u0, u1);
+            const float loc = fmaxf(lo, -half), hic = fminf(hi, half);
+            int q0 = (int)floorf(loc + half);
+            float e = (float)q0 - half;
+            if (loc < e) {   // exact correction of a rounded floor
+                --q0;
+                e -= 1.f;
+            }
+            const float d = hic - e, f = loc - e;
+            const float *tp = wl + min(max(q0 - ws, 0), FP_WIN);
+            float s = fmaxf(fminf(d, 1.f) - f, 0.f) * tp[0];
+            s = fmaf(__builtin_amdgcn_fmed3f(d - 1.f, 0.f, 1.f), tp[1], s);
+            s = fmaf(__builtin_amdgcn_fmed3f(d - 2.f, 0.f, 1.f), tp[2], s);
+            acc = fmaf(s, rcp_approx(hi - lo), acc);
+            __builtin_amdgcn_wave_barrier();
+        }
+    } else
     for (int l = l0; l < l1; ++l, lc += 1.f) {
         const int ws = __builtin_amdgcn_readlane(ws_v, l - lb);
         const int wn = __builtin_amdgcn_readlane(wn_v, l - lb);
