@@ -154,39 +154,80 @@ __device__ __forceinline__ void fp_body(const FpLaunch &a, const int bx, const i
     const float lcL = lc0 + (float)(NL - 1);
     const float fw = fmaxf(fabsf(fmaf(lc0, b1.y - b0.y, b1.x - b0.x)), fabsf(fmaf(lcL, b1.y - b0.y, b1.x - b0.x)));
     const float bw = fmaxf(fabsf(fmaf(lc0, bL.y - bF.y, bL.x - bF.x)), fabsf(fmaf(lcL, bL.y - bF.y, bL.x - bF.x)));
-    if (__ballot(fw > 1.99f || bw + 5.f > (float)FP_WIN) == 0) {
-        for (int l = l0; l < l1; ++l, lc += 1.f) {
-            const int ws = __builtin_amdgcn_readlane(ws_v, l - lb);
-            if (!ONES) {
-#pragma unroll
-                for (int j = 0; j < FP_PF; ++j) wl[lane + 64 * j] = pf[j];
-            }
-            __builtin_amdgcn_wave_barrier();
-            if (l + 1 < l1) {
-                if (l + 1 - lb == 64) {
-                    lb += 64;
-                    windows(lb);
-                }
-                prefetch(l + 1, __builtin_amdgcn_readlane(ws_v, l + 1 - lb));
-            }
-            const float u0 = fmaf(lc, b0.y, b0.x);
-            const float u1 = fmaf(lc, b1.y, b1.x);
-            const float lo = fminf(u0, u1), hi = fmaxf(u0, u1);
-            const float loc = fmaxf(lo, -half), hic = fminf(hi, half);
-            int q0 = (int)floorf(loc + half);
-            float e = (float)q0 - half;
+    // first pixel q0 of a footprint starting at loc and its left edge e (exact)
+    auto first_pixel = [&](float loc, int &q0, float &e, auto even_tag) {
+        if (decltype(even_tag)::value) {   // pixel edges sit at integers: floor is exact
+            e = floorf(loc);
+            q0 = (int)e + hq;
+        } else {
+            q0 = (int)floorf(loc + half);
+            e = (float)q0 - half;
             if (loc < e) {   // exact correction of a rounded floor
                 --q0;
                 e -= 1.f;
             }
+        }
+    };
+    // two lines in flight: register sets A (even steps) and B (odd steps), no moves between them; every
+    // step issues its loads (the last line repeats past the end) so that the loads in flight are counted
+    // statically
+    auto fast_lines = [&](auto even_tag) {
+        float pA[FP_PF], pB[FP_PF];
+        int wsA = 0, wsB = 0;
+        auto fetch_into = [&](int ll, float (&dst)[FP_PF], int &wsd) {
+            ll = min(ll, l1 - 1);
+            if (ll - lb == 64) {
+                lb += 64;
+                windows(lb);
+            }
+            wsd = __builtin_amdgcn_readlane(ws_v, ll - lb);
+            prefetch(ll, wsd);
+#pragma unroll
+            for (int j = 0; j < FP_PF; ++j) dst[j] = pf[j];
+        };
+        auto step = [&](int l, const float (&src)[FP_PF], int ws) {
+            if (!ONES) {
+#pragma unroll
+                for (int j = 0; j < FP_PF; ++j) wl[lane + 64 * j] = src[j];
+            }
+            __builtin_amdgcn_wave_barrier();
+            const float lcl = lc0 + (float)l;
+            const float u0 = fmaf(lcl, b0.y, b0.x);
+            const float u1 = fmaf(lcl, b1.y, b1.x);
+            const float lo = fminf(u0, u1), hi = fmaxf(u0, u1);
+            const float loc = fmaxf(lo, -half), hic = fminf(hi, half);
+            int q0;
+            float e;
+            first_pixel(loc, q0, e, even_tag);
             const float d = hic - e, f = loc - e;
             const float *tp = wl + min(max(q0 - ws, 0), FP_WIN);
             float s = fmaxf(fminf(d, 1.f) - f, 0.f) * tp[0];
             s = fmaf(__builtin_amdgcn_fmed3f(d - 1.f, 0.f, 1.f), tp[1], s);
             s = fmaf(__builtin_amdgcn_fmed3f(d - 2.f, 0.f, 1.f), tp[2], s);
-            acc = fmaf(s, rcp_approx(hi - lo), acc);
+            return s * rcp_approx(hi - lo);
+        };
+        // line l0 is already fetched into pf (by the caller's prefetch); line l0 + 1 goes to B
+        int wsA0 = __builtin_amdgcn_readlane(ws_v, l0 - lb);
+#pragma unroll
+        for (int j = 0; j < FP_PF; ++j) pA[j] = pf[j];
+        wsA = wsA0;
+        fetch_into(l0 + 1, pB, wsB);
+        for (int l = l0; l < l1; l += 2) {
+            const float ca = step(l, pA, wsA);
             __builtin_amdgcn_wave_barrier();
+            fetch_into(l + 2, pA, wsA);
+            acc += ca;
+            if (l + 1 < l1) {
+                const float cb = step(l + 1, pB, wsB);
+                __builtin_amdgcn_wave_barrier();
+                fetch_into(l + 3, pB, wsB);
+                acc += cb;
+            }
         }
+    };
+    if (__ballot(fw > 1.99f || bw + 5.f > (float)FP_WIN) == 0) {
+        if (even) fast_lines(std::true_type{});
+        else fast_lines(std::false_type{});
     } else
     for (int l = l0; l < l1; ++l, lc += 1.f) {
         const int ws = __builtin_amdgcn_readlane(ws_v, l - lb);
