@@ -104,6 +104,14 @@ __device__ __forceinline__ void fp_body(const FpLaunch &a, const int bx, const i
     const float2 *bv = G.bnd + (size_t)v * (nb + 1);
     const float2 b0 = bv[kc], b1 = bv[kc + 1];
     const float2 bF = bv[kblk], bL = bv[klast];
+    // operands of the epilogue (wave 0), loaded with the boundaries so that their latency overlaps
+    float e_sc = 0.f, e_w = 0.f, e_y = 0.f;
+    if (wave == 0 && k < nb) {
+        const size_t si = (size_t)v * nb + k;
+        e_sc = G.scale[si];
+        if (EPI != FP_PLAIN) e_w = ld<TY>(a.w, si);
+        if (EPI == FP_RESIDUAL) e_y = ld<TY>(a.y, si);
+    }
     float *wl = win + wave * PADW;
     for (int t = lane; t < PADW; t += 64) wl[t] = ONES ? 1.f : 0.f;
     const int l0 = (wave * NL) / WAVES, l1 = ((wave + 1) * NL) / WAVES;
@@ -293,14 +301,13 @@ __device__ __forceinline__ void fp_body(const FpLaunch &a, const int bx, const i
         float p = 0.f;
 #pragma unroll
         for (int ww = 0; ww < WAVES; ++ww) p += red[ww * 64 + lane];
-        const float sc = G.scale[(size_t)v * nb + k];
+        const float sc = e_sc;
         p *= sc;
         const size_t o = (size_t)vi * nb + k;
-        const size_t si = (size_t)v * nb + k;
         if (EPI == FP_PLAIN) st<TO>(a.out, o, p);
         // the residual is stored multiplied by the bin scale, the factor the back-projector applies to it
-        else if (EPI == FP_RESIDUAL) st<TO>(a.out, o, (a.mscale * ld<TY>(a.w, si) * (p - ld<TY>(a.y, si))) * sc);
-        else st<TO>(a.out, o, ld<TY>(a.w, si) * p);
+        else if (EPI == FP_RESIDUAL) st<TO>(a.out, o, (a.mscale * e_w * (p - e_y)) * sc);
+        else st<TO>(a.out, o, e_w * p);
     }
 }
 
