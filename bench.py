@@ -185,7 +185,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--niters", type=int, default=100)
-    ap.add_argument("--t1hu-iters", type=int, default=300, help="iterations of the time-to-1-HU runs")
+    ap.add_argument("--t1hu-iters", type=int, default=500, help="iterations of the time-to-1-HU runs")
+    ap.add_argument("--no-t1hu", action="store_true", help="skip the time-to-1-HU runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven 32-slice batch")
@@ -370,7 +371,7 @@ def main():
     # iterations. Ordered subsets do not converge: a run that settles in a limit cycle above 1 HU reports
     # iters null with its best RMSD.
     t1hu = None
-    if os.path.exists(XSTAR):
+    if os.path.exists(XSTAR) and not args.no_t1hu:
         xstar = torch.as_tensor(np.load(XSTAR)["x"], device=dev)
         t1hu = {}
         geoms = {41: G, 12: G12, 4: api.Geometry(g.replace(nsubsets=4))}
@@ -394,7 +395,7 @@ def main():
             best = min(r["rmsd_hu"] for r in rows)
             entry = {"iters": hit[0] if hit else None, "best_rmsd_hu": round(best, 3),
                      "rmsd_hu_at": {str(r["iter"]): round(r["rmsd_hu"], 2) for r in rows
-                                    if r["iter"] in (1, 2, 5, 10, 20, 50, 100, 200, 300)}}
+                                    if r["iter"] in (1, 2, 5, 10, 20, 50, 100, 200, 300, 500)}}
             if hit:
                 solve_m(M_, alpha, hit[0], start=start)
                 entry["seconds"] = round(timed(lambda: solve_m(M_, alpha, hit[0], start=start), 3), 5)
