@@ -60,14 +60,27 @@ __device__ __forceinline__ void st(void *p, size_t i, float v)
     static_cast<T *>(p)[i] = (T)v;
 }
 
-// one element of type T through a buffer resource, byte offset off, as float
+// The bits of one element of type T through a buffer resource (byte offset off), and their value as
+// float. The two are separate so that a prefetch can keep the raw bits in flight: converting at load time
+// would make the load wait for its data at once.
+// (float32 elements are kept as float.)
 template <typename T>
-__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t rs, unsigned off)
+using RawT = std::conditional_t<sizeof(T) == 4, float, unsigned>;
+template <typename T>
+__device__ __forceinline__ RawT<T> buf_raw(__amdgpu_buffer_rsrc_t rs, unsigned off)
 {
     if constexpr (sizeof(T) == 4)
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0));
     else
-        return (float)__builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(rs, (int)off, 0, 0));
+        return __builtin_amdgcn_raw_buffer_load_b16(rs, (int)off, 0, 0);
+}
+template <typename T>
+__device__ __forceinline__ float from_raw(RawT<T> u)
+{
+    if constexpr (sizeof(T) == 4)
+        return u;
+    else
+        return (float)__builtin_bit_cast(T, (unsigned short)u);
 }
 
 // Forward projection of the views vstart + vi * vstride (vi = blockIdx.y) for the 64 bins of block
@@ -127,7 +140,7 @@ __device__ __forceinline__ void fp_body(const FpLaunch &a, const int bx, const i
         const int we = min((int)floorf(hi + half) + 1, NQ - 1);
         wn_v = lo < hi ? we - ws_v + 1 : 0;
     };
-    float pf[FP_PF];
+    RawT<TI> pf[FP_PF];
     // Image lines are read through a buffer resource over the whole image: one scalar descriptor, a 32-bit
     // byte offset per lane (line base included, so the hardware range check covers every read) and reads
     // past the image returning 0. Reads past the end of a line only feed taps of zero weight (their
@@ -140,7 +153,7 @@ __device__ __forceinline__ void fp_body(const FpLaunch &a, const int bx, const i
             const unsigned base = ((unsigned)l * (unsigned)NQ + (unsigned)ws) * (unsigned)sizeof(TI);
 #pragma unroll
             for (int j = 0; j < FP_PF; ++j) {
-                pf[j] = buf_ld<TI>(img_rs, lane_off + base + (unsigned)(64 * j * sizeof(TI)));
+                pf[j] = buf_raw<TI>(img_rs, lane_off + base + (unsigned)(64 * j * sizeof(TI)));
             }
         }
     };
@@ -180,9 +193,9 @@ __device__ __forceinline__ void fp_body(const FpLaunch &a, const int bx, const i
     // step issues its loads (the last line repeats past the end) so that the loads in flight are counted
     // statically
     auto fast_lines = [&](auto even_tag) {
-        float pA[FP_PF], pB[FP_PF];
+        RawT<TI> pA[FP_PF], pB[FP_PF];
         int wsA = 0, wsB = 0;
-        auto fetch_into = [&](int ll, float (&dst)[FP_PF], int &wsd) {
+        auto fetch_into = [&](int ll, RawT<TI> (&dst)[FP_PF], int &wsd) {
             ll = min(ll, l1 - 1);
             if (ll - lb == 64) {
                 lb += 64;
@@ -193,10 +206,10 @@ __device__ __forceinline__ void fp_body(const FpLaunch &a, const int bx, const i
 #pragma unroll
             for (int j = 0; j < FP_PF; ++j) dst[j] = pf[j];
         };
-        auto step = [&](int l, const float (&src)[FP_PF], int ws) {
+        auto step = [&](int l, const RawT<TI> (&src)[FP_PF], int ws) {
             if (!ONES) {
 #pragma unroll
-                for (int j = 0; j < FP_PF; ++j) wl[lane + 64 * j] = src[j];
+                for (int j = 0; j < FP_PF; ++j) wl[lane + 64 * j] = from_raw<TI>(src[j]);
             }
             __builtin_amdgcn_wave_barrier();
             const float lcl = lc0 + (float)l;
@@ -242,7 +255,7 @@ __device__ __forceinline__ void fp_body(const FpLaunch &a, const int bx, const i
         const int wn = __builtin_amdgcn_readlane(wn_v, l - lb);
         if (!ONES) {
 #pragma unroll
-            for (int j = 0; j < FP_PF; ++j) wl[lane + 64 * j] = pf[j];
+            for (int j = 0; j < FP_PF; ++j) wl[lane + 64 * j] = from_raw<TI>(pf[j]);
         }
         // LDS operations of one wave complete in order: the window is readable by every lane below,
         // and the next line's stores cannot overtake these reads.
