@@ -75,6 +75,14 @@ __device__ __forceinline__ RawT<T> buf_raw(__amdgpu_buffer_rsrc_t rs, unsigned o
         return __builtin_amdgcn_raw_buffer_load_b16(rs, (int)off, 0, 0);
 }
 template <typename T>
+__device__ __forceinline__ RawT<T> ld_raw(const T *p, unsigned i)
+{
+    if constexpr (sizeof(T) == 4)
+        return p[i];
+    else
+        return __builtin_bit_cast(unsigned short, p[i]);
+}
+template <typename T>
 __device__ __forceinline__ float from_raw(RawT<T> u)
 {
     if constexpr (sizeof(T) == 4)
@@ -602,12 +610,15 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
                 nq = n > 0 && n <= BP_SWIN ? n + 1 : 0;
             }
             // staging of view ci: lane L loads entries 2L and 2L + 1; the running sum is formed on store
+            // (residuals are kept as their raw bits until stored, so that all of a view's loads are in
+            // flight together)
             struct Fetch {
                 float2 b0, b1;
-                float r0, r1;
+                RawT<TR> r0, r1;
+                float s0, s1;   // bin scales (modes whose residual is not prescaled)
             };
             auto fetch = [&](int ci) {
-                Fetch q = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), 0.f, 0.f};
+                Fetch q = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), 0, 0, 1.f, 1.f};
                 const int ne = __builtin_amdgcn_readlane(nq, ci);
                 if (ne == 0) return q;
                 const int kw0 = __builtin_amdgcn_readlane(wq.x, ci);
@@ -620,8 +631,14 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
                 const unsigned ks = v * (unsigned)nb + (unsigned)(kw0 + e0i);
                 if (e0i < ne) q.b0 = G.bnd[kb];
                 if (e1i < ne) q.b1 = G.bnd[kb + 1];
-                if (e0i < ne - 1) q.r0 = PRESCALED ? (float)r[kr] : (float)r[kr] * G.scale[ks];
-                if (e1i < ne - 1) q.r1 = PRESCALED ? (float)r[kr + 1] : (float)r[kr + 1] * G.scale[ks + 1];
+                if (e0i < ne - 1) {
+                    q.r0 = ld_raw<TR>(r, kr);
+                    if (!PRESCALED) q.s0 = G.scale[ks];
+                }
+                if (e1i < ne - 1) {
+                    q.r1 = ld_raw<TR>(r, kr + 1);
+                    if (!PRESCALED) q.s1 = G.scale[ks + 1];
+                }
                 return q;
             };
             auto put = [&](int ci, const Fetch &q) {
@@ -629,9 +646,10 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
                 if (ne == 0) return;
                 const float s = ld_uniform(G.sgn, (unsigned)(vstart + (wave + BP_GROUPS * (c0 + ci)) * vstride));
                 const int e0i = 2 * lane, e1i = e0i + 1;
-                const float p0 = wave_shift_up(wave_prefix_sum(q.r0 + q.r1));
-                if (e0i < ne) E[e0i] = make_float4(s * q.b0.x, s * q.b0.y, p0, q.r0);
-                if (e1i < ne) E[e1i] = make_float4(s * q.b1.x, s * q.b1.y, p0 + q.r0, q.r1);
+                const float r0 = from_raw<TR>(q.r0) * q.s0, r1 = from_raw<TR>(q.r1) * q.s1;
+                const float p0 = wave_shift_up(wave_prefix_sum(r0 + r1));
+                if (e0i < ne) E[e0i] = make_float4(s * q.b0.x, s * q.b0.y, p0, r0);
+                if (e1i < ne) E[e1i] = make_float4(s * q.b1.x, s * q.b1.y, p0 + r0, r1);
             };
             for (int ci = 0; ci < cn; ++ci) {
                 // LDS operations of one wave complete in order: the previous view's reads precede these
