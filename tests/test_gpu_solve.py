@@ -61,6 +61,13 @@ CFG1_CASES = [
     dict(alpha=1.999, subset_order="bitrev", kappa=True),
     dict(alpha=1.999, subset_order="bitrev", algorithm=2),
     dict(alpha=1.999, subset_order="sequential", kappa=True),
+    # fixed AL penalty (Section IV, rho = 0.05) with the proposed and the simple relaxation
+    dict(alpha=1.999, subset_order="bitrev", rho_mode="fixed", rho_fixed=0.05),
+    dict(alpha=1.999, subset_order="bitrev", rho_mode="fixed", rho_fixed=0.05, algorithm=2),
+    # the Fair potential of the paper's XCAT run, the maximum-curvature D_R, the full-gradient start
+    dict(alpha=1.5, subset_order="bitrev", potential="fair"),
+    dict(alpha=1.999, subset_order="bitrev", huber=False),
+    dict(alpha=1.999, subset_order="bitrev", init_full=True),
 ]
 
 
