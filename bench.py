@@ -418,6 +418,32 @@ def main():
                 except api.CtError as e:
                     relax[f"{name},rho={rho_mode}"] = {"error": str(e)[:80]}
 
+    # Ablations of the supplement (Section S-III / S-IV): alpha sweep with the continuation and with
+    # fixed rho 0.05 (12 subsets, 50 iterations); 1 vs 12 subsets over 360 subiterations with fixed rho
+    # 1/6 (relaxed) and 1/12 (unrelaxed); Huber vs maximum curvature for D_R. RMSD in HU to x*.
+    ablate = None
+    if os.path.exists(XSTAR) and not args.no_t1hu:
+        ablate = {}
+        G1 = api.Geometry(g.replace(nsubsets=1))
+
+        def run(Gx, niters, marks, **kw):
+            p = api.Params(niters=niters, subset_order=ORDER, start="fbp", fov_radius=synth.fov_radius(g), **kw)
+            try:
+                rows = api.rlalm_solve(Gx, p, y, w, x, x_ref=xstar, trace=True)
+            except api.CtError as e:
+                return {"error": str(e)[:80]}
+            return {str(r["iter"]): round(r["rmsd_hu"], 2) for r in rows if r["iter"] in marks}
+
+        for a in (1.0, 1.5, 1.999):
+            ablate[f"M=12,alpha={a},rho=continuation"] = run(G12, 50, (10, 20, 50), alpha=a)
+            ablate[f"M=12,alpha={a},rho=0.05"] = run(G12, 50, (10, 20, 50), alpha=a, rho_mode="fixed")
+        for a, rho in ((1.999, 1 / 6), (1.0, 1 / 12), (1.0, 1 / 6)):
+            ablate[f"M=1,alpha={a},rho={rho:.4f},360 subiterations"] = run(G1, 360, (60, 120, 360), alpha=a,
+                                                                            rho_mode="fixed", rho_fixed=rho)
+            ablate[f"M=12,alpha={a},rho={rho:.4f},360 subiterations"] = run(G12, 30, (5, 10, 30), alpha=a,
+                                                                             rho_mode="fixed", rho_fixed=rho)
+        ablate["M=12,alpha=1.999,D_R=maximum curvature"] = run(G12, 50, (10, 20, 50), alpha=1.999, huber=False)
+
     cpu = None
     if not args.no_cpu:
         cpu = oracle_baseline(g, s, args.cpu_iters)
@@ -447,6 +473,7 @@ def main():
         "wall_s": round(wall, 3),
         "time_to_1hu": t1hu,
         "relaxation_rmsd_hu_12_subsets": relax,
+        "ablations_rmsd_hu": ablate,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
