@@ -57,21 +57,24 @@ __device__ __forceinline__ const bf16 *src_ptr(const ConvSrc &S, int ci0, int n,
     return S.src1 + (((size_t)n * h + y) * w + x) * S.c1 + (ci0 - S.c0);
 }
 
-// 3x3 convolution, wave tile 32 output channels x 64 pixels, four waves per workgroup on consecutive
-// pixel blocks. FWD: out = relu(conv + bias). !FWD (input gradient): out = conv * (mask > 0) (mask
-// optional). Requires c_in, c_out multiples of 32. The pixel count n*h*w is arbitrary (deep levels of
-// small images hold a handful of pixels): lanes past the last pixel read the last pixel's data and
-// store nothing.
-template <bool FWD>
+// 3x3 convolution, wave tile 32 output channels x 64 pixels. KS = 1: four waves per workgroup on
+// consecutive pixel blocks. KS = 4 (layers with few tiles, the deep levels): the four waves share one
+// tile and split the (tap, 32-channel chunk) steps into quarters; their partial tiles are added in LDS in
+// a fixed order, wave w finishing pixel sub-block w. FWD: out = relu(conv + bias). !FWD (input gradient):
+// out = conv * (mask > 0) (mask optional). Requires c_in, c_out multiples of 32. The pixel count n*h*w
+// is arbitrary (deep levels of small images hold a handful of pixels): lanes past the last pixel read
+// the last pixel's data and store nothing.
+template <bool FWD, int KS>
 __global__ __launch_bounds__(256) void k_conv3x3(ConvSrc S, const bf16 *__restrict__ wt, const float *__restrict__ bias,
                                                  const bf16 *__restrict__ mask, bf16 *__restrict__ out, int n, int h,
                                                  int w, int cout)
 {
+    __shared__ f32x4 red[KS > 1 ? KS * 8 * 64 : 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int cin = S.c0 + S.c1;
     const int hw = h * w, npix = n * hw;
-    const int p0 = (blockIdx.x * 4 + wave) * 64;
-    if (p0 >= npix) return;
+    const int p0 = KS > 1 ? blockIdx.x * 64 : (blockIdx.x * 4 + wave) * 64;
+    if (p0 >= npix) return;   // (KS > 1: the same for every wave of the workgroup)
     const int co0 = blockIdx.y * 32;
     const int g = lane >> 4, r = lane & 15;
     int pn[4], py[4], px[4];
@@ -89,7 +92,11 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvSrc S, const bf16 *__restri
 #pragma unroll
         for (int s = 0; s < 4; ++s) acc[m][s] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bf16x8 zero8 = {};
-    for (int tap = 0; tap < 9; ++tap) {
+    // steps (tap, chunk) in the order tap-major; this wave's range
+    const int nch = cin / 32, T = 9 * nch;
+    const int it0 = KS > 1 ? (wave * T) / KS : 0, it1 = KS > 1 ? ((wave + 1) * T) / KS : T;
+    for (int it = it0; it < it1; ++it) {
+        const int tap = it / nch, ci0 = (it - tap * nch) * 32;
         const int dy = tap / 3 - 1, dx = tap % 3 - 1;
         int ny_[4], nx_[4];
         bool ok[4];
@@ -100,30 +107,43 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvSrc S, const bf16 *__restri
             ny_[s] = ok[s] ? yy : py[s];   // in-range address for masked lanes
             nx_[s] = ok[s] ? xx : px[s];
         }
-        for (int ci0 = 0; ci0 < cin; ci0 += 32) {
-            bf16x8 a[2], b[4];
+        bf16x8 a[2], b[4];
 #pragma unroll
-            for (int m = 0; m < 2; ++m)
-                a[m] = *reinterpret_cast<const bf16x8 *>(wt + ((size_t)(co0 + 16 * m + r) * 9 + tap) * cin + ci0 + 8 * g);
+        for (int m = 0; m < 2; ++m)
+            a[m] = *reinterpret_cast<const bf16x8 *>(wt + ((size_t)(co0 + 16 * m + r) * 9 + tap) * cin + ci0 + 8 * g);
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const bf16x8 v = *reinterpret_cast<const bf16x8 *>(src_ptr(S, ci0, pn[s], ny_[s], nx_[s], h, w) + 8 * g);
-                b[s] = ok[s] ? v : zero8;
-            }
+        for (int s = 0; s < 4; ++s) {
+            const bf16x8 v = *reinterpret_cast<const bf16x8 *>(src_ptr(S, ci0, pn[s], ny_[s], nx_[s], h, w) + 8 * g);
+            b[s] = ok[s] ? v : zero8;
+        }
 #pragma unroll
-            for (int m = 0; m < 2; ++m)
+        for (int m = 0; m < 2; ++m)
 #pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    acc[m][s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[s], acc[m][s], 0, 0, 0);
+            for (int s = 0; s < 4; ++s)
+                acc[m][s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[s], acc[m][s], 0, 0, 0);
+    }
+    if (KS > 1) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) red[((wave * 2 + m) * 4 + s) * 64 + lane] = acc[m][s];
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            f32x4 t = red[((0 * 2 + m) * 4 + wave) * 64 + lane];
+#pragma unroll
+            for (int k = 1; k < KS; ++k) t += red[((k * 2 + m) * 4 + wave) * 64 + lane];
+            acc[m][0] = t;   // this wave's pixel sub-block, held in slot 0
         }
     }
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
         const int co = co0 + 16 * m + 4 * g;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            if (p0 + 16 * s + r >= npix) continue;
-            const size_t o = (size_t)(p0 + 16 * s + r) * cout + co;
+        for (int s = 0; s < (KS > 1 ? 1 : 4); ++s) {
+            const int sb = KS > 1 ? wave : s;   // pixel sub-block
+            if (p0 + 16 * sb + r >= npix) continue;
+            const size_t o = (size_t)(p0 + 16 * sb + r) * cout + co;
             bf16x4 v;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -616,6 +636,10 @@ ct_status ensure_part(ct_unet *u, size_t n)
     return fail(CT_ERR_HIP, "internal: partial-sum buffer too small");
 }
 
+// The deep levels have too few 32 x 64 output tiles to fill the device: split each tile's steps over
+// four waves when the tiles number fewer than 2048 (eight waves per CU).
+bool split_k(size_t npix, int cout) { return ((npix + 63) / 64) * (size_t)(cout / 32) < 2048; }
+
 ConvSrc one(const bf16 *src, int c) { return ConvSrc{src, c, 0, nullptr, 0}; }
 ConvSrc cat(const bf16 *low, int cl, const bf16 *skip, int cs) { return ConvSrc{low, cl, 1, skip, cs}; }
 
@@ -623,9 +647,14 @@ hipError_t conv_fwd(const ct_unet *u, int l, const ConvSrc &S, bf16 *out, int n,
 {
     const int cout = kShape[l][1];
     const size_t npix = (size_t)n * h * w;
-    dim3 grid(blocks(npix, 256), cout / 32);
-    hipLaunchKernelGGL(k_conv3x3<true>, grid, dim3(256), 0, s, S, u->wf[l], u->theta + u->off[l] + (size_t)cout * kShape[l][0] * 9,
-                       nullptr, out, n, h, w, cout);
+    const float *bias = u->theta + u->off[l] + (size_t)cout * kShape[l][0] * 9;
+    if (split_k(npix, cout)) {
+        dim3 grid(blocks(npix, 64), cout / 32);
+        hipLaunchKernelGGL((k_conv3x3<true, 4>), grid, dim3(256), 0, s, S, u->wf[l], bias, nullptr, out, n, h, w, cout);
+    } else {
+        dim3 grid(blocks(npix, 256), cout / 32);
+        hipLaunchKernelGGL((k_conv3x3<true, 1>), grid, dim3(256), 0, s, S, u->wf[l], bias, nullptr, out, n, h, w, cout);
+    }
     return hipGetLastError();
 }
 
@@ -635,8 +664,15 @@ hipError_t conv_dgrad(const ct_unet *u, int l, const bf16 *dz, const bf16 *act, 
 {
     const int cin = kShape[l][0], cout = kShape[l][1];
     const size_t npix = (size_t)n * h * w;
-    dim3 grid(blocks(npix, 256), cin / 32);
-    hipLaunchKernelGGL(k_conv3x3<false>, grid, dim3(256), 0, s, one(dz, cout), u->wb[l], nullptr, act, out, n, h, w, cin);
+    if (split_k(npix, cin)) {
+        dim3 grid(blocks(npix, 64), cin / 32);
+        hipLaunchKernelGGL((k_conv3x3<false, 4>), grid, dim3(256), 0, s, one(dz, cout), u->wb[l], nullptr, act, out, n,
+                           h, w, cin);
+    } else {
+        dim3 grid(blocks(npix, 256), cin / 32);
+        hipLaunchKernelGGL((k_conv3x3<false, 1>), grid, dim3(256), 0, s, one(dz, cout), u->wb[l], nullptr, act, out, n,
+                           h, w, cin);
+    }
     return hipGetLastError();
 }
 
