@@ -6,6 +6,8 @@ iterations. Cases: cfg1 (128^2, 220 views, M = 10, 20 iterations) for alpha = 1 
 element-wise on x, g and h; the state interface (init / iterate, checkpoint-resume) and graph replay
 compared bitwise against the plain launches.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -181,3 +183,26 @@ def test_solve_parity_cfg2_first_iterations(api, alpha):
     d = hu_rmsd(xg, xo, mask)
     say(f"  RMSD(gpu, oracle) = {d:.4f} HU")
     assert d <= 0.5
+
+
+RAGGED = {
+    # sizes that are not multiples of the 16 x 16 update tile or of the 64-bin projection block, an
+    # off-centre detector, and 6 subsets of 6 views
+    "ragged": synth.ScanGeometry(nx=77, ny=53, dx=1.1, dy=0.8, nb=131, du=1.3, u_offset=-0.25, det="flat",
+                                 nviews=36, beta0=0.05, span=2 * math.pi, dso=300.0, dsd=600.0, nsubsets=6),
+    "arc_cfg1": synth.CFG1.replace(det="arc"),
+}
+
+
+@pytest.mark.parametrize("name", list(RAGGED))
+def test_solve_parity_ragged_and_arc(api, name):
+    g = RAGGED[name]
+    s = scan(g, 7)
+    x0 = np.zeros((g.ny, g.nx), dtype=np.float32)
+    case = dict(alpha=1.999, subset_order="bitrev", niters=10)
+    xg = gpu_solve(api, g, s, x0, **case)
+    xo = oracle_solve(g, s, x0.astype(np.float64), **case)
+    mask = oracle.fov_mask(g, synth.fov_radius(g))
+    d = hu_rmsd(xg, xo, mask)
+    say(f"[solve {name}] RMSD(gpu, oracle) = {d:.4f} HU over {int(mask.sum())} FOV pixels")
+    assert mask.sum() > 100 and d <= 0.5
