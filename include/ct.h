@@ -114,7 +114,8 @@ typedef struct {
     int niters;          /* outer iterations; each is M subiterations (one full projection pair)     */
     int rho_mode;        /* 0: continuation rho_k(alpha) with k the subiteration count, 1: fixed    */
     double rho_fixed;    /* rho when rho_mode == 1, > 0                                              */
-    int potential;       /* 0: hyperbola d^2 (sqrt(1 + (t/d)^2) - 1), 1: Fair d^2 (|t/d| - log(1+|t/d|)) */
+    int potential;       /* 0: hyperbola d^2 (sqrt(1 + (t/d)^2) - 1), 1: Fair d^2 (|t/d| - log(1+|t/d|)),
+                            2: q-GGMRF (p = 2, q = 1.2) t^2 / (2 (1 + |t/d|^0.8))                     */
     double delta, beta;  /* potential scale (mm^-1) and regularization strength; beta_i = beta/|s_i| */
     int huber;           /* 1: Huber curvature for D_R (the paper's choice), 0: maximum curvature   */
     int algorithm;       /* 1: Algorithm 1 (proposed relaxation), 2: Algorithm 2 (simple relaxation) */

@@ -171,7 +171,7 @@ def row_sweep(g, v: int) -> bool:
     return bool(lib().or_row_sweep(ctypes.byref(G), v))
 
 
-POTENTIALS = {"hyperbola": 0, "fair": 1}
+POTENTIALS = {"hyperbola": 0, "fair": 1, "qggmrf": 2}
 
 
 def reg_cost(x, potential="hyperbola", delta=1e-4, beta=1024.0) -> float:

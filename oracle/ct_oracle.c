@@ -259,33 +259,42 @@ void or_line_boundaries(const or_geom *g, int v, int l, double *b)
 /* Regularizer: R(x) = sum_i beta_i sum_n phi([C_i x]_n)                                             */
 /* Four directions (0,1), (1,0), (1,1), (1,-1) in (row, col) offsets, beta_i = beta / ||s_i||,       */
 /* kappa = 1, a difference exists only when both pixels are inside the image.                        */
-/* potential 0 = hyperbola delta^2 (sqrt(1 + (t/delta)^2) - 1), 1 = Fair delta^2 (|t/d| - log(1+|t/d|)) */
+/* potential 0 = hyperbola delta^2 (sqrt(1 + (t/delta)^2) - 1), 1 = Fair delta^2 (|t/d| - log(1+|t/d|)), */
+/* 2 = q-GGMRF with p = 2, q = 1.2 (the q-generalized Gaussian MRF the paper's chest-scan experiment    */
+/* cites, in its published form): |t|^2 / (2 (1 + |t/d|^(p-q))), t^2/2 near 0 like the other two.       */
 /* ------------------------------------------------------------------------------------------------ */
 
 static const int DIR_DI[4] = {0, 1, 1, 1};
 static const int DIR_DJ[4] = {1, 0, 1, -1};
+
+#define QGG_Q 1.2
 
 static double pot(int kind, double d, double t)
 {
     double z = t / d;
     if (kind == 0) return d * d * (sqrt(1.0 + z * z) - 1.0);
     double a = fabs(z);
-    return d * d * (a - log1p(a));
+    if (kind == 1) return d * d * (a - log1p(a));
+    return 0.5 * t * t / (1.0 + pow(a, 2.0 - QGG_Q));
+}
+
+/* Huber curvature phi'(t)/t (its limit 1 at t = 0). For the q-GGMRF, with s = |t/d|^(2-q):
+   phi'(t) = t (2 + q s) / (2 (1 + s)^2). */
+static double wpot(int kind, double d, double t)
+{
+    double z = t / d;
+    if (kind == 0) return 1.0 / sqrt(1.0 + z * z);
+    if (kind == 1) return 1.0 / (1.0 + fabs(z));
+    double s = pow(fabs(z), 2.0 - QGG_Q);
+    return (2.0 + QGG_Q * s) / (2.0 * (1.0 + s) * (1.0 + s));
 }
 
 static double dpot(int kind, double d, double t)
 {
     double z = t / d;
     if (kind == 0) return t / sqrt(1.0 + z * z);
-    return t / (1.0 + fabs(z));
-}
-
-/* Huber curvature phi'(t)/t (its limit 1 at t = 0) */
-static double wpot(int kind, double d, double t)
-{
-    double z = t / d;
-    if (kind == 0) return 1.0 / sqrt(1.0 + z * z);
-    return 1.0 / (1.0 + fabs(z));
+    if (kind == 1) return t / (1.0 + fabs(z));
+    return t * wpot(kind, d, t);
 }
 
 static double dir_beta(double beta, int i) { return i < 2 ? beta : beta / sqrt(2.0); }
@@ -446,7 +455,7 @@ typedef struct {
     int nsubsets;       /* M */
     int rho_mode;       /* 0 continuation, 1 fixed */
     double rho_fixed;
-    int potential;      /* 0 hyperbola, 1 Fair */
+    int potential;      /* 0 hyperbola, 1 Fair, 2 q-GGMRF */
     double delta, beta;
     int huber;          /* 1 Huber curvature D_R (the paper's choice), 0 maximum curvature */
     int algorithm;      /* 1 proposed (with h), 2 simple */

@@ -88,7 +88,7 @@ class Params:
     niters: int = 20
     rho_mode: str = "continuation"   # or "fixed"
     rho_fixed: float = 0.05
-    potential: str = "hyperbola"     # or "fair"
+    potential: str = "hyperbola"     # or "fair", "qggmrf"
     delta: float = 1e-4
     beta: float = 1024.0
     huber: bool = True
@@ -111,7 +111,7 @@ class Params:
         p.niters = self.niters
         p.rho_mode = {"continuation": 0, "fixed": 1}[self.rho_mode]
         p.rho_fixed = self.rho_fixed
-        p.potential = {"hyperbola": 0, "fair": 1}[self.potential]
+        p.potential = {"hyperbola": 0, "fair": 1, "qggmrf": 2}[self.potential]
         p.delta = self.delta
         p.beta = self.beta
         p.huber = int(self.huber)

@@ -85,7 +85,7 @@ ct_status check_params(const ct_rlalm_params *p)
     if (p->niters < 0) return fail(CT_ERR_INVALID_ARG, "niters must be >= 0");
     if (p->rho_mode != 0 && p->rho_mode != 1) return fail(CT_ERR_INVALID_ARG, "rho_mode must be 0 or 1");
     if (p->rho_mode == 1 && !(p->rho_fixed > 0)) return fail(CT_ERR_INVALID_ARG, "rho_fixed must be > 0");
-    if (p->potential != 0 && p->potential != 1) return fail(CT_ERR_INVALID_ARG, "potential must be 0 or 1");
+    if (p->potential < 0 || p->potential > 2) return fail(CT_ERR_INVALID_ARG, "potential must be 0, 1 or 2");
     if (!(p->delta > 0) || !(p->beta >= 0)) return fail(CT_ERR_INVALID_ARG, "need delta > 0, beta >= 0");
     if (p->algorithm != 1 && p->algorithm != 2) return fail(CT_ERR_INVALID_ARG, "algorithm must be 1 or 2");
     if (p->subset_order != CT_ORDER_SEQUENTIAL && p->subset_order != CT_ORDER_BITREV)

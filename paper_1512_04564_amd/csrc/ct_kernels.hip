@@ -513,8 +513,12 @@ __device__ __forceinline__ void pot_terms(int potential, float delta, float t, f
     const float z = t / delta;
     if (potential == 0) {
         omega = rsqrtf(fmaf(z, z, 1.f));
-    } else {
+    } else if (potential == 1) {
         omega = 1.f / (1.f + fabsf(z));
+    } else {   // q-GGMRF, p = 2, q = 1.2: s = |z|^0.8 (0 at z = 0: exp2(-inf))
+        const float s = exp2f(0.8f * log2f(fabsf(z)));
+        const float u = 1.f + s;
+        omega = fmaf(1.2f, s, 2.f) / (2.f * u * u);
     }
     dphi = t * omega;
 }

@@ -226,8 +226,10 @@ class Scan:
 
 
 def noisy_scan(g: ScanGeometry, seed: int, *, i0: float = 1e5, sigma: float = 5.0, n_ellipses: int = 8,
-               truth: bool = True) -> Scan:
-    """One seeded scan: Poisson(I0 e^-l) + N(0, sigma^2) counts, clamped at 1, log, weights Y^2/(Y+25).
+               truth: bool = True, weights: str = "counts") -> Scan:
+    """One seeded scan: Poisson(I0 e^-l) + N(0, sigma^2) counts, clamped at 1, log, weights Y^2/(Y+25)
+    (``weights="counts"``) or exp(-y) = Y/I0 (``weights="exp"``, the statistical weights of the paper's
+    simulated scan; a scale of about 1/I0 against the default, so beta scales with them).
 
     ``y`` and ``w`` are rounded to float32; every consumer (GPU path and oracle) reads the same values.
     """
@@ -237,7 +239,10 @@ def noisy_scan(g: ScanGeometry, seed: int, *, i0: float = 1e5, sigma: float = 5.
     counts = rng.poisson(i0 * np.exp(-li)).astype(np.float64) + rng.normal(0.0, sigma, li.shape)
     counts = np.maximum(counts, 1.0)
     y = np.log(i0 / counts).astype(np.float32)
-    w = (counts * counts / (counts + sigma * sigma)).astype(np.float32)
+    if weights == "exp":
+        w = np.exp(-y.astype(np.float64)).astype(np.float32)
+    else:
+        w = (counts * counts / (counts + sigma * sigma)).astype(np.float32)
     img = phantom_image(g, ell) if truth else None
     return Scan(g, seed, y, w, img, li, ell)
 

@@ -206,3 +206,39 @@ def test_solve_parity_ragged_and_arc(api, name):
     d = hu_rmsd(xg, xo, mask)
     say(f"[solve {name}] RMSD(gpu, oracle) = {d:.4f} HU over {int(mask.sum())} FOV pixels")
     assert mask.sum() > 100 and d <= 0.5
+
+
+def test_solve_parity_exp_weights(api):
+    """Statistical weights w = exp(-y) (the paper's simulated scan), about 1/I0 of the default weights, with
+    beta scaled alike (1024 / 1e5)."""
+    g = synth.CFG1
+    s = synth.noisy_scan(g, 3, weights="exp")
+    x0 = np.zeros((g.ny, g.nx), dtype=np.float32)
+    case = dict(alpha=1.999, subset_order="bitrev", niters=20, beta=1024.0 / 1e5)
+    xg = gpu_solve(api, g, s, x0, **case)
+    xo = oracle_solve(g, s, x0.astype(np.float64), **case)
+    mask = oracle.fov_mask(g, synth.fov_radius(g))
+    d = hu_rmsd(xg, xo, mask)
+    say(f"[solve exp weights] RMSD(gpu, oracle) = {d:.4f} HU; RMSD(oracle, truth) = {hu_rmsd(xo, s.truth, mask):.2f} HU")
+    assert d <= 0.5
+
+
+def test_solve_parity_potentials(api):
+    """The three potentials (hyperbola, Fair, q-GGMRF with p = 2, q = 1.2) with a strong regularizer
+    (beta = 1e6), where their images differ from each other by more than 0.3 HU: the GPU must match the
+    oracle's result for the same potential to 0.05 HU, well inside that separation (the 0.5 HU bar of the
+    other cases would not tell the potentials apart)."""
+    g = synth.CFG1
+    s = scan(g, 0)
+    x0 = np.zeros((g.ny, g.nx), dtype=np.float32)
+    mask = oracle.fov_mask(g, synth.fov_radius(g))
+    xo = {}
+    for pot in ("hyperbola", "fair", "qggmrf"):
+        case = dict(alpha=1.999, subset_order="bitrev", niters=20, beta=1e6, potential=pot)
+        xg = gpu_solve(api, g, s, x0, **case)
+        xo[pot] = oracle_solve(g, s, x0.astype(np.float64), **case)
+        d = hu_rmsd(xg, xo[pot], mask)
+        say(f"[solve potential {pot}, beta 1e6] RMSD(gpu, oracle) = {d:.4f} HU")
+        assert d <= 0.05
+    for a, b in (("hyperbola", "fair"), ("hyperbola", "qggmrf"), ("fair", "qggmrf")):
+        assert hu_rmsd(xo[a], xo[b], mask) > 0.3, (a, b)

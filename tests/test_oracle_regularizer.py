@@ -24,7 +24,7 @@ def laplacian(x, beta):
     return out
 
 
-@pytest.mark.parametrize("potential", ["hyperbola", "fair"])
+@pytest.mark.parametrize("potential", ["hyperbola", "fair", "qggmrf"])
 def test_gradient_matches_finite_differences(potential):
     rng = np.random.default_rng(1)
     x = rng.uniform(0.01, 0.03, (9, 11))
@@ -40,7 +40,7 @@ def test_gradient_matches_finite_differences(potential):
         assert abs(fd - gr[i, j]) <= 1e-6 * max(abs(gr[i, j]), beta * delta)
 
 
-@pytest.mark.parametrize("potential", ["hyperbola", "fair"])
+@pytest.mark.parametrize("potential", ["hyperbola", "fair", "qggmrf"])
 @pytest.mark.parametrize("huber", [True, False])
 def test_sqs_majorizes(potential, huber):
     """R(z) <= R(x) + grad R(x)'(z - x) + 1/2 ||z - x||^2_{D_R(x)} (Section II, majorization condition)."""
@@ -72,3 +72,29 @@ def test_curvature_closed_form_at_constant_image():
     assert abs(dr[2, 3] - interior) < 1e-9 * interior
     assert abs(dr[0, 0] - corner) < 1e-9 * corner
     assert abs(dr[0, 3] - edge) < 1e-9 * edge
+
+
+def pair_gradient(potential, delta, t):
+    """phi'(t) through the oracle: R of the 1 x 2 image (0, t) is beta phi(-t) over the one horizontal pair,
+    so its gradient at the second pixel is beta phi'(t)."""
+    gr, dr = oracle.reg_grad(np.array([[0.0, t]]), potential, delta, 1.0)
+    return gr[0, 1], dr[0, 1]
+
+
+@pytest.mark.parametrize("potential", ["hyperbola", "fair", "qggmrf"])
+def test_potentials_are_quadratic_near_zero(potential):
+    """Every potential is t^2 / 2 to second order (Huber curvature 1 at t = 0): the same scale of delta."""
+    d = 1e-3
+    g, dr = pair_gradient(potential, d, 1e-9 * d)
+    assert abs(g / (1e-9 * d) - 1.0) < 1e-6
+    assert abs(dr - 2.0) < 1e-6   # D_R = 2 beta omega for the one pair
+
+
+def test_qggmrf_tail_exponent():
+    """q-GGMRF with p = 2, q = 1.2: phi'(t) grows like t^(q-1) for |t| >> delta (the published form's
+    large-difference behaviour, q the exponent of the edge-preserving tail)."""
+    d = 1e-3
+    g1, _ = pair_gradient("qggmrf", d, 1e6 * d)
+    g2, _ = pair_gradient("qggmrf", d, 1e7 * d)
+    slope = math.log(g2 / g1) / math.log(10.0)
+    assert abs(slope - 0.2) < 2e-3
