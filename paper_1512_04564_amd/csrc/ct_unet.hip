@@ -157,6 +157,84 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvSrc S, const bf16 *__restri
     }
 }
 
+// The same 3x3 convolution for large images, with the input staged in LDS: a workgroup computes 32 output
+// channels of a 16 x 16 pixel tile (wave w: tile rows 4w .. 4w + 3, one 16-pixel row per operand block).
+// For each 32-channel chunk the 18 x 18 input tile (one-pixel halo, zero outside the image) is loaded
+// once into LDS, 64 bytes per pixel, and the nine taps read their 16-byte fragments from there, so each
+// input value is read from memory once per chunk instead of once per tap and wave. Weight fragments are
+// read from memory as before. FWD / !FWD as in k_conv3x3. Images of n planes; grid (tiles, c_out / 32).
+constexpr int CT_T = 16;                     // tile edge (pixels)
+constexpr int CT_H = CT_T + 2;               // with halo
+template <bool FWD>
+__global__ __launch_bounds__(256) void k_conv3x3_tile(ConvSrc S, const bf16 *__restrict__ wt,
+                                                      const float *__restrict__ bias, const bf16 *__restrict__ mask,
+                                                      bf16 *__restrict__ out, int n, int h, int w, int cout)
+{
+    __shared__ bf16x8 tile[CT_H * CT_H * 4];   // [hy][hx][8-channel group]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int cin = S.c0 + S.c1;
+    const int tx = (w + CT_T - 1) / CT_T, ty = (h + CT_T - 1) / CT_T;
+    int t = blockIdx.x;
+    const int tix = t % tx;
+    t /= tx;
+    const int tiy = t % ty;
+    const int pn = t / ty;
+    const int x0 = tix * CT_T, y0 = tiy * CT_T;
+    const int co0 = blockIdx.y * 32;
+    const int g = lane >> 4, r = lane & 15;
+    f32x4 acc[2][4];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc[m][s] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16x8 zero8 = {};
+    for (int ci0 = 0; ci0 < cin; ci0 += 32) {
+        __syncthreads();   // the previous chunk's reads are done
+        for (int v = threadIdx.x; v < CT_H * CT_H * 4; v += 256) {
+            const int px = v >> 2, part = v & 3;
+            const int yy = y0 - 1 + px / CT_H, xx = x0 - 1 + px % CT_H;
+            bf16x8 val = zero8;
+            if (yy >= 0 && yy < h && xx >= 0 && xx < w)
+                val = *reinterpret_cast<const bf16x8 *>(src_ptr(S, ci0 + 8 * part, pn, yy, xx, h, w));
+            tile[v] = val;
+        }
+        __syncthreads();
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3, dx = tap % 3;   // offsets into the haloed tile
+            bf16x8 a[2], b[4];
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+                a[m] = *reinterpret_cast<const bf16x8 *>(wt + ((size_t)(co0 + 16 * m + r) * 9 + tap) * cin + ci0 + 8 * g);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) b[s] = tile[((4 * wave + s + dy) * CT_H + r + dx) * 4 + g];
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    acc[m][s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[s], acc[m][s], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const int co = co0 + 16 * m + 4 * g;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int yy = y0 + 4 * wave + s, xx = x0 + r;
+            if (yy >= h || xx >= w) continue;
+            const size_t o = (((size_t)pn * h + yy) * w + xx) * cout + co;
+            bf16x4 v;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                float tv = acc[m][s][j];
+                if (FWD) tv = fmaxf(tv + bias[co + j], 0.f);
+                else if (mask) tv = (float)mask[o + j] > 0.f ? tv : 0.f;
+                v[j] = (bf16)tv;
+            }
+            *reinterpret_cast<bf16x4 *>(out + o) = v;
+        }
+    }
+}
+
 // Weight gradient partials of a 3x3 convolution: part[split][c_out][tap][c_in] over the pixels
 // [split * pps, min((split + 1) * pps, npix)) (pps a multiple of 32; the last chunk of 32 may be
 // partial, its missing pixels count as zero). One wave per (split, tap, 32 x 32 channel block); grid
@@ -640,6 +718,10 @@ ct_status ensure_part(ct_unet *u, size_t n)
 // four waves when the tiles number fewer than 2048 (eight waves per CU).
 bool split_k(size_t npix, int cout) { return ((npix + 63) / 64) * (size_t)(cout / 32) < 2048; }
 
+// Large images use the LDS-tiled form (16 x 16 tiles); it needs enough tiles to fill the device.
+int tiles16(int e) { return (e + 15) / 16; }
+bool use_tile(int n, int h, int w, int cout) { return (size_t)n * tiles16(h) * tiles16(w) * (cout / 32) >= 512; }
+
 ConvSrc one(const bf16 *src, int c) { return ConvSrc{src, c, 0, nullptr, 0}; }
 ConvSrc cat(const bf16 *low, int cl, const bf16 *skip, int cs) { return ConvSrc{low, cl, 1, skip, cs}; }
 
@@ -648,7 +730,10 @@ hipError_t conv_fwd(const ct_unet *u, int l, const ConvSrc &S, bf16 *out, int n,
     const int cout = kShape[l][1];
     const size_t npix = (size_t)n * h * w;
     const float *bias = u->theta + u->off[l] + (size_t)cout * kShape[l][0] * 9;
-    if (split_k(npix, cout)) {
+    if (use_tile(n, h, w, cout)) {
+        dim3 grid(n * tiles16(h) * tiles16(w), cout / 32);
+        hipLaunchKernelGGL(k_conv3x3_tile<true>, grid, dim3(256), 0, s, S, u->wf[l], bias, nullptr, out, n, h, w, cout);
+    } else if (split_k(npix, cout)) {
         dim3 grid(blocks(npix, 64), cout / 32);
         hipLaunchKernelGGL((k_conv3x3<true, 4>), grid, dim3(256), 0, s, S, u->wf[l], bias, nullptr, out, n, h, w, cout);
     } else {
@@ -664,7 +749,11 @@ hipError_t conv_dgrad(const ct_unet *u, int l, const bf16 *dz, const bf16 *act, 
 {
     const int cin = kShape[l][0], cout = kShape[l][1];
     const size_t npix = (size_t)n * h * w;
-    if (split_k(npix, cin)) {
+    if (use_tile(n, h, w, cin)) {
+        dim3 grid(n * tiles16(h) * tiles16(w), cin / 32);
+        hipLaunchKernelGGL(k_conv3x3_tile<false>, grid, dim3(256), 0, s, one(dz, cout), u->wb[l], nullptr, act, out, n,
+                           h, w, cin);
+    } else if (split_k(npix, cin)) {
         dim3 grid(blocks(npix, 64), cin / 32);
         hipLaunchKernelGGL((k_conv3x3<false, 4>), grid, dim3(256), 0, s, one(dz, cout), u->wb[l], nullptr, act, out, n,
                            h, w, cin);
