@@ -161,8 +161,9 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvSrc S, const bf16 *__restri
 // channels of a 16 x 16 pixel tile (wave w: tile rows 4w .. 4w + 3, one 16-pixel row per operand block).
 // For each 32-channel chunk the 18 x 18 input tile (one-pixel halo, zero outside the image) is loaded
 // once into LDS, 64 bytes per pixel, and the nine taps read their 16-byte fragments from there, so each
-// input value is read from memory once per chunk instead of once per tap and wave. Weight fragments are
-// read from memory as before. FWD / !FWD as in k_conv3x3. Images of n planes; grid (tiles, c_out / 32).
+// input value is read from memory once per chunk instead of once per tap and wave; the chunk's weights
+// are staged alike, once per workgroup. FWD / !FWD as in k_conv3x3. Images of n planes; grid (tiles,
+// c_out / 32).
 constexpr int CT_T = 16;                     // tile edge (pixels)
 constexpr int CT_H = CT_T + 2;               // with halo
 template <bool FWD>
@@ -171,6 +172,8 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvSrc S, const bf16 *__r
                                                       bf16 *__restrict__ out, int n, int h, int w, int cout)
 {
     __shared__ bf16x8 tile[CT_H * CT_H * 4];   // [hy][hx][8-channel group]
+    constexpr int WP = 9 * 4 + 1;              // weight row pitch (16-byte units), padded against bank conflicts
+    __shared__ bf16x8 wts[32 * WP];            // [c_out of the block][tap][8-channel group]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int cin = S.c0 + S.c1;
     const int tx = (w + CT_T - 1) / CT_T, ty = (h + CT_T - 1) / CT_T;
@@ -198,13 +201,17 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvSrc S, const bf16 *__r
                 val = *reinterpret_cast<const bf16x8 *>(src_ptr(S, ci0 + 8 * part, pn, yy, xx, h, w));
             tile[v] = val;
         }
+        for (int v = threadIdx.x; v < 32 * 9 * 4; v += 256) {   // the chunk's weights, staged alike
+            const int co = v / 36, rem = v % 36;
+            wts[co * WP + rem] = *reinterpret_cast<const bf16x8 *>(wt + ((size_t)(co0 + co) * 9 + rem / 4) * cin + ci0 +
+                                                                   8 * (rem % 4));
+        }
         __syncthreads();
         for (int tap = 0; tap < 9; ++tap) {
             const int dy = tap / 3, dx = tap % 3;   // offsets into the haloed tile
             bf16x8 a[2], b[4];
 #pragma unroll
-            for (int m = 0; m < 2; ++m)
-                a[m] = *reinterpret_cast<const bf16x8 *>(wt + ((size_t)(co0 + 16 * m + r) * 9 + tap) * cin + ci0 + 8 * g);
+            for (int m = 0; m < 2; ++m) a[m] = wts[(16 * m + r) * WP + tap * 4 + g];
 #pragma unroll
             for (int s = 0; s < 4; ++s) b[s] = tile[((4 * wave + s + dy) * CT_H + r + dx) * 4 + g];
 #pragma unroll
