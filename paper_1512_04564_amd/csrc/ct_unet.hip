@@ -727,7 +727,7 @@ bool split_k(size_t npix, int cout) { return ((npix + 63) / 64) * (size_t)(cout 
 
 // Large images use the LDS-tiled form (16 x 16 tiles); it needs enough tiles to fill the device.
 int tiles16(int e) { return (e + 15) / 16; }
-bool use_tile(int n, int h, int w, int cout) { return (size_t)n * tiles16(h) * tiles16(w) * (cout / 32) >= 512; }
+bool use_tile(int n, int h, int w, int cout) { return (size_t)n * tiles16(h) * tiles16(w) * (cout / 32) >= 256; }
 
 ConvSrc one(const bf16 *src, int c) { return ConvSrc{src, c, 0, nullptr, 0}; }
 ConvSrc cat(const bf16 *low, int cl, const bf16 *skip, int cs) { return ConvSrc{low, cl, 1, skip, cs}; }
