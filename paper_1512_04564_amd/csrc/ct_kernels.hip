@@ -508,12 +508,13 @@ __device__ __forceinline__ T wave_shift_up(T v)
     return dpp_or_zero<0x138, 0xF>(v);   // wave_shr:1
 }
 
-__device__ __forceinline__ void pot_terms(int potential, float delta, float t, float &dphi, float &omega)
+template <int POT>
+__device__ __forceinline__ void pot_terms(float delta, float t, float &dphi, float &omega)
 {
     const float z = t / delta;
-    if (potential == 0) {
+    if (POT == 0) {
         omega = rsqrtf(fmaf(z, z, 1.f));
-    } else if (potential == 1) {
+    } else if (POT == 1) {
         omega = 1.f / (1.f + fabsf(z));
     } else {   // q-GGMRF, p = 2, q = 1.2: s = |z|^0.8 (0 at z = 0: exp2(-inf))
         const float s = exp2f(0.8f * log2f(fabsf(z)));
@@ -562,6 +563,30 @@ constexpr int BP_NT = BP_TX * BP_TY;
 constexpr int BP_GROUPS = 8;    // view groups (waves) per workgroup
 constexpr int BP_SWIN = 125;    // widest window staged (bins); wider ones read the tables directly
 constexpr int BP_SLOT = 128;    // staged entries per view (n + 1 for a window of n bins)
+
+// Regularizer gradient and Huber curvature at pixel (i, j) of value xc: the pair terms of the 8 neighbours
+// (4 directions, each pair seen from both sides) with potential POT, weighted by beta and the kappa factors.
+template <int POT>
+__device__ __forceinline__ void reg_stencil(const UpdateArgs &U, int i, int j, int nx, int ny, size_t idx,
+                                            float xc, float &gr, float &dr)
+{
+    gr = 0.f;
+    dr = 0.f;
+    const float kc = U.kappa ? U.kappa[idx] : 1.f;
+    const int di[8] = {0, 0, 1, -1, 1, -1, 1, -1};
+    const int dj[8] = {1, -1, 0, 0, 1, -1, -1, 1};
+#pragma unroll
+    for (int n = 0; n < 8; ++n) {
+        const int i2 = i + di[n], j2 = j + dj[n];
+        if (i2 < 0 || i2 >= ny || j2 < 0 || j2 >= nx) continue;
+        const size_t i2x = (size_t)i2 * nx + j2;
+        const float bt = (n < 4 ? U.beta_ax : U.beta_dg) * (U.kappa ? kc * U.kappa[i2x] : 1.f);
+        float dphi, om;
+        pot_terms<POT>(U.delta, xc - U.x[i2x], dphi, om);
+        gr = fmaf(bt, dphi, gr);
+        dr = fmaf(bt, 2.f * (U.huber ? om : 1.f), dr);
+    }
+}
 
 struct BpShared {
     float tile_t[BP_TX][BP_TY + 1];
@@ -749,22 +774,12 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
                 const float rho1 = U.rho[tx1];
                 const float s = U.algorithm == 1 ? rho1 * fmaf(d, xc, -hh) + (1.f - rho1) * g
                                                  : rho1 * hh + (1.f - rho1) * g;
-                // regularizer gradient and Huber curvature at xc (8 neighbours, 4 directions)
-                float gr = 0.f, dr = 0.f;
-                const float kc = U.kappa ? U.kappa[idx] : 1.f;
-                const int di[8] = {0, 0, 1, -1, 1, -1, 1, -1};
-                const int dj[8] = {1, -1, 0, 0, 1, -1, -1, 1};
-#pragma unroll
-                for (int n = 0; n < 8; ++n) {
-                    const int i2 = i + di[n], j2 = j + dj[n];
-                    if (i2 < 0 || i2 >= ny || j2 < 0 || j2 >= nx) continue;
-                    const size_t i2x = (size_t)i2 * nx + j2;
-                    const float bt = (n < 4 ? U.beta_ax : U.beta_dg) * (U.kappa ? kc * U.kappa[i2x] : 1.f);
-                    float dphi, om;
-                    pot_terms(U.potential, U.delta, xc - U.x[i2x], dphi, om);
-                    gr = fmaf(bt, dphi, gr);
-                    dr = fmaf(bt, 2.f * (U.huber ? om : 1.f), dr);
-                }
+                // regularizer gradient and Huber curvature at xc (8 neighbours, 4 directions); one uniform
+                // branch on the potential per pixel, not one per neighbour
+                float gr, dr;
+                if (U.potential == 0) reg_stencil<0>(U, i, j, nx, ny, idx, xc, gr, dr);
+                else if (U.potential == 1) reg_stencil<1>(U, i, j, nx, ny, idx, xc, gr, dr);
+                else reg_stencil<2>(U, i, j, nx, ny, idx, xc, gr, dr);
                 const float den = fmaf(rho1, d, dr);
                 xn = den > 0.f ? fmaxf(xc - (s + gr) / den, 0.f) : xc;
                 U.x_next[idx] = xn;
