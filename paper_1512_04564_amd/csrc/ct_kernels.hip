@@ -38,6 +38,9 @@ constexpr int FP_BINS = 64;          // bins per forward workgroup (one per lane
 constexpr int FP_WAVES = 16;         // waves per forward workgroup (single launches); each streams its own lines
 constexpr int FP_WIN = 128;          // LDS pixel window of one wave (floats)
 constexpr int FP_PF = FP_WIN / 64;   // prefetch registers per lane
+#ifndef FP_RING
+#define FP_RING 2                    // image lines in flight per wave (fast line loop)
+#endif
 constexpr int BP_TX = kBpTile, BP_TY = kBpTile;
 
 __device__ __forceinline__ float rcp_approx(float v) { return __builtin_amdgcn_rcpf(v); }
@@ -181,7 +184,14 @@ __device__ __forceinline__ void fp_body(const FpLaunch &a, const int bx, const i
     // a footprint that misses the line gets zero weights, and the tap index is clamped into the padded
     // window, whose entries are finite.
     const float lcL = lc0 + (float)(NL - 1);
-    const float fw = fmaxf(fabsf(fmaf(lc0, b1.y - b0.y, b1.x - b0.x)), fabsf(fmaf(lcL, b1.y - b0.y, b1.x - b0.x)));
+    // signed footprint width at the first and the last line (linear in between)
+    const float sw0 = fmaf(lc0, b1.y - b0.y, b1.x - b0.x), sw1 = fmaf(lcL, b1.y - b0.y, b1.x - b0.x);
+    const float fw = fmaxf(fabsf(sw0), fabsf(sw1));
+    // The fast loop takes the lane's boundaries in a fixed order: where the footprint keeps one orientation
+    // over all lines, by a margin far above the rounding of a boundary position, the order of the two
+    // rounded positions is that of the exact ones on every line, which min / max would find.
+    const bool ordered = (sw0 > 0.01f && sw1 > 0.01f) || (sw0 < -0.01f && sw1 < -0.01f);
+    const float2 blo = sw0 > 0.f ? b0 : b1, bhi = sw0 > 0.f ? b1 : b0;
     const float bw = fmaxf(fabsf(fmaf(lc0, bL.y - bF.y, bL.x - bF.x)), fabsf(fmaf(lcL, bL.y - bF.y, bL.x - bF.x)));
     // first pixel q0 of a footprint starting at loc and its left edge e (exact)
     auto first_pixel = [&](float loc, int &q0, float &e, auto even_tag) {
@@ -197,12 +207,12 @@ __device__ __forceinline__ void fp_body(const FpLaunch &a, const int bx, const i
             }
         }
     };
-    // two lines in flight: register sets A (even steps) and B (odd steps), no moves between them; every
-    // step issues its loads (the last line repeats past the end) so that the loads in flight are counted
-    // statically
+    // FP_RING lines in flight: register set r serves the lines l0 + r, l0 + r + FP_RING, ..., with no moves
+    // between sets; every step issues its loads (the last line repeats past the end) so that the loads in
+    // flight are counted statically
     auto fast_lines = [&](auto even_tag) {
-        RawT<TI> pA[FP_PF], pB[FP_PF];
-        int wsA = 0, wsB = 0;
+        RawT<TI> pr[FP_RING][FP_PF];
+        int wsr[FP_RING];
         auto fetch_into = [&](int ll, RawT<TI> (&dst)[FP_PF], int &wsd) {
             ll = min(ll, l1 - 1);
             if (ll - lb == 64) {
@@ -214,47 +224,54 @@ __device__ __forceinline__ void fp_body(const FpLaunch &a, const int bx, const i
 #pragma unroll
             for (int j = 0; j < FP_PF; ++j) dst[j] = pf[j];
         };
-        auto step = [&](int l, const RawT<TI> (&src)[FP_PF], int ws) {
+        // line coordinate lcl (exact: integers plus the half of lc0)
+        auto step = [&](float lcl, const RawT<TI> (&src)[FP_PF], int ws) {
             if (!ONES) {
 #pragma unroll
                 for (int j = 0; j < FP_PF; ++j) wl[lane + 64 * j] = from_raw<TI>(src[j]);
             }
             __builtin_amdgcn_wave_barrier();
-            const float lcl = lc0 + (float)l;
-            const float u0 = fmaf(lcl, b0.y, b0.x);
-            const float u1 = fmaf(lcl, b1.y, b1.x);
-            const float lo = fminf(u0, u1), hi = fmaxf(u0, u1);
-            const float loc = fmaxf(lo, -half), hic = fminf(hi, half);
+            const float lo = fmaf(lcl, blo.y, blo.x);
+            const float hi = fmaf(lcl, bhi.y, bhi.x);
+            // both ends clamped into the line: loc <= hic, so the first weight min(d, 1) - f is >= 0, and a
+            // footprint that misses the line gets d = f = 0
+            const float loc = __builtin_amdgcn_fmed3f(lo, -half, half), hic = __builtin_amdgcn_fmed3f(hi, -half, half);
             int q0;
             float e;
             first_pixel(loc, q0, e, even_tag);
             const float d = hic - e, f = loc - e;
             const float *tp = wl + min(max(q0 - ws, 0), FP_WIN);
-            float s = fmaxf(fminf(d, 1.f) - f, 0.f) * tp[0];
+            float s = (fminf(d, 1.f) - f) * tp[0];
             s = fmaf(__builtin_amdgcn_fmed3f(d - 1.f, 0.f, 1.f), tp[1], s);
             s = fmaf(__builtin_amdgcn_fmed3f(d - 2.f, 0.f, 1.f), tp[2], s);
             return s * rcp_approx(hi - lo);
         };
-        // line l0 is already fetched into pf (by the caller's prefetch); line l0 + 1 goes to B
-        int wsA0 = __builtin_amdgcn_readlane(ws_v, l0 - lb);
+        // line l0 is already fetched into pf (by the caller's prefetch); lines l0 + 1 .. go to the other sets
+        wsr[0] = __builtin_amdgcn_readlane(ws_v, l0 - lb);
 #pragma unroll
-        for (int j = 0; j < FP_PF; ++j) pA[j] = pf[j];
-        wsA = wsA0;
-        fetch_into(l0 + 1, pB, wsB);
-        for (int l = l0; l < l1; l += 2) {
-            const float ca = step(l, pA, wsA);
-            __builtin_amdgcn_wave_barrier();
-            fetch_into(l + 2, pA, wsA);
-            acc += ca;
-            if (l + 1 < l1) {
-                const float cb = step(l + 1, pB, wsB);
+        for (int j = 0; j < FP_PF; ++j) pr[0][j] = pf[j];
+#pragma unroll
+        for (int r = 1; r < FP_RING; ++r) fetch_into(l0 + r, pr[r], wsr[r]);
+        // The loop body has no branch around a step, so that the wait before a set's use counts the other
+        // sets' loads as still in flight (a conditional step would make the compiler wait for all of them);
+        // the last lines (fewer than FP_RING) are taken after the loop, in line order.
+        float lcl = lc0 + (float)l0;
+        int l = l0;
+        for (; l + FP_RING <= l1; l += FP_RING) {
+#pragma unroll
+            for (int r = 0; r < FP_RING; ++r) {
+                const float c = step(lcl + (float)r, pr[r], wsr[r]);
                 __builtin_amdgcn_wave_barrier();
-                fetch_into(l + 3, pB, wsB);
-                acc += cb;
+                fetch_into(l + r + FP_RING, pr[r], wsr[r]);
+                acc += c;
             }
+            lcl += (float)FP_RING;
         }
+#pragma unroll
+        for (int r = 0; r + 1 < FP_RING; ++r)
+            if (l + r < l1) acc += step(lcl + (float)r, pr[r], wsr[r]);
     };
-    if (__ballot(fw > 1.99f || bw + 5.f > (float)FP_WIN) == 0) {
+    if (l0 < l1 && __ballot(fw > 1.99f || bw + 5.f > (float)FP_WIN || !ordered) == 0) {   // (waves with no lines skip both)
         if (even) fast_lines(std::true_type{});
         else fast_lines(std::false_type{});
     } else
