@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvSrc S, const bf16 *__restri
 // c_out / 32).
 constexpr int CT_T = 16;                     // tile edge (pixels)
 constexpr int CT_H = CT_T + 2;               // with halo
-template <bool FWD>
+template <bool FWD, bool PF>
 __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvSrc S, const bf16 *__restrict__ wt,
                                                       const float *__restrict__ bias, const bf16 *__restrict__ mask,
                                                       bf16 *__restrict__ out, int n, int h, int w, int cout)
@@ -191,22 +191,7 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvSrc S, const bf16 *__r
 #pragma unroll
         for (int s = 0; s < 4; ++s) acc[m][s] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bf16x8 zero8 = {};
-    for (int ci0 = 0; ci0 < cin; ci0 += 32) {
-        __syncthreads();   // the previous chunk's reads are done
-        for (int v = threadIdx.x; v < CT_H * CT_H * 4; v += 256) {
-            const int px = v >> 2, part = v & 3;
-            const int yy = y0 - 1 + px / CT_H, xx = x0 - 1 + px % CT_H;
-            bf16x8 val = zero8;
-            if (yy >= 0 && yy < h && xx >= 0 && xx < w)
-                val = *reinterpret_cast<const bf16x8 *>(src_ptr(S, ci0 + 8 * part, pn, yy, xx, h, w));
-            tile[v] = val;
-        }
-        for (int v = threadIdx.x; v < 32 * 9 * 4; v += 256) {   // the chunk's weights, staged alike
-            const int co = v / 36, rem = v % 36;
-            wts[co * WP + rem] = *reinterpret_cast<const bf16x8 *>(wt + ((size_t)(co0 + co) * 9 + rem / 4) * cin + ci0 +
-                                                                   8 * (rem % 4));
-        }
-        __syncthreads();
+    auto taps = [&]() {
         for (int tap = 0; tap < 9; ++tap) {
             const int dy = tap / 3, dx = tap % 3;   // offsets into the haloed tile
             bf16x8 a[2], b[4];
@@ -219,6 +204,69 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvSrc S, const bf16 *__r
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
                     acc[m][s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[s], acc[m][s], 0, 0, 0);
+        }
+    };
+    if constexpr (PF) {
+        // A chunk's input tile and weights go through registers: the next chunk's loads are issued before
+        // the current chunk's taps, so that their latency overlaps the matrix work (ceil(18 * 18 * 4 / 256)
+        // = 6 and ceil(32 * 9 * 4 / 256) = 5 values per thread). For layers with few workgroups per CU,
+        // which have no other workgroup to run during a chunk's loads.
+        constexpr int NT = (CT_H * CT_H * 4 + 255) / 256, NW = (32 * 9 * 4 + 255) / 256;
+        bf16x8 pt[NT], pw[NW];
+        auto load_chunk = [&](int ci0) {
+#pragma unroll
+            for (int i = 0; i < NT; ++i) {
+                const int v = threadIdx.x + 256 * i;
+                const int px = v >> 2, part = v & 3;
+                const int yy = y0 - 1 + px / CT_H, xx = x0 - 1 + px % CT_H;
+                pt[i] = zero8;
+                if (v < CT_H * CT_H * 4 && yy >= 0 && yy < h && xx >= 0 && xx < w)
+                    pt[i] = *reinterpret_cast<const bf16x8 *>(src_ptr(S, ci0 + 8 * part, pn, yy, xx, h, w));
+            }
+#pragma unroll
+            for (int i = 0; i < NW; ++i) {   // the chunk's weights
+                const int v = threadIdx.x + 256 * i;
+                const int co = v / 36, rem = v % 36;
+                if (v < 32 * 9 * 4)
+                    pw[i] = *reinterpret_cast<const bf16x8 *>(wt + ((size_t)(co0 + co) * 9 + rem / 4) * cin + ci0 +
+                                                              8 * (rem % 4));
+            }
+        };
+        load_chunk(0);
+        for (int ci0 = 0; ci0 < cin; ci0 += 32) {
+            __syncthreads();   // the previous chunk's reads are done
+#pragma unroll
+            for (int i = 0; i < NT; ++i) {
+                const int v = threadIdx.x + 256 * i;
+                if (v < CT_H * CT_H * 4) tile[v] = pt[i];
+            }
+#pragma unroll
+            for (int i = 0; i < NW; ++i) {
+                const int v = threadIdx.x + 256 * i;
+                if (v < 32 * 9 * 4) wts[(v / 36) * WP + v % 36] = pw[i];
+            }
+            __syncthreads();
+            if (ci0 + 32 < cin) load_chunk(ci0 + 32);
+            taps();
+        }
+    } else {
+        for (int ci0 = 0; ci0 < cin; ci0 += 32) {
+            __syncthreads();   // the previous chunk's reads are done
+            for (int v = threadIdx.x; v < CT_H * CT_H * 4; v += 256) {
+                const int px = v >> 2, part = v & 3;
+                const int yy = y0 - 1 + px / CT_H, xx = x0 - 1 + px % CT_H;
+                bf16x8 val = zero8;
+                if (yy >= 0 && yy < h && xx >= 0 && xx < w)
+                    val = *reinterpret_cast<const bf16x8 *>(src_ptr(S, ci0 + 8 * part, pn, yy, xx, h, w));
+                tile[v] = val;
+            }
+            for (int v = threadIdx.x; v < 32 * 9 * 4; v += 256) {   // the chunk's weights, staged alike
+                const int co = v / 36, rem = v % 36;
+                wts[co * WP + rem] = *reinterpret_cast<const bf16x8 *>(wt + ((size_t)(co0 + co) * 9 + rem / 4) * cin +
+                                                                       ci0 + 8 * (rem % 4));
+            }
+            __syncthreads();
+            taps();
         }
     }
 #pragma unroll
@@ -725,9 +773,13 @@ ct_status ensure_part(ct_unet *u, size_t n)
 // four waves when the tiles number fewer than 2048 (eight waves per CU).
 bool split_k(size_t npix, int cout) { return ((npix + 63) / 64) * (size_t)(cout / 32) < 2048; }
 
-// Large images use the LDS-tiled form (16 x 16 tiles); it needs enough tiles to fill the device.
+// Layers with at least 64 workgroups of the LDS-tiled form (16 x 16 tiles, one workgroup per tile and 32
+// output channels) use it; below four workgroups per CU it prefetches each channel chunk into registers,
+// which hides the chunk loads well enough to beat the split form down to a quarter workgroup per CU.
 int tiles16(int e) { return (e + 15) / 16; }
-bool use_tile(int n, int h, int w, int cout) { return (size_t)n * tiles16(h) * tiles16(w) * (cout / 32) >= 256; }
+size_t tile_wgs(int n, int h, int w, int cout) { return (size_t)n * tiles16(h) * tiles16(w) * (cout / 32); }
+bool use_tile(int n, int h, int w, int cout) { return tile_wgs(n, h, w, cout) >= 64; }
+bool tile_prefetch(int n, int h, int w, int cout) { return tile_wgs(n, h, w, cout) < 1024; }
 
 ConvSrc one(const bf16 *src, int c) { return ConvSrc{src, c, 0, nullptr, 0}; }
 ConvSrc cat(const bf16 *low, int cl, const bf16 *skip, int cs) { return ConvSrc{low, cl, 1, skip, cs}; }
@@ -739,7 +791,12 @@ hipError_t conv_fwd(const ct_unet *u, int l, const ConvSrc &S, bf16 *out, int n,
     const float *bias = u->theta + u->off[l] + (size_t)cout * kShape[l][0] * 9;
     if (use_tile(n, h, w, cout)) {
         dim3 grid(n * tiles16(h) * tiles16(w), cout / 32);
-        hipLaunchKernelGGL(k_conv3x3_tile<true>, grid, dim3(256), 0, s, S, u->wf[l], bias, nullptr, out, n, h, w, cout);
+        if (tile_prefetch(n, h, w, cout))
+            hipLaunchKernelGGL((k_conv3x3_tile<true, true>), grid, dim3(256), 0, s, S, u->wf[l], bias, nullptr, out, n,
+                               h, w, cout);
+        else
+            hipLaunchKernelGGL((k_conv3x3_tile<true, false>), grid, dim3(256), 0, s, S, u->wf[l], bias, nullptr, out,
+                               n, h, w, cout);
     } else if (split_k(npix, cout)) {
         dim3 grid(blocks(npix, 64), cout / 32);
         hipLaunchKernelGGL((k_conv3x3<true, 4>), grid, dim3(256), 0, s, S, u->wf[l], bias, nullptr, out, n, h, w, cout);
@@ -758,8 +815,12 @@ hipError_t conv_dgrad(const ct_unet *u, int l, const bf16 *dz, const bf16 *act, 
     const size_t npix = (size_t)n * h * w;
     if (use_tile(n, h, w, cin)) {
         dim3 grid(n * tiles16(h) * tiles16(w), cin / 32);
-        hipLaunchKernelGGL(k_conv3x3_tile<false>, grid, dim3(256), 0, s, one(dz, cout), u->wb[l], nullptr, act, out, n,
-                           h, w, cin);
+        if (tile_prefetch(n, h, w, cin))
+            hipLaunchKernelGGL((k_conv3x3_tile<false, true>), grid, dim3(256), 0, s, one(dz, cout), u->wb[l], nullptr,
+                               act, out, n, h, w, cin);
+        else
+            hipLaunchKernelGGL((k_conv3x3_tile<false, false>), grid, dim3(256), 0, s, one(dz, cout), u->wb[l], nullptr,
+                               act, out, n, h, w, cin);
     } else if (split_k(npix, cin)) {
         dim3 grid(blocks(npix, 64), cin / 32);
         hipLaunchKernelGGL((k_conv3x3<false, 4>), grid, dim3(256), 0, s, one(dz, cout), u->wb[l], nullptr, act, out, n,
