@@ -241,6 +241,14 @@ BpLaunch bp_launch(const GeomDev &G, const void *r, int vstart, int vstride, int
     return a;
 }
 
+// The second residual plane of a subset projection of nv views when it is split (forward_split), right
+// after the first in the residual block; nullptr otherwise.
+float *split_plane(const Ctx &c, int nv)
+{
+    const ct_geom_desc &d = c.g->desc;
+    return forward_split(c.g->dev, nv, d.nviews, c.dtype) ? c.g->ws.r + (size_t)nv * d.nb : nullptr;
+}
+
 UpdateArgs make_update(const Ctx &c)
 {
     UpdateArgs U;
@@ -267,17 +275,22 @@ hipError_t launch_subiter_part(const Ctx &c, long long t_abs, long long tofs, in
     Workspace &W = c.g->ws;
     const GeomDev &G = c.g->dev;
     const int m = c.order[(size_t)(t_abs % c.M)];
-    if (part == 0)
-        return launch_forward(fp_launch(G, proj_img(W, c.dtype, cur_is_a), proj_imgT(W, cur_is_a), m, c.M, c.nvm, c.y,
-                                        c.w, (float)c.M, W.r),
-                              0, FP_RESIDUAL, c.dtype, s);
+    float *r2 = split_plane(c, c.nvm);
+    if (part == 0) {
+        FpLaunch a = fp_launch(G, proj_img(W, c.dtype, cur_is_a), proj_imgT(W, cur_is_a), m, c.M, c.nvm, c.y, c.w,
+                               (float)c.M, W.r);
+        a.out2 = r2;
+        return launch_forward(a, 0, FP_RESIDUAL, c.dtype, s);
+    }
     UpdateArgs U = make_update(c);
     U.x = cur_is_a ? W.xa : W.xb;
     U.x_next = cur_is_a ? W.xb : W.xa;
     U.xc_next = proj_copy(W, c.dtype, !cur_is_a);
     U.xT_next = proj_imgT(W, !cur_is_a);
     U.tofs = tofs;
-    return launch_back_update(bp_launch(G, W.r, m, c.M, c.nvm, nullptr, U), BP_FULL, c.dtype, c.dtype, s);
+    BpLaunch b = bp_launch(G, W.r, m, c.M, c.nvm, nullptr, U);
+    b.r2 = r2;
+    return launch_back_update(b, BP_FULL, c.dtype, c.dtype, s);
 }
 
 hipError_t launch_subiter(const Ctx &c, long long t_abs, long long tofs, int cur_is_a, hipStream_t s)
@@ -490,9 +503,12 @@ ct_status do_init(const Ctx &c, const float *x_in, int zero_start, hipStream_t s
         CT_HIP_CHECK(launch_back_update(bp_launch(G, W.r, 0, 1, nv, nullptr, U), BP_INIT, c.dtype, c.dtype, s));
     } else {
         const int m = c.order[(size_t)c.M - 1];
-        CT_HIP_CHECK(launch_forward(fp_launch(G, img, W.xta, m, c.M, c.nvm, c.y, c.w, (float)c.M, W.r), 0, FP_RESIDUAL,
-                                    c.dtype, s));
-        CT_HIP_CHECK(launch_back_update(bp_launch(G, W.r, m, c.M, c.nvm, nullptr, U), BP_INIT, c.dtype, c.dtype, s));
+        FpLaunch a = fp_launch(G, img, W.xta, m, c.M, c.nvm, c.y, c.w, (float)c.M, W.r);
+        a.out2 = split_plane(c, c.nvm);
+        CT_HIP_CHECK(launch_forward(a, 0, FP_RESIDUAL, c.dtype, s));
+        BpLaunch b = bp_launch(G, W.r, m, c.M, c.nvm, nullptr, U);
+        b.r2 = a.out2;
+        CT_HIP_CHECK(launch_back_update(b, BP_INIT, c.dtype, c.dtype, s));
     }
     return CT_OK;
 }
@@ -516,6 +532,7 @@ std::vector<SliceDev> slice_table(const std::vector<Ctx> &cs, const std::vector<
         S.y = c.y;
         S.w = c.w;
         S.r = W.r;
+        S.r2 = split_plane(c, c.nvm);
         S.x[0] = W.xa;
         S.x[1] = W.xb;
         S.xc[0] = const_cast<void *>(proj_img(W, c.dtype, 1));
@@ -527,7 +544,7 @@ std::vector<SliceDev> slice_table(const std::vector<Ctx> &cs, const std::vector<
         S.dl = c.dl;
         S.kappa = c.kappa;
         S.fp_begin = fp;
-        fp += forward_workgroups(S.G, S.nvm, fp_waves);
+        fp += forward_workgroups(S.G, S.nvm, fp_waves, S.r2 != nullptr);
         S.fp_end = fp;
         S.bp_begin = bp;
         bp += update_workgroups(S.G);

@@ -131,6 +131,9 @@ struct FpLaunch {
     const void *img = nullptr, *imgT = nullptr;
     const void *y = nullptr, *w = nullptr;
     void *out = nullptr;
+    // Residual epilogue with the block's lines split over two workgroups (see forward_split): the first
+    // half of the lines writes M w (p_1 - y) s to out, the second half M w p_2 s to out2 (float32).
+    void *out2 = nullptr;
     int vstart = 0, vstride = 1, nv = 0;
     float mscale = 1.f;
 };
@@ -163,6 +166,7 @@ struct UpdateArgs {
 struct BpLaunch {
     GeomDev G;
     const void *r = nullptr;
+    const void *r2 = nullptr;   // second residual plane of a split forward projection (float32), added to r
     int vstart = 0, vstride = 1, nv = 0;
     float *out_back = nullptr;
     UpdateArgs U;
@@ -175,6 +179,7 @@ struct SliceDev {
     int M = 1, nvm = 0;
     const void *y = nullptr, *w = nullptr;
     void *r = nullptr;
+    void *r2 = nullptr;   // second residual plane when the slice's forward projection is split
     float *x[2] = {nullptr, nullptr};
     void *xc[2] = {nullptr, nullptr};
     void *xt[2] = {nullptr, nullptr};
@@ -205,7 +210,9 @@ hipError_t launch_forward_batch(const SliceDev *tab, int ns, int nwg_fp, int m, 
                                 hipStream_t s);
 hipError_t launch_update_batch(const SliceDev *tab, int ns, int nwg_bp, int m, int par, const BatchUpdate &u,
                                int dtype, hipStream_t s);
-int forward_workgroups(const GeomDev &G, int nv, int fp_waves);   // per-launch workgroup count
+int forward_workgroups(const GeomDev &G, int nv, int fp_waves, bool split);   // per-launch workgroup count
+// Whether the residual projection of nv views (of nviews) splits each block's lines over two workgroups.
+bool forward_split(const GeomDev &G, int nv, int nviews, int dtype);
 int update_workgroups(const GeomDev &G);
 
 hipError_t launch_transpose(const float *x, float *xT, int nx, int ny, hipStream_t s);

@@ -38,9 +38,7 @@ constexpr int FP_BINS = 64;          // bins per forward workgroup (one per lane
 constexpr int FP_WAVES = 16;         // waves per forward workgroup (single launches); each streams its own lines
 constexpr int FP_WIN = 128;          // LDS pixel window of one wave (floats)
 constexpr int FP_PF = FP_WIN / 64;   // prefetch registers per lane
-#ifndef FP_RING
-#define FP_RING 2                    // image lines in flight per wave (fast line loop)
-#endif
+constexpr int FP_RING = 2;           // image lines in flight per wave (fast line loop)
 constexpr int BP_TX = kBpTile, BP_TY = kBpTile;
 
 __device__ __forceinline__ float rcp_approx(float v) { return __builtin_amdgcn_rcpf(v); }
@@ -102,7 +100,7 @@ __device__ __forceinline__ float from_raw(RawT<T> u)
 // window is padded, so taps past its end read finite data with zero weight); wider footprints (oblique
 // lines) continue in a loop, and lines whose window exceeds the LDS slice read global memory.
 template <int EPI, bool ONES, int WAVES, typename TI, typename TY, typename TO>
-__device__ __forceinline__ void fp_body(const FpLaunch &a, const int bx, const int vi, float *win)
+__device__ __forceinline__ void fp_body(const FpLaunch &a, const int bx, const int vi, const int half_of, float *win)
 {
     const GeomDev &G = a.G;
     const int vstart = a.vstart, vstride = a.vstride;
@@ -138,7 +136,9 @@ __device__ __forceinline__ void fp_body(const FpLaunch &a, const int bx, const i
     }
     float *wl = win + wave * PADW;
     for (int t = lane; t < PADW; t += 64) wl[t] = ONES ? 1.f : 0.f;
-    const int l0 = (wave * NL) / WAVES, l1 = ((wave + 1) * NL) / WAVES;
+    // the workgroup's lines: all, or half half_of (0: [0, NL / 2), 1: [NL / 2, NL)) of a split block
+    const int lbeg = half_of == 1 ? NL / 2 : 0, nlw = half_of < 0 ? NL : (half_of == 0 ? NL / 2 : NL - NL / 2);
+    const int l0 = lbeg + (wave * nlw) / WAVES, l1 = lbeg + ((wave + 1) * nlw) / WAVES;
 
     // pixels [ws, ws + wn) of line l that the block's bins can overlap (boundaries are monotone in k);
     // computed by lane (l - lb) for the 64 lines starting at lb
@@ -344,16 +344,25 @@ __device__ __forceinline__ void fp_body(const FpLaunch &a, const int bx, const i
         const size_t o = (size_t)vi * nb + k;
         if (EPI == FP_PLAIN) st<TO>(a.out, o, p);
         // the residual is stored multiplied by the bin scale, the factor the back-projector applies to it
-        else if (EPI == FP_RESIDUAL) st<TO>(a.out, o, (a.mscale * e_w * (p - e_y)) * sc);
+        else if (EPI == FP_RESIDUAL) {
+            if (half_of == 1) st<float>(a.out2, o, (a.mscale * e_w * p) * sc);   // the data term is in half 0
+            else st<TO>(a.out, o, (a.mscale * e_w * (p - e_y)) * sc);
+        }
         else st<TO>(a.out, o, e_w * p);
     }
 }
 
-template <int EPI, bool ONES, int WAVES, typename TI, typename TY, typename TO>
+// SPLIT: each block's lines split over two workgroups (grid x doubled; residual epilogue, float32)
+template <int EPI, bool ONES, int WAVES, typename TI, typename TY, typename TO, bool SPLIT>
 __global__ __launch_bounds__(FP_BINS *WAVES) void k_forward(FpLaunch a)
 {
     __shared__ float win[WAVES * (FP_WIN + 4)];
-    fp_body<EPI, ONES, WAVES, TI, TY, TO>(a, blockIdx.x, blockIdx.y, win);
+    if constexpr (SPLIT) {
+        const int nbx = (a.G.nb + FP_BINS - 1) / FP_BINS;
+        fp_body<EPI, ONES, WAVES, TI, TY, TO>(a, blockIdx.x % nbx, blockIdx.y, (int)blockIdx.x / nbx, win);
+    } else {
+        fp_body<EPI, ONES, WAVES, TI, TY, TO>(a, blockIdx.x, blockIdx.y, -1, win);
+    }
 }
 
 // Slice of workgroup b in a batched grid: the table holds ascending, contiguous workgroup ranges.
@@ -380,13 +389,15 @@ __global__ __launch_bounds__(FP_BINS *WAVES) void k_forward_batch(const SliceDev
     a.y = S.y;
     a.w = S.w;
     a.out = S.r;
+    a.out2 = S.r2;
     a.vstart = m;
     a.vstride = S.M;
     a.nv = S.nvm;
     a.mscale = (float)S.M;
     const int local = blockIdx.x - S.fp_begin;
-    const int nbx = (S.G.nb + FP_BINS - 1) / FP_BINS;
-    fp_body<FP_RESIDUAL, false, WAVES, T, T, T>(a, local % nbx, local / nbx, win);
+    const int nbx = (S.G.nb + FP_BINS - 1) / FP_BINS, per_view = S.r2 ? 2 * nbx : nbx;
+    const int rem = local % per_view;
+    fp_body<FP_RESIDUAL, false, WAVES, T, T, T>(a, rem % nbx, local / per_view, S.r2 ? rem / nbx : -1, win);
 }
 
 // Back-projection of one pixel for one view: bins whose interval meets the pixel [e0, e0 + 1] on line
@@ -610,7 +621,9 @@ struct BpShared {
     float4 ent[BP_GROUPS][BP_SLOT];   // per wave: the staged view, then the wave's partial sums
 };
 
-template <int MODE, typename TR, typename TXC>
+// R2: the second residual plane of a split forward projection (float32 only) is absent (0), present (1),
+// or present where a.r2 is set (2, the batched kernel, whose slices differ).
+template <int MODE, typename TR, typename TXC, int R2>
 __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const int by, BpShared &sh)
 {
     // the solver's residual blocks come from the forward epilogue already multiplied by the bin scale
@@ -619,6 +632,7 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
     const UpdateArgs &U = a.U;
     const int vstart = a.vstart, vstride = a.vstride, nv = a.nv;
     const TR *__restrict__ r = static_cast<const TR *>(a.r);
+    const float *__restrict__ r2 = static_cast<const float *>(a.r2);
     // threads 0 .. 255 (hv = 0) update pixel tid of the tile after the back-projection
     const int hv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / BP_NT));
     const int tid = threadIdx.x % BP_NT;
@@ -684,6 +698,12 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
                 if (e1i < ne - 1) {
                     q.r1 = ld_raw<TR>(r, kr + 1);
                     if (!PRESCALED) q.s1 = G.scale[ks + 1];
+                }
+                if constexpr (R2 != 0 && std::is_same<TR, float>::value) {
+                    if (R2 == 1 || r2) {   // the second plane of a split forward projection
+                        if (e0i < ne - 1) q.r0 += r2[kr];
+                        if (e1i < ne - 1) q.r1 += r2[kr + 1];
+                    }
                 }
                 return q;
             };
@@ -815,11 +835,11 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
 }
 
 // Eight waves per SIMD (four workgroups per CU): the register budget is held to that occupancy.
-template <int MODE, typename TR, typename TXC>
+template <int MODE, typename TR, typename TXC, int R2>
 __global__ __launch_bounds__(2 * BP_TX *BP_TY) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_back_update(BpLaunch a)
 {
     __shared__ BpShared sh;
-    bp_body<MODE, TR, TXC>(a, blockIdx.x, blockIdx.y, sh);
+    bp_body<MODE, TR, TXC, R2>(a, blockIdx.x, blockIdx.y, sh);
 }
 
 // Batched fused back-projection / relaxed update of subset m: every slice reads image buffer par and
@@ -834,6 +854,7 @@ __global__ __launch_bounds__(2 * BP_TX *BP_TY) __attribute__((amdgpu_waves_per_e
     BpLaunch a;
     a.G = S.G;
     a.r = S.r;
+    a.r2 = S.r2;
     a.vstart = m;
     a.vstride = S.M;
     a.nv = S.nvm;
@@ -857,7 +878,7 @@ __global__ __launch_bounds__(2 * BP_TX *BP_TY) __attribute__((amdgpu_waves_per_e
     a.U.huber = u.huber;
     const int local = blockIdx.x - S.bp_begin;
     const int tilesx = (S.G.nx + BP_TX - 1) / BP_TX;
-    bp_body<BP_FULL, T, T>(a, local % tilesx, local / tilesx, sh);
+    bp_body<BP_FULL, T, T, std::is_same<T, float>::value ? 2 : 0>(a, local % tilesx, local / tilesx, sh);
 }
 
 __global__ void k_transpose(const float *__restrict__ x, float *__restrict__ xT, int nx, int ny)
@@ -920,7 +941,20 @@ __global__ void k_set_counter(int *c, int value) { c[0] = value; }
 
 }  // namespace
 
-int forward_workgroups(const GeomDev &G, int nv, int) { return ((G.nb + FP_BINS - 1) / FP_BINS) * nv; }
+int forward_workgroups(const GeomDev &G, int nv, int, bool split)
+{
+    return ((G.nb + FP_BINS - 1) / FP_BINS) * nv * (split ? 2 : 1);
+}
+
+// A float32 subset projection whose (block, view) workgroups would number fewer than two per CU (512 on
+// the 256 CUs) splits each block's lines over two workgroups, which halves the chain of line steps that
+// bounds a workgroup. The halves write two residual planes (the data term in the first), which the update
+// kernel adds when it stages a view; both planes must fit the residual block of nviews views. 16-bit
+// storage keeps one plane: each half's residual would round to 16 bits before the two cancel.
+bool forward_split(const GeomDev &G, int nv, int nviews, int dtype)
+{
+    return dtype == CT_F32 && 2 * nv <= nviews && ((G.nb + FP_BINS - 1) / FP_BINS) * nv < 512;
+}
 
 int update_workgroups(const GeomDev &G) { return ((G.nx + BP_TX - 1) / BP_TX) * ((G.ny + BP_TY - 1) / BP_TY); }
 
@@ -930,9 +964,12 @@ int update_workgroups(const GeomDev &G) { return ((G.nx + BP_TX - 1) / BP_TX) * 
 hipError_t launch_forward(const FpLaunch &a, int ones, int epi, int dtype, hipStream_t s)
 {
     if (a.nv <= 0) return hipSuccess;
-    dim3 grid((a.G.nb + FP_BINS - 1) / FP_BINS, a.nv), block(FP_BINS * FP_WAVES);
-#define CT_FP(E, O, TI, TY, TO) hipLaunchKernelGGL((k_forward<E, O, FP_WAVES, TI, TY, TO>), grid, block, 0, s, a)
-    if (dtype == CT_F32) {
+    if (a.out2 && (epi != FP_RESIDUAL || dtype != CT_F32 || ones)) return hipErrorInvalidValue;
+    dim3 grid(((a.G.nb + FP_BINS - 1) / FP_BINS) * (a.out2 ? 2 : 1), a.nv), block(FP_BINS * FP_WAVES);
+#define CT_FP(E, O, TI, TY, TO) hipLaunchKernelGGL((k_forward<E, O, FP_WAVES, TI, TY, TO, false>), grid, block, 0, s, a)
+    if (a.out2) {
+        hipLaunchKernelGGL((k_forward<FP_RESIDUAL, false, FP_WAVES, float, float, float, true>), grid, block, 0, s, a);
+    } else if (dtype == CT_F32) {
         if (ones) {
             if (epi == FP_PLAIN) CT_FP(FP_PLAIN, true, float, float, float);
             else if (epi == FP_RESIDUAL) CT_FP(FP_RESIDUAL, true, float, float, float);
@@ -962,13 +999,17 @@ hipError_t launch_forward(const FpLaunch &a, int ones, int epi, int dtype, hipSt
 hipError_t launch_back_update(const BpLaunch &a, int mode, int rtype, int ctype, hipStream_t s)
 {
     dim3 grid((a.G.nx + BP_TX - 1) / BP_TX, (a.G.ny + BP_TY - 1) / BP_TY), block(2 * BP_TX * BP_TY);
-#define CT_BP(M, TR, TC) hipLaunchKernelGGL((k_back_update<M, TR, TC>), grid, block, 0, s, a)
+#define CT_BP(M, TR, TC) hipLaunchKernelGGL((k_back_update<M, TR, TC, 0>), grid, block, 0, s, a)
 #define CT_BP_ALL(T)                                                                                           \
     if (mode == BP_INIT) CT_BP(BP_INIT, T, T);                                                                 \
     else if (mode == BP_FULL) CT_BP(BP_FULL, T, T);                                                            \
     else if (mode == BP_XSTEP) CT_BP(BP_XSTEP, T, T);                                                          \
     else return hipErrorInvalidValue;
-    if (mode == BP_BACK) {
+    if (a.r2) {   // a split forward projection's two residual planes (float32 only)
+        if (rtype != CT_F32 || ctype != CT_F32 || (mode != BP_INIT && mode != BP_FULL)) return hipErrorInvalidValue;
+        if (mode == BP_INIT) hipLaunchKernelGGL((k_back_update<BP_INIT, float, float, 1>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_back_update<BP_FULL, float, float, 1>), grid, block, 0, s, a);
+    } else if (mode == BP_BACK) {
         if (rtype == CT_F32) CT_BP(BP_BACK, float, float);
         else if (rtype == CT_F16) CT_BP(BP_BACK, _Float16, float);
         else if (rtype == CT_BF16) CT_BP(BP_BACK, __bf16, float);
