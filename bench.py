@@ -89,7 +89,9 @@ def write_traffic(fetch_dir, write_dir):
     kib = COPY_BYTES / 1024.0
     ff, wf = kib / float(cf["Counter_Value"]), kib / float(cw["Counter_Value"])
     kernels = {}
-    for name, key in (("update", "k_back_update<2, float, float>"), ("forward", "k_forward<1, false, 16, float")):
+    # the 41-subset float32 solve's instances: split forward projection, update adding the two residual planes
+    for name, key in (("update", "k_back_update<2, float, float, 1>"),
+                      ("forward", "k_forward<1, false, 16, float, float, float, true>")):
         fk, n = mean_of(rf, key)
         wk, _ = mean_of(rw, key)
         kernels[name] = {"kernel": key, "fetch_kib_per_dispatch": round(fk, 1), "write_kib_per_dispatch": round(wk, 1),
