@@ -39,7 +39,7 @@ class RlalmParams(ctypes.Structure):
                 ("subset_order", ctypes.c_int), ("kappa", ctypes.c_int), ("start", ctypes.c_int),
                 ("init_full", ctypes.c_int), ("dl_scale", ctypes.c_double), ("x_ref", ctypes.c_void_p),
                 ("mu_water", ctypes.c_double), ("fov_radius", ctypes.c_double), ("use_graph", ctypes.c_int),
-                ("time_kernels", ctypes.c_int), ("unet", ctypes.c_void_p)]
+                ("time_kernels", ctypes.c_int), ("unet", ctypes.c_void_p), ("forward_split", ctypes.c_int)]
 
 
 class KernelTimes(ctypes.Structure):

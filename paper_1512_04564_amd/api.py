@@ -103,6 +103,7 @@ class Params:
     use_graph: bool = True
     time_kernels: bool = False
     unet: object = None              # unet.UNet for start="learned"
+    forward_split: int = -1          # -1: when the launch underfills the device, 0: never, 1: always
 
     def to_c(self, x_ref: torch.Tensor | None = None) -> RlalmParams:
         p = RlalmParams()
@@ -121,6 +122,7 @@ class Params:
         p.start = {"given": 0, "zero": 1, "fbp": 2, "learned": 3}[self.start]
         p.unet = self.unet.handle.value if self.unet is not None else None
         p.init_full = int(self.init_full)
+        p.forward_split = self.forward_split
         p.dl_scale = self.dl_scale
         p.x_ref = x_ref.data_ptr() if x_ref is not None else None
         p.mu_water = self.mu_water

@@ -93,6 +93,7 @@ ct_status check_params(const ct_rlalm_params *p)
     if (!(p->dl_scale > 0)) return fail(CT_ERR_INVALID_ARG, "dl_scale must be > 0");
     if (p->start < 0 || p->start > 3) return fail(CT_ERR_INVALID_ARG, "start must be 0, 1, 2 or 3");
     if (p->start == 3 && !p->unet) return fail(CT_ERR_INVALID_ARG, "start == 3 needs a network (unet)");
+    if (p->forward_split < -1 || p->forward_split > 1) return fail(CT_ERR_INVALID_ARG, "forward_split must be -1, 0 or 1");
     return CT_OK;
 }
 
@@ -241,12 +242,19 @@ BpLaunch bp_launch(const GeomDev &G, const void *r, int vstart, int vstride, int
     return a;
 }
 
-// The second residual plane of a subset projection of nv views when it is split (forward_split), right
-// after the first in the residual block; nullptr otherwise.
-float *split_plane(const Ctx &c, int nv)
+// The second residual plane of a subset projection of nv views when it is split, right after the first in
+// the residual block; nullptr otherwise. A single slice's launch decides for itself (forward_split); a
+// batched launch passes its own decision (batch_split).
+float *split_plane(const Ctx &c, int nv, int batch_split = -1)
 {
     const ct_geom_desc &d = c.g->desc;
-    return forward_split(c.g->dev, nv, d.nviews, c.dtype) ? c.g->ws.r + (size_t)nv * d.nb : nullptr;
+    const int mode = c.p->forward_split;
+    bool split = false;
+    if (mode == 1) split = split_eligible(c.g->dev, nv, d.nviews, c.dtype);
+    else if (mode == -1)
+        split = batch_split >= 0 ? batch_split && split_eligible(c.g->dev, nv, d.nviews, c.dtype)
+                                 : forward_split(c.g->dev, nv, d.nviews, c.dtype);
+    return split ? c.g->ws.r + (size_t)nv * d.nb : nullptr;
 }
 
 UpdateArgs make_update(const Ctx &c)
@@ -522,6 +530,10 @@ std::vector<SliceDev> slice_table(const std::vector<Ctx> &cs, const std::vector<
 {
     std::vector<SliceDev> tab;
     int fp = 0, bp = 0;
+    // the automatic split is decided for the launch as a whole: all of its unsplit forward workgroups
+    int fp_all = 0;
+    for (int i : order) fp_all += forward_workgroups(cs[(size_t)i].g->dev, cs[(size_t)i].nvm, fp_waves, false);
+    const int batch_split = launch_underfills(fp_all) ? 1 : 0;
     for (int i : order) {
         const Ctx &c = cs[(size_t)i];
         const Workspace &W = c.g->ws;
@@ -532,7 +544,7 @@ std::vector<SliceDev> slice_table(const std::vector<Ctx> &cs, const std::vector<
         S.y = c.y;
         S.w = c.w;
         S.r = W.r;
-        S.r2 = split_plane(c, c.nvm);
+        S.r2 = split_plane(c, c.nvm, batch_split);
         S.x[0] = W.xa;
         S.x[1] = W.xb;
         S.xc[0] = const_cast<void *>(proj_img(W, c.dtype, 1));
@@ -712,6 +724,7 @@ void ct_rlalm_params_default(ct_rlalm_params *p)
     p->fov_radius = 0.0;
     p->use_graph = 1;
     p->time_kernels = 0;
+    p->forward_split = -1;
 }
 
 ct_status ct_geom_create(const ct_geom_desc *desc, ct_geom **out)

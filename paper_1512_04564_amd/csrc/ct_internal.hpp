@@ -211,8 +211,11 @@ hipError_t launch_forward_batch(const SliceDev *tab, int ns, int nwg_fp, int m, 
 hipError_t launch_update_batch(const SliceDev *tab, int ns, int nwg_bp, int m, int par, const BatchUpdate &u,
                                int dtype, hipStream_t s);
 int forward_workgroups(const GeomDev &G, int nv, int fp_waves, bool split);   // per-launch workgroup count
-// Whether the residual projection of nv views (of nviews) splits each block's lines over two workgroups.
+// Whether the residual projection of nv views (of nviews) splits each block's lines over two workgroups:
+// it can (float32, both planes fit the residual block) and its launch alone would underfill the device.
 bool forward_split(const GeomDev &G, int nv, int nviews, int dtype);
+bool split_eligible(const GeomDev &G, int nv, int nviews, int dtype);
+bool launch_underfills(int forward_wgs);   // fewer than two workgroups per CU
 int update_workgroups(const GeomDev &G);
 
 hipError_t launch_transpose(const float *x, float *xT, int nx, int ny, hipStream_t s);

@@ -951,9 +951,11 @@ int forward_workgroups(const GeomDev &G, int nv, int, bool split)
 // bounds a workgroup. The halves write two residual planes (the data term in the first), which the update
 // kernel adds when it stages a view; both planes must fit the residual block of nviews views. 16-bit
 // storage keeps one plane: each half's residual would round to 16 bits before the two cancel.
+bool split_eligible(const GeomDev &, int nv, int nviews, int dtype) { return dtype == CT_F32 && 2 * nv <= nviews; }
+bool launch_underfills(int forward_wgs) { return forward_wgs < 512; }
 bool forward_split(const GeomDev &G, int nv, int nviews, int dtype)
 {
-    return dtype == CT_F32 && 2 * nv <= nviews && ((G.nb + FP_BINS - 1) / FP_BINS) * nv < 512;
+    return split_eligible(G, nv, nviews, dtype) && launch_underfills(((G.nb + FP_BINS - 1) / FP_BINS) * nv);
 }
 
 int update_workgroups(const GeomDev &G) { return ((G.nx + BP_TX - 1) / BP_TX) * ((G.ny + BP_TY - 1) / BP_TY); }

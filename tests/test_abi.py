@@ -46,6 +46,7 @@ def test_params_default_and_struct_layout():
     assert p.niters == 20 and p.algorithm == 1 and p.huber == 1 and p.use_graph == 1
     assert p.delta == pytest.approx(1e-4) and p.beta == pytest.approx(1024.0)
     assert p.mu_water == pytest.approx(0.02)
+    assert p.forward_split == -1
 
 
 def test_invalid_descriptor_is_rejected_without_touching_the_gpu():

@@ -37,12 +37,14 @@ def small_classes(M):
     return [cls(48, 110, 96), cls(80, 150, 160), cls(128, 220, 256), cls(64, 130, 128)]
 
 
-@pytest.mark.parametrize("M,niters", [(5, 3), (10, 2)])
-def test_batched_equals_single_solves_bitwise(api, M, niters):
+@pytest.mark.parametrize("M,niters,split", [(5, 3, -1), (10, 2, -1), (10, 2, 0), (10, 2, 1)])
+def test_batched_equals_single_solves_bitwise(api, M, niters, split):
+    """Same bits with the same forward_split setting: automatic (these small batches underfill the device,
+    so the batch and every single launch split), never, always."""
     import torch
     geoms = small_classes(M)
     scans = [synth.noisy_scan(g, 40 + i, truth=False) for i, g in enumerate(geoms)]
-    p = api.Params(alpha=1.999, niters=niters, subset_order="bitrev", start="zero")
+    p = api.Params(alpha=1.999, niters=niters, subset_order="bitrev", start="zero", forward_split=split)
     Gs = [api.Geometry(g) for g in geoms]
     ys = [to_dev(s.y) for s in scans]
     ws = [to_dev(s.w) for s in scans]

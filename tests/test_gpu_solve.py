@@ -50,6 +50,7 @@ def gpu_solve(api, g, s, x0, **kw):
 def oracle_solve(g, s, x0, **kw):
     kw = dict(kw)
     kw.pop("use_graph", None)
+    kw.pop("forward_split", None)   # how the GPU forms the residual, not what it computes
     start = kw.pop("start", "given")
     p = oracle.params(nsubsets=g.nsubsets, **kw)
     x, _, _ = oracle.rlalm_solve(g, p, s.y.astype(np.float64), s.w.astype(np.float64),
@@ -70,6 +71,9 @@ CFG1_CASES = [
     dict(alpha=1.5, subset_order="bitrev", potential="fair"),
     dict(alpha=1.999, subset_order="bitrev", huber=False),
     dict(alpha=1.999, subset_order="bitrev", init_full=True),
+    # the forward projection split over two workgroups per block (the default at this size) and not
+    dict(alpha=1.999, subset_order="bitrev", forward_split=0),
+    dict(alpha=1.999, subset_order="bitrev", forward_split=1),
 ]
 
 
@@ -242,3 +246,17 @@ def test_solve_parity_potentials(api):
         assert d <= 0.05
     for a, b in (("hyperbola", "fair"), ("hyperbola", "qggmrf"), ("fair", "qggmrf")):
         assert hu_rmsd(xo[a], xo[b], mask) > 0.3, (a, b)
+
+
+def test_forward_split_setting(api):
+    """The split and the unsplit residual differ by rounding only; an unknown setting is an argument error."""
+    g = synth.CFG1
+    s = scan(g, 0)
+    x0 = np.zeros((g.ny, g.nx), dtype=np.float32)
+    mask = oracle.fov_mask(g, synth.fov_radius(g))
+    xs = {k: gpu_solve(api, g, s, x0, niters=5, alpha=1.999, subset_order="bitrev", forward_split=k) for k in (0, 1)}
+    d = hu_rmsd(xs[0], xs[1], mask)
+    say(f"  RMSD(split, unsplit) = {d:.2e} HU")
+    assert 0.0 < d <= 0.01
+    with pytest.raises(api.CtError):
+        gpu_solve(api, g, s, x0, niters=1, forward_split=2)
