@@ -592,9 +592,10 @@ constexpr int BP_GROUPS = 8;    // view groups (waves) per workgroup
 constexpr int BP_SWIN = 125;    // widest window staged (bins); wider ones read the tables directly
 constexpr int BP_SLOT = 128;    // staged entries per view (n + 1 for a window of n bins)
 
-// Regularizer gradient and Huber curvature at pixel (i, j) of value xc: the pair terms of the 8 neighbours
-// (4 directions, each pair seen from both sides) with potential POT, weighted by beta and the kappa factors.
-template <int POT>
+// Regularizer gradient and Huber curvature at pixel (i, j) of value xc: the pair terms of neighbours
+// N0 .. N1 - 1 of the 8 (4 directions, each pair seen from both sides; 0 .. 3 axial, 4 .. 7 diagonal) with
+// potential POT, weighted by beta and the kappa factors.
+template <int POT, int N0, int N1>
 __device__ __forceinline__ void reg_stencil(const UpdateArgs &U, int i, int j, int nx, int ny, size_t idx,
                                             float xc, float &gr, float &dr)
 {
@@ -604,7 +605,7 @@ __device__ __forceinline__ void reg_stencil(const UpdateArgs &U, int i, int j, i
     const int di[8] = {0, 0, 1, -1, 1, -1, 1, -1};
     const int dj[8] = {1, -1, 0, 0, 1, -1, -1, 1};
 #pragma unroll
-    for (int n = 0; n < 8; ++n) {
+    for (int n = N0; n < N1; ++n) {
         const int i2 = i + di[n], j2 = j + dj[n];
         if (i2 < 0 || i2 >= ny || j2 < 0 || j2 >= nx) continue;
         const size_t i2x = (size_t)i2 * nx + j2;
@@ -616,9 +617,20 @@ __device__ __forceinline__ void reg_stencil(const UpdateArgs &U, int i, int j, i
     }
 }
 
+template <int N0, int N1>
+__device__ __forceinline__ void reg_stencil_pot(const UpdateArgs &U, int i, int j, int nx, int ny, size_t idx,
+                                                float xc, float &gr, float &dr)
+{
+    // one uniform branch on the potential per pixel, not one per neighbour
+    if (U.potential == 0) reg_stencil<0, N0, N1>(U, i, j, nx, ny, idx, xc, gr, dr);
+    else if (U.potential == 1) reg_stencil<1, N0, N1>(U, i, j, nx, ny, idx, xc, gr, dr);
+    else reg_stencil<2, N0, N1>(U, i, j, nx, ny, idx, xc, gr, dr);
+}
+
 struct BpShared {
     float tile_t[BP_TX][BP_TY + 1];
     float4 ent[BP_GROUPS][BP_SLOT];   // per wave: the staged view, then the wave's partial sums
+    float2 reg_part[BP_NT];           // the diagonal neighbours' regularizer terms, from the second half
 };
 
 // R2: the second residual plane of a split forward projection (float32 only) is absent (0), present (1),
@@ -781,7 +793,9 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
         }
     }
     float xn = 0.f;
-    if (hv == 0 && inside) {   // half 1 only takes part in the barriers from here on
+    // operands of the x-step, kept over the barrier below: s, rho1, d, xc and the axial regularizer terms
+    float xs_s = 0.f, xs_rho1 = 0.f, xs_d = 0.f, xs_xc = 0.f, gr = 0.f, dr = 0.f;
+    if (hv == 0 && inside) {   // half 1 only evaluates the diagonal regularizer terms from here on
         const size_t idx = (size_t)i * nx + j;
         if (MODE == BP_BACK) {
             a.out_back[idx] = zeta;
@@ -811,20 +825,34 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
                 const float rho1 = U.rho[tx1];
                 const float s = U.algorithm == 1 ? rho1 * fmaf(d, xc, -hh) + (1.f - rho1) * g
                                                  : rho1 * hh + (1.f - rho1) * g;
-                // regularizer gradient and Huber curvature at xc (8 neighbours, 4 directions); one uniform
-                // branch on the potential per pixel, not one per neighbour
-                float gr, dr;
-                if (U.potential == 0) reg_stencil<0>(U, i, j, nx, ny, idx, xc, gr, dr);
-                else if (U.potential == 1) reg_stencil<1>(U, i, j, nx, ny, idx, xc, gr, dr);
-                else reg_stencil<2>(U, i, j, nx, ny, idx, xc, gr, dr);
-                const float den = fmaf(rho1, d, dr);
-                xn = den > 0.f ? fmaxf(xc - (s + gr) / den, 0.f) : xc;
-                U.x_next[idx] = xn;
-                if (!std::is_same<TXC, float>::value) st<TXC>(U.xc_next, idx, xn);
+                // regularizer gradient and Huber curvature at xc: the axial neighbours here, the diagonal
+                // ones by the second half of the workgroup (below), added after the barrier
+                reg_stencil_pot<0, 4>(U, i, j, nx, ny, idx, xc, gr, dr);
+                xs_s = s;
+                xs_rho1 = rho1;
+                xs_d = d;
+                xs_xc = xc;
             }
         }
     }
     if (MODE == BP_FULL || MODE == BP_XSTEP) {
+        if (hv == 1 && inside) {
+            const size_t idx = (size_t)i * nx + j;
+            float g2, d2;
+            reg_stencil_pot<4, 8>(U, i, j, nx, ny, idx, U.x[idx], g2, d2);
+            sh.reg_part[tid] = make_float2(g2, d2);
+        }
+        __syncthreads();
+        if (hv == 0 && inside) {
+            const size_t idx = (size_t)i * nx + j;
+            const float2 q = sh.reg_part[tid];
+            gr += q.x;
+            dr += q.y;
+            const float den = fmaf(xs_rho1, xs_d, dr);
+            xn = den > 0.f ? fmaxf(xs_xc - (xs_s + gr) / den, 0.f) : xs_xc;
+            U.x_next[idx] = xn;
+            if (!std::is_same<TXC, float>::value) st<TXC>(U.xc_next, idx, xn);
+        }
         // transpose through LDS: write xT_next[j][i] in runs of BP_TY along i
         if (hv == 0) tile_t[tx][ty] = xn;
         __syncthreads();
