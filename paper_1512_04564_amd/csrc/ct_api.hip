@@ -298,7 +298,7 @@ hipError_t launch_subiter_part(const Ctx &c, long long t_abs, long long tofs, in
     U.tofs = tofs;
     BpLaunch b = bp_launch(G, W.r, m, c.M, c.nvm, nullptr, U);
     b.r2 = r2;
-    return launch_back_update(b, BP_FULL, c.dtype, c.dtype, s);
+    return launch_back_update(b, BP_FULL, r2 ? CT_F32 : c.dtype, c.dtype, s);
 }
 
 hipError_t launch_subiter(const Ctx &c, long long t_abs, long long tofs, int cur_is_a, hipStream_t s)
@@ -516,7 +516,7 @@ ct_status do_init(const Ctx &c, const float *x_in, int zero_start, hipStream_t s
         CT_HIP_CHECK(launch_forward(a, 0, FP_RESIDUAL, c.dtype, s));
         BpLaunch b = bp_launch(G, W.r, m, c.M, c.nvm, nullptr, U);
         b.r2 = a.out2;
-        CT_HIP_CHECK(launch_back_update(b, BP_INIT, c.dtype, c.dtype, s));
+        CT_HIP_CHECK(launch_back_update(b, BP_INIT, b.r2 ? CT_F32 : c.dtype, c.dtype, s));
     }
     return CT_OK;
 }

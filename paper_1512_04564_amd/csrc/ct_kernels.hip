@@ -397,7 +397,10 @@ __global__ __launch_bounds__(FP_BINS *WAVES) void k_forward_batch(const SliceDev
     const int local = blockIdx.x - S.fp_begin;
     const int nbx = (S.G.nb + FP_BINS - 1) / FP_BINS, per_view = S.r2 ? 2 * nbx : nbx;
     const int rem = local % per_view;
-    fp_body<FP_RESIDUAL, false, WAVES, T, T, T>(a, rem % nbx, local / per_view, S.r2 ? rem / nbx : -1, win);
+    if (S.r2)   // split: float32 residual planes
+        fp_body<FP_RESIDUAL, false, WAVES, T, T, float>(a, rem % nbx, local / per_view, rem / nbx, win);
+    else
+        fp_body<FP_RESIDUAL, false, WAVES, T, T, T>(a, rem % nbx, local / per_view, -1, win);
 }
 
 // Back-projection of one pixel for one view: bins whose interval meets the pixel [e0, e0 + 1] on line
@@ -633,11 +636,12 @@ struct BpShared {
     float2 reg_part[BP_NT];           // the diagonal neighbours' regularizer terms, from the second half
 };
 
-// R2: the second residual plane of a split forward projection (float32 only) is absent (0), present (1),
-// or present where a.r2 is set (2, the batched kernel, whose slices differ).
+// R2 = 1: the residual is the sum of the two float32 planes of a split forward projection (a.r, a.r2);
+// R2 = 2: the same where a.r2 is set (the float32 batched kernel, whose slices differ).
 template <int MODE, typename TR, typename TXC, int R2>
 __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const int by, BpShared &sh)
 {
+    static_assert(R2 == 0 || std::is_same<TR, float>::value, "split residual planes are float32");
     // the solver's residual blocks come from the forward epilogue already multiplied by the bin scale
     constexpr bool PRESCALED = MODE == BP_INIT || MODE == BP_FULL;
     const GeomDev &G = a.G;
@@ -711,7 +715,7 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
                     q.r1 = ld_raw<TR>(r, kr + 1);
                     if (!PRESCALED) q.s1 = G.scale[ks + 1];
                 }
-                if constexpr (R2 != 0 && std::is_same<TR, float>::value) {
+                if constexpr (R2 != 0) {
                     if (R2 == 1 || r2) {   // the second plane of a split forward projection
                         if (e0i < ne - 1) q.r0 += r2[kr];
                         if (e1i < ne - 1) q.r1 += r2[kr + 1];
@@ -906,7 +910,12 @@ __global__ __launch_bounds__(2 * BP_TX *BP_TY) __attribute__((amdgpu_waves_per_e
     a.U.huber = u.huber;
     const int local = blockIdx.x - S.bp_begin;
     const int tilesx = (S.G.nx + BP_TX - 1) / BP_TX;
-    bp_body<BP_FULL, T, T, std::is_same<T, float>::value ? 2 : 0>(a, local % tilesx, local / tilesx, sh);
+    if constexpr (std::is_same<T, float>::value) {
+        bp_body<BP_FULL, float, float, 2>(a, local % tilesx, local / tilesx, sh);
+    } else {   // 16-bit slices: the two float32 residual planes of a split projection, or one 16-bit block
+        if (S.r2) bp_body<BP_FULL, float, T, 1>(a, local % tilesx, local / tilesx, sh);
+        else bp_body<BP_FULL, T, T, 0>(a, local % tilesx, local / tilesx, sh);
+    }
 }
 
 __global__ void k_transpose(const float *__restrict__ x, float *__restrict__ xT, int nx, int ny)
@@ -977,9 +986,9 @@ int forward_workgroups(const GeomDev &G, int nv, int, bool split)
 // A float32 subset projection whose (block, view) workgroups would number fewer than two per CU (512 on
 // the 256 CUs) splits each block's lines over two workgroups, which halves the chain of line steps that
 // bounds a workgroup. The halves write two residual planes (the data term in the first), which the update
-// kernel adds when it stages a view; both planes must fit the residual block of nviews views. 16-bit
-// storage keeps one plane: each half's residual would round to 16 bits before the two cancel.
-bool split_eligible(const GeomDev &, int nv, int nviews, int dtype) { return dtype == CT_F32 && 2 * nv <= nviews; }
+// kernel adds when it stages a view; both planes must fit the residual block of nviews views. The planes
+// are float32 in every storage mode: two 16-bit partial residuals would round before they cancel.
+bool split_eligible(const GeomDev &, int nv, int nviews, int) { return 2 * nv <= nviews; }
 bool launch_underfills(int forward_wgs) { return forward_wgs < 512; }
 bool forward_split(const GeomDev &G, int nv, int nviews, int dtype)
 {
@@ -994,11 +1003,20 @@ int update_workgroups(const GeomDev &G) { return ((G.nx + BP_TX - 1) / BP_TX) * 
 hipError_t launch_forward(const FpLaunch &a, int ones, int epi, int dtype, hipStream_t s)
 {
     if (a.nv <= 0) return hipSuccess;
-    if (a.out2 && (epi != FP_RESIDUAL || dtype != CT_F32 || ones)) return hipErrorInvalidValue;
+    if (a.out2 && (epi != FP_RESIDUAL || ones)) return hipErrorInvalidValue;
     dim3 grid(((a.G.nb + FP_BINS - 1) / FP_BINS) * (a.out2 ? 2 : 1), a.nv), block(FP_BINS * FP_WAVES);
 #define CT_FP(E, O, TI, TY, TO) hipLaunchKernelGGL((k_forward<E, O, FP_WAVES, TI, TY, TO, false>), grid, block, 0, s, a)
-    if (a.out2) {
-        hipLaunchKernelGGL((k_forward<FP_RESIDUAL, false, FP_WAVES, float, float, float, true>), grid, block, 0, s, a);
+    if (a.out2) {   // split: float32 residual planes in every storage mode
+        if (dtype == CT_F32)
+            hipLaunchKernelGGL((k_forward<FP_RESIDUAL, false, FP_WAVES, float, float, float, true>), grid, block, 0, s, a);
+        else if (dtype == CT_F16)
+            hipLaunchKernelGGL((k_forward<FP_RESIDUAL, false, FP_WAVES, _Float16, _Float16, float, true>), grid, block, 0,
+                               s, a);
+        else if (dtype == CT_BF16)
+            hipLaunchKernelGGL((k_forward<FP_RESIDUAL, false, FP_WAVES, __bf16, __bf16, float, true>), grid, block, 0, s,
+                               a);
+        else
+            return hipErrorInvalidValue;
     } else if (dtype == CT_F32) {
         if (ones) {
             if (epi == FP_PLAIN) CT_FP(FP_PLAIN, true, float, float, float);
@@ -1035,10 +1053,21 @@ hipError_t launch_back_update(const BpLaunch &a, int mode, int rtype, int ctype,
     else if (mode == BP_FULL) CT_BP(BP_FULL, T, T);                                                            \
     else if (mode == BP_XSTEP) CT_BP(BP_XSTEP, T, T);                                                          \
     else return hipErrorInvalidValue;
-    if (a.r2) {   // a split forward projection's two residual planes (float32 only)
-        if (rtype != CT_F32 || ctype != CT_F32 || (mode != BP_INIT && mode != BP_FULL)) return hipErrorInvalidValue;
-        if (mode == BP_INIT) hipLaunchKernelGGL((k_back_update<BP_INIT, float, float, 1>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_back_update<BP_FULL, float, float, 1>), grid, block, 0, s, a);
+    if (a.r2) {   // a split forward projection's two float32 residual planes, any image-copy storage
+#define CT_BP2(T)                                                                                              \
+    if (mode == BP_INIT) hipLaunchKernelGGL((k_back_update<BP_INIT, float, T, 1>), grid, block, 0, s, a);      \
+    else hipLaunchKernelGGL((k_back_update<BP_FULL, float, T, 1>), grid, block, 0, s, a);
+        if (rtype != CT_F32 || (mode != BP_INIT && mode != BP_FULL)) return hipErrorInvalidValue;
+        if (ctype == CT_F32) {
+            CT_BP2(float)
+        } else if (ctype == CT_F16) {
+            CT_BP2(_Float16)
+        } else if (ctype == CT_BF16) {
+            CT_BP2(__bf16)
+        } else {
+            return hipErrorInvalidValue;
+        }
+#undef CT_BP2
     } else if (mode == BP_BACK) {
         if (rtype == CT_F32) CT_BP(BP_BACK, float, float);
         else if (rtype == CT_F16) CT_BP(BP_BACK, _Float16, float);

@@ -37,23 +37,26 @@ def small_classes(M):
     return [cls(48, 110, 96), cls(80, 150, 160), cls(128, 220, 256), cls(64, 130, 128)]
 
 
-@pytest.mark.parametrize("M,niters,split", [(5, 3, -1), (10, 2, -1), (10, 2, 0), (10, 2, 1)])
-def test_batched_equals_single_solves_bitwise(api, M, niters, split):
+@pytest.mark.parametrize("M,niters,split,storage", [(5, 3, -1, "f32"), (10, 2, -1, "f32"), (10, 2, 0, "f32"),
+                                                     (10, 2, 1, "f32"), (10, 2, -1, "bf16"), (10, 2, 0, "bf16")])
+def test_batched_equals_single_solves_bitwise(api, M, niters, split, storage):
     """Same bits with the same forward_split setting: automatic (these small batches underfill the device,
-    so the batch and every single launch split), never, always."""
+    so the batch and every single launch split), never, always; float32 and bfloat16 storage (a split
+    projection's residual planes are float32 in both)."""
     import torch
     geoms = small_classes(M)
     scans = [synth.noisy_scan(g, 40 + i, truth=False) for i, g in enumerate(geoms)]
     p = api.Params(alpha=1.999, niters=niters, subset_order="bitrev", start="zero", forward_split=split)
-    Gs = [api.Geometry(g) for g in geoms]
-    ys = [to_dev(s.y) for s in scans]
-    ws = [to_dev(s.w) for s in scans]
+    Gs = [api.Geometry(g, storage) for g in geoms]
+    dt = torch.float32 if storage == "f32" else torch.bfloat16
+    ys = [to_dev(s.y).to(dt) for s in scans]
+    ws = [to_dev(s.w).to(dt) for s in scans]
     xs = [torch.zeros((g.ny, g.nx), device="cuda:0") for g in geoms]
     cfg = api.rlalm_solve_batched(Gs, p, ys, ws, xs)
     assert cfg["fp_waves"] == 16 and not cfg["largest_first"]
     for i, g in enumerate(geoms):
         xr = torch.zeros((g.ny, g.nx), device="cuda:0")
-        api.rlalm_solve(api.Geometry(g), p, ys[i], ws[i], xr)
+        api.rlalm_solve(api.Geometry(g, storage), p, ys[i], ws[i], xr)
         torch.cuda.synchronize()
         assert torch.equal(xs[i], xr), f"slice {i} ({g.nx}^2) differs from its single solve"
 
