@@ -669,9 +669,6 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
         const float lc_r = (float)(ti0 + pi) - 0.5f * (float)(ny - 1), ex_r = (float)(tj0 + pj) - 0.5f * (float)nx;
         float acc[2][2] = {{0.f, 0.f}, {0.f, 0.f}};   // [row][column] within the block
         float4 *E = sh.ent[wave];
-        auto rl_f = [](float x, int q) {
-            return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), q));
-        };
         const int nvw = nv > wave ? (nv - wave + BP_GROUPS - 1) / BP_GROUPS : 0;   // views of this group
         for (int c0 = 0; c0 < nvw; c0 += 64) {
             const int cn = min(64, nvw - c0);
