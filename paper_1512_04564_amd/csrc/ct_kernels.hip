@@ -759,13 +759,20 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
                         const float2 *bv = G.bnd + (size_t)v * (nb + 1);
                         const float *sv = G.scale + (size_t)v * nb;
                         const TR *rv = r + (size_t)vi * nb;
+                        const float *rv2 = (R2 != 0 && r2) ? r2 + (size_t)vi * nb : nullptr;   // a split projection's second plane
+                        auto rs = [&](int k) {
+                            float rk = (float)rv[k];
+                            if constexpr (R2 != 0) {
+                                if (R2 == 1 || rv2) rk += rv2[k];
+                            }
+                            return PRESCALED ? rk : rk * sv[k];
+                        };
 #pragma unroll
                         for (int ln = 0; ln < 2; ++ln)
 #pragma unroll
                             for (int m = 0; m < 2; ++m)
                                 val[ln][m] = bp_view(G, im, lc0 + (float)ln, ex + (float)m, kw0, kw1,
-                                                     [&](int k) { return bv[k]; },
-                                                     [&](int k) { return PRESCALED ? (float)rv[k] : (float)rv[k] * sv[k]; });
+                                                     [&](int k) { return bv[k]; }, rs);
                     }
                     if (row) {
                         acc[0][0] += val[0][0];
