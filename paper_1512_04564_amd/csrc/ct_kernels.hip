@@ -514,6 +514,32 @@ __device__ __forceinline__ void bp_line3(const GeomDev &G, const float4 im, floa
     val[1] = pos ? F2 - F1 : F1 - F2;
 }
 
+// Back-projection of view onto the NP pixels [ex + m, ex + m + 1] (m < NP) of line lc from the cumulative
+// form: the NP + 1 edges are evaluated once each, one after the other (with the same arithmetic as
+// bp_line3), each pixel taking the difference of its two edges' values.
+template <int NP>
+__device__ __forceinline__ void bp_line(const GeomDev &G, const float4 im, float lc, float ex, bool pos, int n,
+                                        float kofs, const float4 *__restrict__ E, float (&val)[NP])
+{
+    const float nlc = lc * im.y;
+    const float dlc = fmaf(lc, im.w, G.dso);
+    float Fp = 0.f;
+#pragma unroll
+    for (int m = 0; m <= NP; ++m) {
+        const float em = ex + (float)m;
+        float t = fmaf(em, im.x, nlc) * rcp_approx(fmaf(em, im.z, dlc));
+        if (G.arc) t = atanf(t);
+        const int e = min(max((int)floorf(fmaf(G.c_kf, t, kofs)), 0), n - 1);
+        const float u = pos ? em : -em;   // the edge in signed coordinates
+        CumBin c = cum_bin(E, e, lc);
+        if ((u < c.ua) | (u > c.ub))   // the estimate missed its edge's bin by a hair: the neighbouring entry
+            c = cum_bin(E, min(max(u < c.ua ? e - 1 : e + 1, 0), n - 1), lc);
+        const float F = cum_value(c, u);
+        if (m > 0) val[m - 1] = pos ? F - Fp : Fp - F;
+        Fp = F;
+    }
+}
+
 // Inclusive prefix sum over the 64 lanes of a wave: shifts within rows of 16 lanes, then the row totals
 // broadcast into the following rows.
 template <int CTRL, int ROWS, typename T>
@@ -663,11 +689,14 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
         const int ti0 = by * BP_TY, ti1 = min(ti0 + BP_TY, ny);
         const int tj0 = bx * BP_TX, tj1 = min(tj0 + BP_TX, nx);
         const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // view group
-        // the lane's block: tile rows 2 (lane / 8) + {0, 1}, columns 2 (lane % 8) + {0, 1}. Row sweep views:
-        // lines are the two rows, edges run along x; column sweep views: lines are the two columns.
-        const int pi = 2 * (lane >> 3), pj = 2 * (lane & 7);
-        const float lc_r = (float)(ti0 + pi) - 0.5f * (float)(ny - 1), ex_r = (float)(tj0 + pj) - 0.5f * (float)nx;
-        float acc[2][2] = {{0.f, 0.f}, {0.f, 0.f}};   // [row][column] within the block
+        // The lane's pixels are four consecutive pixels of one line of the view, so that five edges give four
+        // pixels: for row sweep views tile row r4 = lane / 4, columns q4 + {0..3} (q4 = 4 (lane % 4)), edges
+        // along x; for column sweep views tile column r4, rows q4 + {0..3}, edges along y. Row and column
+        // views accumulate separately (acc_r, acc_c) and meet in the partial sums.
+        const int r4 = lane >> 2, q4 = 4 * (lane & 3);
+        const float lc_row = (float)(ti0 + r4) - 0.5f * (float)(ny - 1), ex_row = (float)(tj0 + q4) - 0.5f * (float)nx;
+        const float lc_col = (float)(tj0 + r4) - 0.5f * (float)(nx - 1), ex_col = (float)(ti0 + q4) - 0.5f * (float)ny;
+        float acc_r[4] = {0.f, 0.f, 0.f, 0.f}, acc_c[4] = {0.f, 0.f, 0.f, 0.f};
         float4 *E = sh.ent[wave];
         const int nvw = nv > wave ? (nv - wave + BP_GROUPS - 1) / BP_GROUPS : 0;   // views of this group
         for (int c0 = 0; c0 < nvw; c0 += 64) {
@@ -743,16 +772,10 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
                     const bool row = ld_uniform(G.rowsweep, vu) != 0;
                     const bool pos = ld_uniform(G.sgn, vu) > 0.f;
                     const int ne = __builtin_amdgcn_readlane(nq, ci);
-                    // column sweep: line of column tj0 + pj at ex_r + 1/2, edges along y from lc_r - 1/2
-                    const float lc0 = row ? lc_r : ex_r + 0.5f, ex = row ? ex_r : lc_r - 0.5f;
-                    float val[2][2];   // [line][pixel along the line]
+                    const float lc0 = row ? lc_row : lc_col, ex = row ? ex_row : ex_col;
+                    float val[4];   // the lane's four pixels along the line
                     if (ne > 0) {
-                        const float kofs = G.k0 - (float)kw0;
-#pragma unroll
-                        for (int ln = 0; ln < 2; ++ln) {
-                            bp_line3(G, im, lc0 + (float)ln, ex, pos, ne - 1, kofs, E, val[ln]);
-                            __builtin_amdgcn_sched_barrier(0);   // one line at a time: bounds register use
-                        }
+                        bp_line<4>(G, im, lc0, ex, pos, ne - 1, G.k0 - (float)kw0, E, val);
                     } else {   // window wider than the staging slots: read the tables directly
                         const int vi = wave + BP_GROUPS * (c0 + ci);
                         const int v = vstart + vi * vstride;
@@ -768,32 +791,26 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
                             return PRESCALED ? rk : rk * sv[k];
                         };
 #pragma unroll
-                        for (int ln = 0; ln < 2; ++ln)
-#pragma unroll
-                            for (int m = 0; m < 2; ++m)
-                                val[ln][m] = bp_view(G, im, lc0 + (float)ln, ex + (float)m, kw0, kw1,
-                                                     [&](int k) { return bv[k]; }, rs);
+                        for (int m = 0; m < 4; ++m)
+                            val[m] = bp_view(G, im, lc0, ex + (float)m, kw0, kw1, [&](int k) { return bv[k]; }, rs);
                     }
                     if (row) {
-                        acc[0][0] += val[0][0];
-                        acc[0][1] += val[0][1];
-                        acc[1][0] += val[1][0];
-                        acc[1][1] += val[1][1];
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) acc_r[m] += val[m];
                     } else {
-                        acc[0][0] += val[0][0];
-                        acc[1][0] += val[0][1];
-                        acc[0][1] += val[1][0];
-                        acc[1][1] += val[1][1];
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) acc_c[m] += val[m];
                     }
                 }
             }
         }
         // partial sums of the group, by tile pixel, in the wave's own slot (its staged reads are complete)
+        // (row views' pixels (r4, q4 + m) first; then each lane adds its column views' pixels (q4 + m, r4):
+        // every pixel of the tile takes one value of each kind, and the wave's LDS operations are in order)
         float *part = reinterpret_cast<float *>(E);
-        part[pi * BP_TX + pj] = acc[0][0];
-        part[pi * BP_TX + pj + 1] = acc[0][1];
-        part[(pi + 1) * BP_TX + pj] = acc[1][0];
-        part[(pi + 1) * BP_TX + pj + 1] = acc[1][1];
+        *reinterpret_cast<float4 *>(part + r4 * BP_TX + q4) = make_float4(acc_r[0], acc_r[1], acc_r[2], acc_r[3]);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) part[(q4 + m) * BP_TX + r4] += acc_c[m];
         __syncthreads();
         if (hv == 0) {
 #pragma unroll
