@@ -690,10 +690,12 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
         const int tj0 = bx * BP_TX, tj1 = min(tj0 + BP_TX, nx);
         const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // view group
         // The lane's pixels are four consecutive pixels of one line of the view, so that five edges give four
-        // pixels: for row sweep views tile row r4 = lane / 4, columns q4 + {0..3} (q4 = 4 (lane % 4)), edges
+        // pixels: for row sweep views tile row r4 = lane % 16, columns q4 + {0..3} (q4 = 4 (lane / 16)), edges
         // along x; for column sweep views tile column r4, rows q4 + {0..3}, edges along y. Row and column
-        // views accumulate separately (acc_r, acc_c) and meet in the partial sums.
-        const int r4 = lane >> 2, q4 = 4 * (lane & 3);
+        // views accumulate separately (acc_r, acc_c) and meet in the partial sums. Consecutive lanes take
+        // neighbouring lines, whose edges fall in the same or nearby staged entries (fewer LDS bank
+        // conflicts than lanes four pixels apart along one line).
+        const int r4 = lane & 15, q4 = 4 * (lane >> 4);
         const float lc_row = (float)(ti0 + r4) - 0.5f * (float)(ny - 1), ex_row = (float)(tj0 + q4) - 0.5f * (float)nx;
         const float lc_col = (float)(tj0 + r4) - 0.5f * (float)(nx - 1), ex_col = (float)(ti0 + q4) - 0.5f * (float)ny;
         float acc_r[4] = {0.f, 0.f, 0.f, 0.f}, acc_c[4] = {0.f, 0.f, 0.f, 0.f};
