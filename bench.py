@@ -132,6 +132,30 @@ def pmc_workload():
     print("counter workload done", flush=True)
 
 
+def unet_workload():
+    """Short workload for a kernel trace of the warm-start network: inference of one 512^2 image with the
+    committed parameters, 5 warm-up and 10 timed passes."""
+    import torch
+    from paper_1512_04564_amd import api, synth, unet
+    g = synth.CFG2
+    s = synth.noisy_scan(g, 100, truth=False)
+    G = api.Geometry(g)
+    y = torch.as_tensor(s.y, device="cuda:0")
+    net = unet.UNet(np.load(UNET_WEIGHTS)["theta"], 1, g.ny, g.nx)
+    xin = unet.network_input(G, y)[None].contiguous()
+    xo = torch.empty_like(xin)
+    for _ in range(5):
+        net.forward(xin, out=xo)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(10):
+        net.forward(xin, out=xo)
+    b.record()
+    torch.cuda.synchronize()
+    print(f"network workload done: {a.elapsed_time(b) / 10:.4f} ms per 512^2 inference", flush=True)
+
+
 def dd_work_counts(g):
     """Distance-driven work per outer iteration (all views), FP64 geometry written out here:
     nonzeros of A, (bin, line) pairs, (pixel, view) pairs."""
@@ -194,11 +218,15 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven 32-slice batch")
     ap.add_argument("--batch-iters", type=int, default=20)
     ap.add_argument("--pmc-workload", action="store_true", help="run the short counter workload and exit")
+    ap.add_argument("--unet-workload", action="store_true", help="run the network inference workload and exit")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the traffic record from the two counter runs and exit (no GPU)")
     args = ap.parse_args()
     if args.pmc_workload:
         pmc_workload()
+        return
+    if args.unet_workload:
+        unet_workload()
         return
     if args.write_traffic:
         write_traffic(*args.write_traffic)
