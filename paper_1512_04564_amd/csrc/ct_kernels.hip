@@ -479,44 +479,10 @@ __device__ __forceinline__ float cum_value(const CumBin &c, float u)
     return fmaf(c.q.w, __builtin_amdgcn_fmed3f((u - c.ua) * rcp_approx(c.ub - c.ua), 0.f, 1.f), c.q.z);
 }
 
-// Back-projection of view onto the two pixels [ex, ex + 1] and [ex + 1, ex + 2] of line lc (val[0],
-// val[1]) from the cumulative form above: the three edges are evaluated once each. kofs = k0 - kw0 (the
-// detector coordinate from the window's first bin), n the window's bins, pos the boundary order.
-__device__ __forceinline__ void bp_line3(const GeomDev &G, const float4 im, float lc, float ex, bool pos, int n,
-                                         float kofs, const float4 *__restrict__ E, float val[2])
-{
-    const float nlc = lc * im.y;
-    const float dlc = fmaf(lc, im.w, G.dso);
-    CumBin c[3];
-    float u[3];
-    int e[3];
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-        const float em = ex + (float)m;
-        float t = fmaf(em, im.x, nlc) * rcp_approx(fmaf(em, im.z, dlc));
-        if (G.arc) t = atanf(t);
-        e[m] = min(max((int)floorf(fmaf(G.c_kf, t, kofs)), 0), n - 1);
-        u[m] = pos ? em : -em;   // the edge in signed coordinates
-        c[m] = cum_bin(E, e[m], lc);
-    }
-    bool miss = false;
-#pragma unroll
-    for (int m = 0; m < 3; ++m) miss |= (u[m] < c[m].ua) | (u[m] > c[m].ub);
-    if (miss) {   // an estimate missed its edge's bin by a hair: take the neighbouring entry
-#pragma unroll
-        for (int m = 0; m < 3; ++m)
-            if ((u[m] < c[m].ua) | (u[m] > c[m].ub))
-                c[m] = cum_bin(E, min(max(u[m] < c[m].ua ? e[m] - 1 : e[m] + 1, 0), n - 1), lc);
-    }
-    const float F0 = cum_value(c[0], u[0]), F1 = cum_value(c[1], u[1]), F2 = cum_value(c[2], u[2]);
-    // pixel m spans the signed edges u[m], u[m + 1] (ascending when pos, descending otherwise)
-    val[0] = pos ? F1 - F0 : F0 - F1;
-    val[1] = pos ? F2 - F1 : F1 - F2;
-}
-
 // Back-projection of view onto the NP pixels [ex + m, ex + m + 1] (m < NP) of line lc from the cumulative
-// form: the NP + 1 edges are evaluated once each, one after the other (with the same arithmetic as
-// bp_line3), each pixel taking the difference of its two edges' values.
+// form: the NP + 1 edges are evaluated once each, one after the other, each pixel taking the difference
+// of its two edges' values. kofs = k0 - kw0 (the detector coordinate from the window's first bin), n the
+// window's bins, pos the boundary order.
 template <int NP>
 __device__ __forceinline__ void bp_line(const GeomDev &G, const float4 im, float lc, float ex, bool pos, int n,
                                         float kofs, const float4 *__restrict__ E, float (&val)[NP])
