@@ -164,63 +164,66 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvSrc S, const bf16 *__restri
 // input value is read from memory once per chunk instead of once per tap and wave; the chunk's weights
 // are staged alike, once per workgroup. FWD / !FWD as in k_conv3x3. Images of n planes; grid (tiles,
 // c_out / 32).
-constexpr int CT_T = 16;                     // tile edge (pixels)
-constexpr int CT_H = CT_T + 2;               // with halo
-template <bool FWD, bool PF>
+constexpr int CT_T = 16;                     // tile width (pixels; one operand block per tile row)
+constexpr int CT_HX = CT_T + 2;              // with halo
+// TY: tile height, 16 (four rows per wave) or 8 (two rows per wave, for layers with few tiles)
+template <bool FWD, bool PF, int TY>
 __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvSrc S, const bf16 *__restrict__ wt,
                                                       const float *__restrict__ bias, const bf16 *__restrict__ mask,
                                                       bf16 *__restrict__ out, int n, int h, int w, int cout)
 {
-    __shared__ bf16x8 tile[CT_H * CT_H * 4];   // [hy][hx][8-channel group]
+    constexpr int RW = TY / 4;                 // tile rows per wave
+    constexpr int HY = TY + 2;                 // haloed rows
+    __shared__ bf16x8 tile[HY * CT_HX * 4];    // [hy][hx][8-channel group]
     constexpr int WP = 9 * 4 + 1;              // weight row pitch (16-byte units), padded against bank conflicts
     __shared__ bf16x8 wts[32 * WP];            // [c_out of the block][tap][8-channel group]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int cin = S.c0 + S.c1;
-    const int tx = (w + CT_T - 1) / CT_T, ty = (h + CT_T - 1) / CT_T;
+    const int tx = (w + CT_T - 1) / CT_T, ty = (h + TY - 1) / TY;
     int t = blockIdx.x;
     const int tix = t % tx;
     t /= tx;
     const int tiy = t % ty;
     const int pn = t / ty;
-    const int x0 = tix * CT_T, y0 = tiy * CT_T;
+    const int x0 = tix * CT_T, y0 = tiy * TY;
     const int co0 = blockIdx.y * 32;
     const int g = lane >> 4, r = lane & 15;
-    f32x4 acc[2][4];
+    f32x4 acc[2][RW];
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
-        for (int s = 0; s < 4; ++s) acc[m][s] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int s = 0; s < RW; ++s) acc[m][s] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bf16x8 zero8 = {};
     auto taps = [&]() {
         for (int tap = 0; tap < 9; ++tap) {
             const int dy = tap / 3, dx = tap % 3;   // offsets into the haloed tile
-            bf16x8 a[2], b[4];
+            bf16x8 a[2], b[RW];
 #pragma unroll
             for (int m = 0; m < 2; ++m) a[m] = wts[(16 * m + r) * WP + tap * 4 + g];
 #pragma unroll
-            for (int s = 0; s < 4; ++s) b[s] = tile[((4 * wave + s + dy) * CT_H + r + dx) * 4 + g];
+            for (int s = 0; s < RW; ++s) b[s] = tile[((RW * wave + s + dy) * CT_HX + r + dx) * 4 + g];
 #pragma unroll
             for (int m = 0; m < 2; ++m)
 #pragma unroll
-                for (int s = 0; s < 4; ++s)
+                for (int s = 0; s < RW; ++s)
                     acc[m][s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[s], acc[m][s], 0, 0, 0);
         }
     };
     if constexpr (PF) {
         // A chunk's input tile and weights go through registers: the next chunk's loads are issued before
-        // the current chunk's taps, so that their latency overlaps the matrix work (ceil(18 * 18 * 4 / 256)
-        // = 6 and ceil(32 * 9 * 4 / 256) = 5 values per thread). For layers with few workgroups per CU,
-        // which have no other workgroup to run during a chunk's loads.
-        constexpr int NT = (CT_H * CT_H * 4 + 255) / 256, NW = (32 * 9 * 4 + 255) / 256;
+        // the current chunk's taps, so that their latency overlaps the matrix work (ceil(HY * 18 * 4 / 256)
+        // and ceil(32 * 9 * 4 / 256) = 5 values per thread). For layers with few workgroups per CU, which
+        // have no other workgroup to run during a chunk's loads.
+        constexpr int NT = (HY * CT_HX * 4 + 255) / 256, NW = (32 * 9 * 4 + 255) / 256;
         bf16x8 pt[NT], pw[NW];
         auto load_chunk = [&](int ci0) {
 #pragma unroll
             for (int i = 0; i < NT; ++i) {
                 const int v = threadIdx.x + 256 * i;
                 const int px = v >> 2, part = v & 3;
-                const int yy = y0 - 1 + px / CT_H, xx = x0 - 1 + px % CT_H;
+                const int yy = y0 - 1 + px / CT_HX, xx = x0 - 1 + px % CT_HX;
                 pt[i] = zero8;
-                if (v < CT_H * CT_H * 4 && yy >= 0 && yy < h && xx >= 0 && xx < w)
+                if (v < HY * CT_HX * 4 && yy >= 0 && yy < h && xx >= 0 && xx < w)
                     pt[i] = *reinterpret_cast<const bf16x8 *>(src_ptr(S, ci0 + 8 * part, pn, yy, xx, h, w));
             }
 #pragma unroll
@@ -238,7 +241,7 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvSrc S, const bf16 *__r
 #pragma unroll
             for (int i = 0; i < NT; ++i) {
                 const int v = threadIdx.x + 256 * i;
-                if (v < CT_H * CT_H * 4) tile[v] = pt[i];
+                if (v < HY * CT_HX * 4) tile[v] = pt[i];
             }
 #pragma unroll
             for (int i = 0; i < NW; ++i) {
@@ -252,9 +255,9 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvSrc S, const bf16 *__r
     } else {
         for (int ci0 = 0; ci0 < cin; ci0 += 32) {
             __syncthreads();   // the previous chunk's reads are done
-            for (int v = threadIdx.x; v < CT_H * CT_H * 4; v += 256) {
+            for (int v = threadIdx.x; v < HY * CT_HX * 4; v += 256) {
                 const int px = v >> 2, part = v & 3;
-                const int yy = y0 - 1 + px / CT_H, xx = x0 - 1 + px % CT_H;
+                const int yy = y0 - 1 + px / CT_HX, xx = x0 - 1 + px % CT_HX;
                 bf16x8 val = zero8;
                 if (yy >= 0 && yy < h && xx >= 0 && xx < w)
                     val = *reinterpret_cast<const bf16x8 *>(src_ptr(S, ci0 + 8 * part, pn, yy, xx, h, w));
@@ -273,8 +276,8 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvSrc S, const bf16 *__r
     for (int m = 0; m < 2; ++m) {
         const int co = co0 + 16 * m + 4 * g;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int yy = y0 + 4 * wave + s, xx = x0 + r;
+        for (int s = 0; s < RW; ++s) {
+            const int yy = y0 + RW * wave + s, xx = x0 + r;
             if (yy >= h || xx >= w) continue;
             const size_t o = (((size_t)pn * h + yy) * w + xx) * cout + co;
             bf16x4 v;
@@ -777,9 +780,31 @@ bool split_k(size_t npix, int cout) { return ((npix + 63) / 64) * (size_t)(cout 
 // output channels) use it; below four workgroups per CU it prefetches each channel chunk into registers,
 // which hides the chunk loads well enough to beat the split form down to a quarter workgroup per CU.
 int tiles16(int e) { return (e + 15) / 16; }
-size_t tile_wgs(int n, int h, int w, int cout) { return (size_t)n * tiles16(h) * tiles16(w) * (cout / 32); }
+size_t tile_wgs(int n, int h, int w, int cout, int ty = 16)
+{
+    return (size_t)n * ((h + ty - 1) / ty) * tiles16(w) * (cout / 32);
+}
 bool use_tile(int n, int h, int w, int cout) { return tile_wgs(n, h, w, cout) >= 64; }
-bool tile_prefetch(int n, int h, int w, int cout) { return tile_wgs(n, h, w, cout) < 1024; }
+// fewer 16 x 16 tiles than CUs: 8-row tiles (twice the workgroups)
+int tile_rows(int n, int h, int w, int cout) { return tile_wgs(n, h, w, cout) < 256 ? 8 : 16; }
+bool tile_prefetch(int n, int h, int w, int cout) { return tile_wgs(n, h, w, cout, tile_rows(n, h, w, cout)) < 1024; }
+
+// The tiled convolution for (n, h, w, c) with c output channels (forward) or input channels (data
+// gradient): tile height and prefetch chosen as above.
+template <bool FWD>
+void launch_conv_tile(const ConvSrc &S, const bf16 *wt, const float *bias, const bf16 *mask, bf16 *out, int n, int h,
+                      int w, int c, hipStream_t s)
+{
+    const int ty = tile_rows(n, h, w, c);
+    dim3 grid(n * ((h + ty - 1) / ty) * tiles16(w), c / 32);
+    const bool pf = tile_prefetch(n, h, w, c);
+    if (ty == 8)
+        hipLaunchKernelGGL((k_conv3x3_tile<FWD, true, 8>), grid, dim3(256), 0, s, S, wt, bias, mask, out, n, h, w, c);
+    else if (pf)
+        hipLaunchKernelGGL((k_conv3x3_tile<FWD, true, 16>), grid, dim3(256), 0, s, S, wt, bias, mask, out, n, h, w, c);
+    else
+        hipLaunchKernelGGL((k_conv3x3_tile<FWD, false, 16>), grid, dim3(256), 0, s, S, wt, bias, mask, out, n, h, w, c);
+}
 
 ConvSrc one(const bf16 *src, int c) { return ConvSrc{src, c, 0, nullptr, 0}; }
 ConvSrc cat(const bf16 *low, int cl, const bf16 *skip, int cs) { return ConvSrc{low, cl, 1, skip, cs}; }
@@ -790,13 +815,7 @@ hipError_t conv_fwd(const ct_unet *u, int l, const ConvSrc &S, bf16 *out, int n,
     const size_t npix = (size_t)n * h * w;
     const float *bias = u->theta + u->off[l] + (size_t)cout * kShape[l][0] * 9;
     if (use_tile(n, h, w, cout)) {
-        dim3 grid(n * tiles16(h) * tiles16(w), cout / 32);
-        if (tile_prefetch(n, h, w, cout))
-            hipLaunchKernelGGL((k_conv3x3_tile<true, true>), grid, dim3(256), 0, s, S, u->wf[l], bias, nullptr, out, n,
-                               h, w, cout);
-        else
-            hipLaunchKernelGGL((k_conv3x3_tile<true, false>), grid, dim3(256), 0, s, S, u->wf[l], bias, nullptr, out,
-                               n, h, w, cout);
+        launch_conv_tile<true>(S, u->wf[l], bias, nullptr, out, n, h, w, cout, s);
     } else if (split_k(npix, cout)) {
         dim3 grid(blocks(npix, 64), cout / 32);
         hipLaunchKernelGGL((k_conv3x3<true, 4>), grid, dim3(256), 0, s, S, u->wf[l], bias, nullptr, out, n, h, w, cout);
@@ -814,13 +833,7 @@ hipError_t conv_dgrad(const ct_unet *u, int l, const bf16 *dz, const bf16 *act, 
     const int cin = kShape[l][0], cout = kShape[l][1];
     const size_t npix = (size_t)n * h * w;
     if (use_tile(n, h, w, cin)) {
-        dim3 grid(n * tiles16(h) * tiles16(w), cin / 32);
-        if (tile_prefetch(n, h, w, cin))
-            hipLaunchKernelGGL((k_conv3x3_tile<false, true>), grid, dim3(256), 0, s, one(dz, cout), u->wb[l], nullptr,
-                               act, out, n, h, w, cin);
-        else
-            hipLaunchKernelGGL((k_conv3x3_tile<false, false>), grid, dim3(256), 0, s, one(dz, cout), u->wb[l], nullptr,
-                               act, out, n, h, w, cin);
+        launch_conv_tile<false>(one(dz, cout), u->wb[l], nullptr, act, out, n, h, w, cin, s);
     } else if (split_k(npix, cin)) {
         dim3 grid(blocks(npix, 64), cin / 32);
         hipLaunchKernelGGL((k_conv3x3<false, 4>), grid, dim3(256), 0, s, one(dz, cout), u->wb[l], nullptr, act, out, n,
