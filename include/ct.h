@@ -136,11 +136,12 @@ typedef struct {
                             workspace is rewritten); read with ct_rlalm_kernel_times                  */
     const ct_unet *unet; /* network of start == 3 (its max sizes must cover the image; ny, nx
                             multiples of 8); NULL otherwise                                           */
-    int forward_split;   /* float32 storage, at least two subsets: split each forward block's lines over
-                            two workgroups, whose two residual planes the update adds (-1: when the
-                            launch would hold fewer than two workgroups per CU, counting all slices of
-                            a batched launch; 0: never; 1: always). The same setting gives the same bits
-                            in single and batched solves; other values are CT_ERR_INVALID_ARG         */
+    int forward_split;   /* at least two subsets: split each forward block's lines over two workgroups,
+                            whose two float32 residual planes (in every storage mode) the update adds
+                            (-1: when the launch would hold fewer than two workgroups per CU, counting
+                            all slices of a batched launch; 0: never; 1: always). The same setting gives
+                            the same bits in single and batched solves; other values are
+                            CT_ERR_INVALID_ARG                                                        */
 } ct_rlalm_params;
 
 /* Fill p with the defaults: alpha 1.999, 20 iterations, continuation, hyperbola delta 1e-4 beta 1024,
