@@ -38,7 +38,8 @@ def small_classes(M):
 
 
 @pytest.mark.parametrize("M,niters,split,storage", [(5, 3, -1, "f32"), (10, 2, -1, "f32"), (10, 2, 0, "f32"),
-                                                     (10, 2, 1, "f32"), (10, 2, -1, "bf16"), (10, 2, 0, "bf16")])
+                                                     (10, 2, 1, "f32"), (10, 2, -1, "bf16"), (10, 2, 0, "bf16"),
+                                                     (10, 2, 1, "bf16"), (10, 2, -1, "f16")])
 def test_batched_equals_single_solves_bitwise(api, M, niters, split, storage):
     """Same bits with the same forward_split setting: automatic (these small batches underfill the device,
     so the batch and every single launch split), never, always; float32 and bfloat16 storage (a split
@@ -48,9 +49,10 @@ def test_batched_equals_single_solves_bitwise(api, M, niters, split, storage):
     scans = [synth.noisy_scan(g, 40 + i, truth=False) for i, g in enumerate(geoms)]
     p = api.Params(alpha=1.999, niters=niters, subset_order="bitrev", start="zero", forward_split=split)
     Gs = [api.Geometry(g, storage) for g in geoms]
-    dt = torch.float32 if storage == "f32" else torch.bfloat16
+    dt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[storage]
+    wscale = 2.0 ** -6 if storage == "f16" else 1.0   # counts-sized weights into float16 range (same inputs on both sides)
     ys = [to_dev(s.y).to(dt) for s in scans]
-    ws = [to_dev(s.w).to(dt) for s in scans]
+    ws = [(to_dev(s.w) * wscale).to(dt) for s in scans]
     xs = [torch.zeros((g.ny, g.nx), device="cuda:0") for g in geoms]
     cfg = api.rlalm_solve_batched(Gs, p, ys, ws, xs)
     assert cfg["fp_waves"] == 16 and not cfg["largest_first"]
