@@ -167,10 +167,12 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvSrc S, const bf16 *__restri
 constexpr int CT_T = 16;                     // tile width (pixels; one operand block per tile row)
 constexpr int CT_HX = CT_T + 2;              // with halo
 // TY: tile height, 16 (four rows per wave) or 8 (two rows per wave, for layers with few tiles)
+// pooled (forward, may be null): also writes the 2 x 2 average of the output (h, w even), as k_pool would.
 template <bool FWD, bool PF, int TY>
 __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvSrc S, const bf16 *__restrict__ wt,
                                                       const float *__restrict__ bias, const bf16 *__restrict__ mask,
-                                                      bf16 *__restrict__ out, int n, int h, int w, int cout)
+                                                      bf16 *__restrict__ out, int n, int h, int w, int cout,
+                                                      bf16 *__restrict__ pooled)
 {
     constexpr int RW = TY / 4;                 // tile rows per wave
     constexpr int HY = TY + 2;                 // haloed rows
@@ -289,6 +291,26 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvSrc S, const bf16 *__r
                 v[j] = (bf16)tv;
             }
             *reinterpret_cast<bf16x4 *>(out + o) = v;
+        }
+        if (FWD && pooled) {
+            // 2 x 2 average of the stored (rounded) outputs: rows s, s + 1 of this lane, columns r (even) and
+            // r + 1 of the next lane, added in k_pool's order; every lane takes part in the exchange
+#pragma unroll
+            for (int s = 0; s < RW; s += 2) {
+                const int yy = y0 + RW * wave + s, xx = x0 + r;
+                bf16x4 q;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float v0 = (float)(bf16)fmaxf(acc[m][s][j] + bias[co + j], 0.f);
+                    const float v1 = (float)(bf16)fmaxf(acc[m][s + 1][j] + bias[co + j], 0.f);
+                    const float v01 = __shfl_xor(v0, 1), v11 = __shfl_xor(v1, 1);
+                    q[j] = (bf16)(0.25f * (((v0 + v01) + v1) + v11));
+                }
+                if ((r & 1) == 0 && yy + 1 < h && xx + 1 < w) {
+                    const int ho = h / 2, wo = w / 2;
+                    *reinterpret_cast<bf16x4 *>(pooled + (((size_t)pn * ho + yy / 2) * wo + xx / 2) * cout + co) = q;
+                }
+            }
         }
     }
 }
@@ -793,35 +815,47 @@ bool tile_prefetch(int n, int h, int w, int cout) { return tile_wgs(n, h, w, cou
 // gradient): tile height and prefetch chosen as above.
 template <bool FWD>
 void launch_conv_tile(const ConvSrc &S, const bf16 *wt, const float *bias, const bf16 *mask, bf16 *out, int n, int h,
-                      int w, int c, hipStream_t s)
+                      int w, int c, hipStream_t s, bf16 *pooled = nullptr)
 {
     const int ty = tile_rows(n, h, w, c);
     dim3 grid(n * ((h + ty - 1) / ty) * tiles16(w), c / 32);
     const bool pf = tile_prefetch(n, h, w, c);
     if (ty == 8)
-        hipLaunchKernelGGL((k_conv3x3_tile<FWD, true, 8>), grid, dim3(256), 0, s, S, wt, bias, mask, out, n, h, w, c);
+        hipLaunchKernelGGL((k_conv3x3_tile<FWD, true, 8>), grid, dim3(256), 0, s, S, wt, bias, mask, out, n, h, w, c,
+                           pooled);
     else if (pf)
-        hipLaunchKernelGGL((k_conv3x3_tile<FWD, true, 16>), grid, dim3(256), 0, s, S, wt, bias, mask, out, n, h, w, c);
+        hipLaunchKernelGGL((k_conv3x3_tile<FWD, true, 16>), grid, dim3(256), 0, s, S, wt, bias, mask, out, n, h, w, c,
+                           pooled);
     else
-        hipLaunchKernelGGL((k_conv3x3_tile<FWD, false, 16>), grid, dim3(256), 0, s, S, wt, bias, mask, out, n, h, w, c);
+        hipLaunchKernelGGL((k_conv3x3_tile<FWD, false, 16>), grid, dim3(256), 0, s, S, wt, bias, mask, out, n, h, w, c,
+                           pooled);
 }
 
 ConvSrc one(const bf16 *src, int c) { return ConvSrc{src, c, 0, nullptr, 0}; }
 ConvSrc cat(const bf16 *low, int cl, const bf16 *skip, int cs) { return ConvSrc{low, cl, 1, skip, cs}; }
 
-hipError_t conv_fwd(const ct_unet *u, int l, const ConvSrc &S, bf16 *out, int n, int h, int w, hipStream_t s)
+// pooled (may be null): also the 2 x 2 average of the output, fused into the tiled form, else by k_pool
+hipError_t conv_fwd(const ct_unet *u, int l, const ConvSrc &S, bf16 *out, int n, int h, int w, hipStream_t s,
+                    bf16 *pooled = nullptr)
 {
     const int cout = kShape[l][1];
     const size_t npix = (size_t)n * h * w;
     const float *bias = u->theta + u->off[l] + (size_t)cout * kShape[l][0] * 9;
     if (use_tile(n, h, w, cout)) {
-        launch_conv_tile<true>(S, u->wf[l], bias, nullptr, out, n, h, w, cout, s);
+        launch_conv_tile<true>(S, u->wf[l], bias, nullptr, out, n, h, w, cout, s, pooled);
+        return hipGetLastError();
     } else if (split_k(npix, cout)) {
         dim3 grid(blocks(npix, 64), cout / 32);
         hipLaunchKernelGGL((k_conv3x3<true, 4>), grid, dim3(256), 0, s, S, u->wf[l], bias, nullptr, out, n, h, w, cout);
     } else {
         dim3 grid(blocks(npix, 256), cout / 32);
         hipLaunchKernelGGL((k_conv3x3<true, 1>), grid, dim3(256), 0, s, S, u->wf[l], bias, nullptr, out, n, h, w, cout);
+    }
+    if (pooled) {
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const size_t nq = (size_t)n * (h / 2) * (w / 2) * (cout / 8);
+        hipLaunchKernelGGL(k_pool, dim3(blocks(nq, 256)), dim3(256), 0, s, out, pooled, n, h / 2, w / 2, cout);
     }
     return hipGetLastError();
 }
@@ -886,17 +920,11 @@ ct_status run_forward(ct_unet *u, const float *x, int n, int h, int w, hipStream
     hipLaunchKernelGGL(k_conv_in, dim3(blocks(P1, 256)), dim3(256), 0, s, x, u->theta + u->off[0], bias_of(u, 0), u->e1a, n,
                        h, w);
     CT_HIP_CHECK(hipGetLastError());
-    CT_HIP_CHECK(conv_fwd(u, 1, one(u->e1a, 32), u->e1b, n, h, w, s));
-    hipLaunchKernelGGL(k_pool, dim3(blocks(P1 / 4 * 4, 256)), dim3(256), 0, s, u->e1b, u->p1, n, h2, w2, 32);
-    CT_HIP_CHECK(hipGetLastError());
+    CT_HIP_CHECK(conv_fwd(u, 1, one(u->e1a, 32), u->e1b, n, h, w, s, u->p1));
     CT_HIP_CHECK(conv_fwd(u, 2, one(u->p1, 32), u->e2a, n, h2, w2, s));
-    CT_HIP_CHECK(conv_fwd(u, 3, one(u->e2a, 64), u->e2b, n, h2, w2, s));
-    hipLaunchKernelGGL(k_pool, dim3(blocks(P1 / 16 * 8, 256)), dim3(256), 0, s, u->e2b, u->p2, n, h3, w3, 64);
-    CT_HIP_CHECK(hipGetLastError());
+    CT_HIP_CHECK(conv_fwd(u, 3, one(u->e2a, 64), u->e2b, n, h2, w2, s, u->p2));
     CT_HIP_CHECK(conv_fwd(u, 4, one(u->p2, 64), u->e3a, n, h3, w3, s));
-    CT_HIP_CHECK(conv_fwd(u, 5, one(u->e3a, 128), u->e3b, n, h3, w3, s));
-    hipLaunchKernelGGL(k_pool, dim3(blocks(P1 / 64 * 16, 256)), dim3(256), 0, s, u->e3b, u->p3, n, h4, w4, 128);
-    CT_HIP_CHECK(hipGetLastError());
+    CT_HIP_CHECK(conv_fwd(u, 5, one(u->e3a, 128), u->e3b, n, h3, w3, s, u->p3));
     CT_HIP_CHECK(conv_fwd(u, 6, one(u->p3, 128), u->ba, n, h4, w4, s));
     CT_HIP_CHECK(conv_fwd(u, 7, one(u->ba, 256), u->bb, n, h4, w4, s));
     CT_HIP_CHECK(conv_fwd(u, 8, cat(u->bb, 256, u->e3b, 128), u->d3a, n, h3, w3, s));
