@@ -422,31 +422,37 @@ __global__ void k_sum_parts(const float *__restrict__ part, int nsplit, int n, f
 }
 
 // Input layer (one channel, 32 outputs): out[p][co] = relu(b[co] + sum_tap W[co][tap] x[p + tap]).
-__global__ void k_conv_in(const float *__restrict__ x, const float *__restrict__ W, const float *__restrict__ b,
-                          bf16 *__restrict__ out, int n, int h, int w)
+// Four lanes per pixel, eight channels each, so that a wave's stores cover 1 KiB contiguously; the
+// weights and bias are staged in LDS once per workgroup.
+__global__ __launch_bounds__(256) void k_conv_in(const float *__restrict__ x, const float *__restrict__ W,
+                                                 const float *__restrict__ b, bf16 *__restrict__ out, int n, int h,
+                                                 int w)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ float sw[32 * 9 + 32];
+    for (int i = threadIdx.x; i < 32 * 9 + 32; i += 256) sw[i] = i < 32 * 9 ? W[i] : b[i - 32 * 9];
+    __syncthreads();
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int hw = h * w;
-    if (p >= n * hw) return;
-    const int pn = p / hw, rem = p - pn * hw, py = rem / w, px = rem - py * w;
+    if (t >= (size_t)n * hw * 4) return;
+    const int q = (int)(t & 3);
+    const size_t p = t >> 2;
+    const int pn = (int)(p / hw), rem = (int)(p - (size_t)pn * hw), py = rem / w, px = rem - py * w;
     float v[9];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        const int yy = py + t / 3 - 1, xx = px + t % 3 - 1;
-        v[t] = (yy >= 0 && yy < h && xx >= 0 && xx < w) ? x[(size_t)pn * hw + yy * w + xx] : 0.f;
+    for (int k = 0; k < 9; ++k) {
+        const int yy = py + k / 3 - 1, xx = px + k % 3 - 1;
+        v[k] = (yy >= 0 && yy < h && xx >= 0 && xx < w) ? x[(size_t)pn * hw + yy * w + xx] : 0.f;
     }
-    for (int c8 = 0; c8 < 32; c8 += 8) {
-        bf16x8 o;
+    bf16x8 o;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int co = c8 + i;
-            float z = b[co];
+    for (int i = 0; i < 8; ++i) {
+        const int co = 8 * q + i;
+        float z = sw[32 * 9 + co];
 #pragma unroll
-            for (int t = 0; t < 9; ++t) z = fmaf(W[co * 9 + t], v[t], z);
-            o[i] = (bf16)fmaxf(z, 0.f);
-        }
-        *reinterpret_cast<bf16x8 *>(out + (size_t)p * 32 + c8) = o;
+        for (int k = 0; k < 9; ++k) z = fmaf(sw[co * 9 + k], v[k], z);
+        o[i] = (bf16)fmaxf(z, 0.f);
     }
+    *reinterpret_cast<bf16x8 *>(out + p * 32 + 8 * q) = o;
 }
 
 // Input layer weight / bias gradient partials: thread t < 288 accumulates (co, tap) = (t / 9, t % 9),
@@ -917,7 +923,7 @@ ct_status run_forward(ct_unet *u, const float *x, int n, int h, int w, hipStream
 {
     const size_t P1 = (size_t)n * h * w;
     const int h2 = h / 2, w2 = w / 2, h3 = h / 4, w3 = w / 4, h4 = h / 8, w4 = w / 8;
-    hipLaunchKernelGGL(k_conv_in, dim3(blocks(P1, 256)), dim3(256), 0, s, x, u->theta + u->off[0], bias_of(u, 0), u->e1a, n,
+    hipLaunchKernelGGL(k_conv_in, dim3(blocks(P1 * 4, 256)), dim3(256), 0, s, x, u->theta + u->off[0], bias_of(u, 0), u->e1a, n,
                        h, w);
     CT_HIP_CHECK(hipGetLastError());
     CT_HIP_CHECK(conv_fwd(u, 1, one(u->e1a, 32), u->e1b, n, h, w, s, u->p1));
