@@ -813,8 +813,8 @@ size_t tile_wgs(int n, int h, int w, int cout, int ty = 16)
     return (size_t)n * ((h + ty - 1) / ty) * tiles16(w) * (cout / 32);
 }
 bool use_tile(int n, int h, int w, int cout) { return tile_wgs(n, h, w, cout) >= 64; }
-// fewer 16 x 16 tiles than CUs: 8-row tiles (twice the workgroups)
-int tile_rows(int n, int h, int w, int cout) { return tile_wgs(n, h, w, cout) < 256 ? 8 : 16; }
+// fewer than two workgroups of 16 x 16 tiles per CU: 8-row tiles (twice the workgroups)
+int tile_rows(int n, int h, int w, int cout) { return tile_wgs(n, h, w, cout) < 512 ? 8 : 16; }
 bool tile_prefetch(int n, int h, int w, int cout) { return tile_wgs(n, h, w, cout, tile_rows(n, h, w, cout)) < 1024; }
 
 // The tiled convolution for (n, h, w, c) with c output channels (forward) or input channels (data
