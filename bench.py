@@ -374,8 +374,10 @@ def main():
         net = unet.UNet(np.load(UNET_WEIGHTS)["theta"], 1, g.ny, g.nx)
         xin = unet.network_input(G, y)[None].contiguous()
         xo = torch.empty_like(xin)
-        net.forward(xin, out=xo)
-        t_inf = timed(lambda: net.forward(xin, out=xo), 20)
+        for _ in range(5):
+            net.forward(xin, out=xo)
+        # median of five windows of 20 back-to-back inferences
+        t_inf = float(np.median([timed(lambda: net.forward(xin, out=xo), 20) for _ in range(5)]))
         fl = unet_flops(g.ny, g.nx)
         unet_line = {"ms_forward_512": round(t_inf * 1e3, 4), "gflop_per_forward": round(fl / 1e9, 2),
                      "tflops": round(fl / t_inf / 1e12, 1), "bound": "mfma", "peak_tflops": MFMA_BF16_PEAK_TFLOPS,
