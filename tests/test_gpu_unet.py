@@ -76,7 +76,10 @@ def test_forward_parity(mods, n, h, w):
     assert e <= 2e-2
 
 
-@pytest.mark.parametrize("n,h,w", [(2, 64, 64), (2, 24, 40)])
+# 2 x 256^2 runs the LDS-tiled convolution in both directions with 16-row tiles (with and without the
+# chunk prefetch) and 8-row tiles, and the pooling fused into its forward epilogue; the smaller images
+# run the untiled forms
+@pytest.mark.parametrize("n,h,w", [(2, 64, 64), (2, 24, 40), (2, 256, 256)])
 def test_gradient_parity_every_layer(mods, n, h, w):
     import torch
     _, unet = mods
