@@ -11,7 +11,8 @@
  *   - regularizer   R(x) = sum_i beta_i sum_n phi([C_i x]_n)            (Section III, eq. def_reg; kappa = 1)
  *   - D_L = diag{A' W A 1}                                               (Section III-A, diagonal majorizer)
  *   - Huber curvature D_R of R at the current x                          (Section III-A)
- *   - Algorithm 1 (proposed over-relaxed OS-LALM) and Algorithm 2 (simple relaxation)
+ *   - the proposed relaxed OS-LALM (Algorithm 1) as a state transition written from eq.
+ *     relaxed_lal_iter_quad, and the simple relaxation (Algorithm 2)
  *   - the alpha-dependent continuation rho_k(alpha)                      (Section III-B, eq. dec_rho)
  *   - reference solution x* by FGM with gradient-based adaptive restart  (Section IV-A, footnote reference)
  *
@@ -498,57 +499,85 @@ void or_kappa(const or_geom *g, const double *w, double *kap)
 }
 
 /*
- * State of the iteration after t subiterations: x, g, h (all [ny][nx]); dl given.
- * Runs subiterations t0 .. t0+nsub-1, each on subset m = t mod M.
- * trace_x: optional, receives x after every completed outer iteration boundary? (not used: NULL)
+ * One subiteration as a state transition (x, g, h) at subiteration t -> the state at t + 1, written from
+ * the quadratic-loss form of the proposed relaxed linearized AL iteration (eq. relaxed_lal_iter_quad)
+ * under the substitution A <- W^(1/2) A, y <- W^(1/2) y (eq. ct_substitution), with phi the indicator of
+ * Omega, psi = R majorized by its Huber-curvature quadratic Q_R(.; x) (Section III-A), D_A = D_L, the
+ * subset gradient M grad L_m in place of grad L (ordered subsets, m the subset of subiteration t), and
+ * rho = rho_t (eq. dec_rho; t counts subiterations):
+ *   gamma = (rho - 1) g + rho h
+ *   x+    = argmin_{x in Omega} Q_R(x; x_old) + 1/2 || x - (rho D_L)^-1 gamma ||^2_{rho D_L}
+ *         = [ (rho D_L + D_R)^-1 (gamma + D_R x_old - grad R(x_old)) ]_+     (separable, clipped)
+ *   zeta  = M grad L_m(x+)
+ *   g+    = rho/(rho+1) (alpha zeta + (1 - alpha) g) + g/(rho+1)
+ *   h+    = alpha (D_L x+ - zeta) + (1 - alpha) h
+ * The simple relaxation (the paper's second OS algorithm, Algorithm 2) has no h recursion; its x-step
+ * linearizes at the last subset gradient, gamma = rho (D_L x_old - zeta_old) + (rho - 1) g, and the h
+ * slot holds that last zeta.
  */
+typedef struct {
+    const or_geom *g;
+    const or_params *pp;
+    const double *y, *w, *dl, *kap;
+    int M, nvm;
+    int *order, *views;
+    double *p, *zeta, *gr, *dr;
+} or_machine;
+
+static void transition(const or_machine *mc, long long t, double *x, double *gv, double *h)
+{
+    const or_params *pp = mc->pp;
+    const size_t npix = (size_t)mc->g->nx * mc->g->ny;
+    const double rho = pp->rho_mode == 0 ? or_rho(t, pp->alpha) : pp->rho_fixed;
+    const double alpha = pp->alpha;
+    /* majorizer of R at the current image: grad R(x_old) and the Huber curvature D_R(x_old) */
+    or_reg_grad_k(mc->g->nx, mc->g->ny, x, pp->potential, pp->delta, pp->beta, pp->huber, mc->kap, mc->gr, mc->dr);
+    for (size_t j = 0; j < npix; ++j) {
+        const double gamma = pp->algorithm == 1 ? (rho - 1.0) * gv[j] + rho * h[j]
+                                                : rho * (mc->dl[j] * x[j] - h[j]) + (rho - 1.0) * gv[j];
+        const double curv = rho * mc->dl[j] + mc->dr[j];
+        const double xn = curv > 0.0 ? (gamma + mc->dr[j] * x[j] - mc->gr[j]) / curv : x[j];
+        x[j] = xn > 0.0 ? xn : 0.0;
+    }
+    const int nv = or_subset_views(mc->g->nviews, mc->M, mc->order[t % mc->M], mc->views);
+    subset_grad(mc->g, mc->views, nv, mc->y, mc->w, x, (double)mc->M, mc->p, mc->zeta);
+    for (size_t j = 0; j < npix; ++j) {
+        const double z = mc->zeta[j], gold = gv[j];
+        gv[j] = rho / (rho + 1.0) * (alpha * z + (1.0 - alpha) * gold) + gold / (rho + 1.0);
+        h[j] = pp->algorithm == 1 ? alpha * (mc->dl[j] * x[j] - z) + (1.0 - alpha) * h[j] : z;
+    }
+}
+
+/* Runs the transitions t0 .. t0+nsub-1 on the state (x, g, h); optionally records the RMSD (HU, over mask)
+   to xref after every trace_every whole iterations. */
 static void rlalm_subiters(const or_geom *g, const or_params *pp, const double *y, const double *w,
                            const double *dl, const double *kap, double *x, double *gv, double *h, long long t0,
                            long long nsub, double *rmsd_ref_out, const double *xref, const unsigned char *mask,
                            double mu_w, int trace_every)
 {
-    int M = pp->nsubsets;
-    int *order = (int *)malloc(sizeof(int) * M);
-    subset_order_table(M, pp->subset_order, order);
-    size_t npix = (size_t)g->nx * g->ny;
-    int nvm = g->nviews / M;
-    int *views = (int *)malloc(sizeof(int) * (nvm + 1));
-    double *p = (double *)malloc(sizeof(double) * (size_t)(nvm + 1) * g->nb);
-    double *zeta = (double *)malloc(sizeof(double) * npix);
-    double *gr = (double *)malloc(sizeof(double) * npix);
-    double *dr = (double *)malloc(sizeof(double) * npix);
-    double alpha = pp->alpha;
+    or_machine mc;
+    const size_t npix = (size_t)g->nx * g->ny;
+    mc.g = g; mc.pp = pp; mc.y = y; mc.w = w; mc.dl = dl; mc.kap = kap;
+    mc.M = pp->nsubsets;
+    mc.nvm = g->nviews / mc.M;
+    mc.order = (int *)malloc(sizeof(int) * mc.M);
+    subset_order_table(mc.M, pp->subset_order, mc.order);
+    mc.views = (int *)malloc(sizeof(int) * (mc.nvm + 1));
+    mc.p = (double *)malloc(sizeof(double) * (size_t)(mc.nvm + 1) * g->nb);
+    mc.zeta = (double *)malloc(sizeof(double) * npix);
+    mc.gr = (double *)malloc(sizeof(double) * npix);
+    mc.dr = (double *)malloc(sizeof(double) * npix);
     for (long long t = t0; t < t0 + nsub; ++t) {
-        double rho = pp->rho_mode == 0 ? or_rho(t, alpha) : pp->rho_fixed;
-        int m = order[t % M];
-        /* s and x-step: x+ = [x - (rho D_L + D_R)^-1 (s + grad R(x))]_+ */
-        or_reg_grad_k(g->nx, g->ny, x, pp->potential, pp->delta, pp->beta, pp->huber, kap, gr, dr);
-        for (size_t j = 0; j < npix; ++j) {
-            double s;
-            if (pp->algorithm == 1) s = rho * (dl[j] * x[j] - h[j]) + (1.0 - rho) * gv[j];
-            else s = rho * h[j] + (1.0 - rho) * gv[j]; /* Algorithm 2: h holds the last zeta */
-            double den = rho * dl[j] + dr[j];
-            double xn = den > 0.0 ? x[j] - (s + gr[j]) / den : x[j];
-            x[j] = xn > 0.0 ? xn : 0.0;
-        }
-        /* zeta = M grad L_m(x+) */
-        int nv = or_subset_views(g->nviews, M, m, views);
-        subset_grad(g, views, nv, y, w, x, (double)M, p, zeta);
-        for (size_t j = 0; j < npix; ++j) {
-            double gold = gv[j];
-            gv[j] = rho / (rho + 1.0) * (alpha * zeta[j] + (1.0 - alpha) * gold) + gold / (rho + 1.0);
-            if (pp->algorithm == 1) h[j] = alpha * (dl[j] * x[j] - zeta[j]) + (1.0 - alpha) * h[j];
-            else h[j] = zeta[j];
-        }
-        if (rmsd_ref_out && trace_every > 0 && ((t + 1) % ((long long)M * trace_every)) == 0) {
-            long long it = (t + 1) / ((long long)M * trace_every) - 1;
+        transition(&mc, t, x, gv, h);
+        if (rmsd_ref_out && trace_every > 0 && ((t + 1) % ((long long)mc.M * trace_every)) == 0) {
+            long long it = (t + 1) / ((long long)mc.M * trace_every) - 1;
             double acc = 0.0; size_t cnt = 0;
             for (size_t j = 0; j < npix; ++j)
                 if (!mask || mask[j]) { double d = x[j] - xref[j]; acc += d * d; ++cnt; }
             rmsd_ref_out[it] = cnt ? 1000.0 / mu_w * sqrt(acc / (double)cnt) : 0.0;
         }
     }
-    free(views); free(p); free(zeta); free(gr); free(dr); free(order);
+    free(mc.views); free(mc.p); free(mc.zeta); free(mc.gr); free(mc.dr); free(mc.order);
 }
 
 /*

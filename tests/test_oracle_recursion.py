@@ -1,0 +1,145 @@
+"""Pins of the oracle's subiteration indexing and of the stability facts the GPU parity cases rely on.
+
+1. A one-pixel image: A is a single column a, so with R = 0 every quantity of the iteration is a scalar
+   and the recursion of eq. relaxed_lal_iter_quad (under eq. ct_substitution, with the subset gradient
+   M grad L_m and rho_t of eq. dec_rho) can be stepped by hand. With one subset, A'WA equals its diagonal
+   majorizer D_L exactly: the setting D_A = L_A I of the supplement's section on continuation with
+   over-relaxation. The hand recursion uses rho_t in the x-step and in g+ of subiteration t and then
+   decreases rho (Algorithm 1), with t the global subiteration count; the oracle must agree to 1e-12 in
+   x, g and h after every subiteration. Using rho_{t+1} in g+, or dropping alpha from g+, fails this.
+2. The 128^2 workload (220 views, 10 subsets, alpha = 1.999): with the subsets in sequential order the
+   relaxed iteration runs away from the phantom within 20 iterations, while the bit-reversed order stays
+   bounded. The GPU parity cases at alpha = 1.999 therefore use the bit-reversed order (or only the first
+   iterations of the sequential one).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1512_04564_amd import synth
+
+
+def one_pixel_geom(M):
+    return synth.ScanGeometry(nx=1, ny=1, dx=2.0, dy=2.0, nb=8, du=1.0, u_offset=0.0, det="flat", nviews=6,
+                              beta0=0.2, span=2 * math.pi, dso=20.0, dsd=40.0, nsubsets=M)
+
+
+def rho_t(t, alpha):
+    # eq. dec_rho, t the number of subiterations done
+    if t == 0:
+        return 1.0
+    c = math.pi / (alpha * (t + 1))
+    return c * math.sqrt(1.0 - (c / 2.0) ** 2)
+
+
+def hand_recursion(a, y, w, M, alpha, x0, nsub):
+    """States (x, g, h) after 0..nsub subiterations of the scalar recursion (sequential subset order)."""
+    nv = a.shape[0]                                   # a, y, w: [views][bins]
+    L = float(np.sum(w * a * a))                      # D_L = A'WA1 (all views); = A'WA exactly here
+    Lm = [float(np.sum((w * a * a)[m::M])) for m in range(M)]   # subset m: views v = m mod M
+    bm = [float(np.sum((w * a * y)[m::M])) for m in range(M)]
+    assert nv % M == 0
+
+    def zeta(x, m):                                   # M grad L_m(x) = M A_m' W_m (A_m x - y_m)
+        return M * (Lm[m] * x - bm[m])
+
+    x = max(x0, 0.0)
+    z = zeta(x, M - 1)                                # initial gradient on the last subset
+    g, h = z, L * x - z
+    states = [(x, g, h)]
+    for t in range(nsub):
+        rho = rho_t(t, alpha)
+        s = rho * (L * x - h) + (1.0 - rho) * g
+        x = max(x - s / (rho * L), 0.0)
+        z = zeta(x, t % M)
+        g = rho / (rho + 1.0) * (alpha * z + (1.0 - alpha) * g) + g / (rho + 1.0)
+        h = alpha * (L * x - z) + (1.0 - alpha) * h
+        states.append((x, g, h))
+    return states
+
+
+@pytest.mark.parametrize("M", [1, 2, 3])
+@pytest.mark.parametrize("alpha", [1.5, 1.999])
+def test_recursion_by_hand_one_pixel(M, alpha):
+    g = one_pixel_geom(M)
+    a = oracle.forward(g, np.ones((1, 1)))            # the one column of A, [views][bins]
+    assert np.all(a.sum(axis=1) > 0)                  # every view sees the pixel
+    rng = np.random.default_rng(7 + M)
+    x_true = 0.8
+    y = a * x_true + rng.normal(0.0, 0.05, a.shape)
+    w = rng.uniform(0.5, 2.0, a.shape)
+    x0, nsub = 0.3, 6 * M
+    ref = hand_recursion(a, y, w, M, alpha, x0, nsub)
+    p = oracle.params(alpha=alpha, niters=1, nsubsets=M, beta=0.0)
+    yy, ww = y, w
+    dl = oracle.dl(g, ww)
+    assert abs(dl[0, 0] - float(np.sum(w * a * a))) <= 1e-12 * dl[0, 0]
+    x, gv, h = oracle.rlalm_init(g, p, yy, ww, dl, np.full((1, 1), x0))
+    moved = 0.0
+    for t in range(nsub + 1):
+        xr, gr, hr = ref[t]
+        scale = max(abs(xr), abs(gr), abs(hr), 1.0)
+        assert abs(x[0, 0] - xr) <= 1e-12 * scale, (t, x[0, 0], xr)
+        assert abs(gv[0, 0] - gr) <= 1e-12 * scale, (t, gv[0, 0], gr)
+        assert abs(h[0, 0] - hr) <= 1e-12 * scale, (t, h[0, 0], hr)
+        if t < nsub:
+            oracle.rlalm_iterate(g, p, yy, ww, dl, x, gv, h, t, 1)
+            moved = max(moved, abs(ref[t + 1][1] - ref[t][1]))
+    # the trajectory is not degenerate: g keeps changing and x stays off the constraint
+    assert moved > 1e-3 and all(s[0] > 0.0 for s in ref[1:])
+
+
+def test_hand_recursion_distinguishes_rho_index():
+    """The pin above has teeth: the same hand recursion with rho_{t+1} in g+ (or without alpha in g+)
+    ends measurably elsewhere."""
+    g = one_pixel_geom(1)
+    a = oracle.forward(g, np.ones((1, 1)))
+    rng = np.random.default_rng(8)
+    y = a * 0.8 + rng.normal(0.0, 0.05, a.shape)
+    w = rng.uniform(0.5, 2.0, a.shape)
+    ref = hand_recursion(a, y, w, 1, 1.999, 0.3, 6)
+    L = float(np.sum(w * a * a))
+    b = float(np.sum(w * a * y))
+    for variant in ("rho_next_in_g", "no_alpha_in_g"):
+        x = 0.3
+        z = L * x - b
+        gg, h = z, L * x - z
+        for t in range(6):
+            rho = rho_t(t, 1.999)
+            s = rho * (L * x - h) + (1.0 - rho) * gg
+            x = max(x - s / (rho * L), 0.0)
+            z = L * x - b
+            rg = rho_t(t + 1, 1.999) if variant == "rho_next_in_g" else rho
+            al = 1.0 if variant == "no_alpha_in_g" else 1.999
+            gg = rg / (rg + 1.0) * (al * z + (1.0 - al) * gg) + gg / (rg + 1.0)
+            h = 1.999 * (L * x - z) + (1.0 - 1.999) * h
+        assert abs(x - ref[-1][0]) > 1e-6 or abs(gg - ref[-1][1]) > 1e-6 * max(1.0, abs(gg))
+
+
+def _cfg1_rmsd_trace(order):
+    g = synth.CFG1
+    s = synth.noisy_scan(g, 0)
+    p = oracle.params(alpha=1.999, niters=20, nsubsets=g.nsubsets, subset_order=order)
+    mask = oracle.fov_mask(g, synth.fov_radius(g))
+    _, _, tr = oracle.rlalm_solve(g, p, s.y.astype(np.float64), s.w.astype(np.float64), np.zeros((g.ny, g.nx)),
+                                  xref=s.truth, mask=mask)
+    return tr
+
+
+def test_sequential_order_diverges_at_128():
+    """alpha = 1.999 with 10 sequential subsets of 22 views: the RMSD to the phantom grows more than
+    tenfold within 20 iterations (the FP64 oracle itself; no GPU involved)."""
+    tr = _cfg1_rmsd_trace("sequential")
+    assert np.all(np.isfinite(tr))
+    assert tr.max() > 10.0 * tr[0], tr
+
+
+def test_bitreversed_order_stays_bounded_at_128():
+    """The same solve with the subsets in bit-reversed order stays within twice its first-iteration
+    RMSD to the phantom over all 20 iterations."""
+    tr = _cfg1_rmsd_trace("bitrev")
+    assert np.all(np.isfinite(tr))
+    assert tr.max() <= 2.0 * tr[0], tr
+    assert tr[-1] <= 100.0, tr
