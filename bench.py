@@ -190,19 +190,64 @@ def unet_flops(ny, nx):
                for i, (ci, co, k) in enumerate(synth.UNET_SHAPES))
 
 
-def oracle_baseline(g, s, iters):
-    """The FP64 CPU oracle as it stands: `iters` outer iterations of Algorithm 1 (after D_L and init)."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_baseline(g, s, iters, iters_single):
+    """The FP64 CPU oracle as it stands: `iters` outer iterations of Algorithm 1 (after D_L and init) on all
+    of the oracle's threads, then `iters_single` on one thread."""
     import oracle
     p = oracle.params(alpha=1.999, niters=1, nsubsets=g.nsubsets, subset_order=ORDER)
     y, w = s.y.astype(np.float64), s.w.astype(np.float64)
     dl = oracle.dl(g, w)
-    x, gv, h = oracle.rlalm_init(g, p, y, w, dl, np.zeros((g.ny, g.nx)))
-    t0 = time.perf_counter()
-    oracle.rlalm_iterate(g, p, y, w, dl, x, gv, h, 0, iters * g.nsubsets)
-    dt = time.perf_counter() - t0
-    return dict(value=iters / dt, unit="iter/s", cores=oracle.num_threads(), kind="oracle",
-                sample=f"{iters} outer iterations ({iters * g.nsubsets} subiterations) of Algorithm 1 on the "
-                       f"same 512^2 scan, FP64, after D_L and initialisation; {dt:.1f} s")
+    x0, g0, h0 = oracle.rlalm_init(g, p, y, w, dl, np.zeros((g.ny, g.nx)))
+
+    def run(n):
+        x, gv, h = x0.copy(), g0.copy(), h0.copy()
+        t0 = time.perf_counter()
+        oracle.rlalm_iterate(g, p, y, w, dl, x, gv, h, 0, n * g.nsubsets)
+        return time.perf_counter() - t0
+
+    cores = oracle.num_threads()
+    dt = run(iters)
+    out = dict(value=iters / dt, unit="iter/s", cores=cores, kind="oracle",
+               sample=f"{iters} outer iterations ({iters * g.nsubsets} subiterations) of Algorithm 1 on the "
+                      f"same 512^2 scan, FP64, after D_L and initialisation, {cores} OpenMP threads; {dt:.1f} s",
+               cpu_model=cpu_model(), host_cpus=os.cpu_count())
+    if iters_single > 0:
+        oracle.set_num_threads(1)
+        try:
+            dt1 = run(iters_single)
+        finally:
+            oracle.set_num_threads(cores)
+        out["single_thread"] = dict(value=iters_single / dt1, unit="iter/s", cores=1,
+                                    sample=f"{iters_single} outer iterations, one thread; {dt1:.1f} s")
+    return out
+
+
+def oracle_class_rmsd(geoms, ys64, ws64, xs_gpu, niters, alpha):
+    """RMSD (HU, field of view and whole image) and max |dx| between each GPU slice image and the oracle's
+    solve of the same inputs (bit-reversed order, zero start)."""
+    import oracle
+    from paper_1512_04564_amd import synth
+    out = []
+    for gc, y64, w64, xg in zip(geoms, ys64, ws64, xs_gpu):
+        p = oracle.params(alpha=alpha, niters=niters, nsubsets=gc.nsubsets, subset_order=ORDER)
+        xo, _, _ = oracle.rlalm_solve(gc, p, y64, w64, np.zeros((gc.ny, gc.nx)))
+        d = xg.astype(np.float64) - xo
+        fov = oracle.fov_mask(gc, synth.fov_radius(gc))
+        out.append({"slice": f"{gc.nx}^2/{gc.nviews} views", "rmsd_hu_fov": round(50000.0 * float(np.sqrt(np.mean(d[fov] ** 2))), 4),
+                    "rmsd_hu_all": round(50000.0 * float(np.sqrt(np.mean(d * d))), 4),
+                    "max_abs_hu": round(50000.0 * float(np.max(np.abs(d))), 3)})
+    return out
 
 
 def main():
@@ -215,6 +260,8 @@ def main():
     ap.add_argument("--no-t1hu", action="store_true", help="skip the time-to-1-HU runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--cpu-iters-single", type=int, default=2, help="iterations of the one-thread oracle leg")
+    ap.add_argument("--no-batch-oracle", action="store_true", help="skip the per-slice oracle comparison of the batch")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven 32-slice batch")
     ap.add_argument("--batch-iters", type=int, default=20)
     ap.add_argument("--pmc-workload", action="store_true", help="run the short counter workload and exit")
@@ -250,10 +297,10 @@ def main():
 
     net = None
 
-    def solve(alpha, niters, xref=None, trace=False, start="zero"):
+    def solve(alpha, niters, xref=None, trace=False, start="zero", wait=True):
         p = api.Params(alpha=alpha, niters=niters, subset_order=ORDER, start=start, fov_radius=synth.fov_radius(g),
                        unet=net if start == "learned" else None)
-        return api.rlalm_solve(G, p, y, w, x, x_ref=xref, trace=trace)
+        return api.rlalm_solve(G, p, y, w, x, x_ref=xref, trace=trace, wait=wait)
 
     def timed(fn, reps):
         torch.cuda.synchronize()
@@ -272,10 +319,11 @@ def main():
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     for _ in range(args.steps):
-        solve(1.999, args.niters)
+        solve(1.999, args.niters, wait=False)   # untraced solves do not wait for the device
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    api.rlalm_status(G)
     ms_per_step = ev0.elapsed_time(ev1) / args.steps
     iters_per_s = args.niters / (ms_per_step / 1e3)
 
@@ -285,9 +333,10 @@ def main():
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(2):
-        solve(1.0, args.niters)
+        solve(1.0, args.niters, wait=False)
     e1.record(stream)
     torch.cuda.synchronize()
+    api.rlalm_status(G)
     iters_per_s_unrelaxed = args.niters / (e0.elapsed_time(e1) / 2 / 1e3)
 
     # per-launch duration of the solve's two kernels: after a solve, its last subiteration's projection and
@@ -364,7 +413,34 @@ def main():
                    "seconds_one_by_one": round(t_seq, 4),
                    "slice_iters_per_s": round(n * args.batch_iters / t_batch, 1),
                    "speedup_vs_one_by_one": round(t_seq / t_batch, 3), "launch_shape": cfg}
-        del Gb, xs_b
+        # bfloat16 storage of the same batch
+        Gb16 = [api.Geometry(gc, "bf16") for gc in geoms]
+        ys16 = [yb.to(torch.bfloat16) for yb in ys_b]
+        ws16 = [wb.to(torch.bfloat16) for wb in ws_b]
+        xs16 = [torch.zeros((gc.ny, gc.nx), device=dev) for gc in geoms]
+        cfg16 = api.rlalm_solve_batched(Gb16, pb, ys16, ws16, xs16, autotune=True)
+        t16 = timed(lambda: api.rlalm_solve_batched(Gb16, pb, ys16, ws16, xs16, autotune=True), 2)
+        batched["bf16"] = {"seconds_batched": round(t16, 4), "slice_iters_per_s": round(n * args.batch_iters / t16, 1),
+                           "launch_shape": cfg16}
+        # error against the FP64 oracle per slice: the slices of a class share their inputs, and a batched
+        # launch gives every slice the same arithmetic wherever it sits in the grid, so each class's slices
+        # must be bitwise equal and one oracle solve per class covers all of them. The comparison runs the
+        # same batch unrelaxed: at 41 subsets the relaxed iteration is chaotic on the 256^2 class (the
+        # oracle's own runs from starts 0.005 HU apart end > 1 HU apart), the unrelaxed one is not.
+        if not args.no_batch_oracle:
+            pc = api.Params(alpha=1.0, niters=args.batch_iters, subset_order=ORDER, start="zero")
+            firsts = [sum(counts[:i]) for i in range(3)]
+            for key, Gk, xs_k, yy, ww in (("f32", Gb, xs_b, ys_b, ws_b), ("bf16", Gb16, xs16, ys16, ws16)):
+                api.rlalm_solve_batched(Gk, pc, yy, ww, xs_k, autotune=True)
+                same = all(torch.equal(xs_k[j], xs_k[firsts[i]]) for i in range(3)
+                           for j in range(firsts[i], firsts[i] + counts[i]))
+                ys64 = [yy[j].to(torch.float64).cpu().numpy() for j in firsts]
+                ws64 = [ww[j].to(torch.float64).cpu().numpy() for j in firsts]
+                per = oracle_class_rmsd([geoms[j] for j in firsts], ys64, ws64,
+                                        [xs_k[j].cpu().numpy() for j in firsts], args.batch_iters, alpha=1.0)
+                batched.setdefault("vs_oracle", {"alpha": 1.0, "iters": args.batch_iters})[key] = {
+                    "slices_of_a_class_bitwise_equal": same, "per_class": per}
+        del Gb, xs_b, Gb16, xs16
 
     # learned warm start: network inference rate (the trained parameters are committed by train_unet.py)
     net = None
@@ -420,8 +496,11 @@ def main():
             key = f"subsets={M_},alpha={alpha},start={start}"
             try:
                 rows = solve_m(M_, alpha, args.t1hu_iters, xref=xstar, trace=True, start=start)
-            except api.CtError as e:   # a diverged solve ends non-finite
-                t1hu[key] = {"error": str(e)[:80]}
+            except api.CtError as e:   # the traced solve stopped: cost growth or non-finite values
+                rows = getattr(e, "rows", [])
+                t1hu[key] = {"iters": None, "diverged": str(e)[:160],
+                             "rmsd_hu_at": {str(r["iter"]): round(r["rmsd_hu"], 2) for r in rows},
+                             "cost_at": {str(r["iter"]): float("%.6e" % r["cost"]) for r in rows}}
                 continue
             hit = [r["iter"] for r in rows if r["rmsd_hu"] <= 1.0]
             best = min(r["rmsd_hu"] for r in rows)
@@ -448,7 +527,9 @@ def main():
                     relax[f"{name},rho={rho_mode}"] = {str(r["iter"]): round(r["rmsd_hu"], 2) for r in rows
                                                        if r["iter"] in (1, 2, 5, 10, 20, 30, 50)}
                 except api.CtError as e:
-                    relax[f"{name},rho={rho_mode}"] = {"error": str(e)[:80]}
+                    rows = getattr(e, "rows", [])
+                    relax[f"{name},rho={rho_mode}"] = {"diverged": str(e)[:160],
+                                                       **{str(r["iter"]): round(r["rmsd_hu"], 2) for r in rows}}
 
     # Ablations of the supplement (Section S-III / S-IV): alpha sweep with the continuation and with
     # fixed rho 0.05 (12 subsets, 50 iterations); 1 vs 12 subsets over 360 subiterations with fixed rho
@@ -463,7 +544,9 @@ def main():
             try:
                 rows = api.rlalm_solve(Gx, p, y, w, x, x_ref=xstar, trace=True)
             except api.CtError as e:
-                return {"error": str(e)[:80]}
+                rows = getattr(e, "rows", [])
+                return {"diverged": str(e)[:160], **{str(r["iter"]): round(r["rmsd_hu"], 2) for r in rows
+                                                     if r["iter"] in marks or r is rows[-1]}}
             return {str(r["iter"]): round(r["rmsd_hu"], 2) for r in rows if r["iter"] in marks}
 
         for a in (1.0, 1.5, 1.999):
@@ -475,10 +558,14 @@ def main():
             ablate[f"M=12,alpha={a},rho={rho:.4f},360 subiterations"] = run(G12, 30, (5, 10, 30), alpha=a,
                                                                              rho_mode="fixed", rho_fixed=rho)
         ablate["M=12,alpha=1.999,D_R=maximum curvature"] = run(G12, 50, (10, 20, 50), alpha=1.999, huber=False)
+        # D_L scaled below the majorizer diag{A'WA1}: the supplement reports that too small a D_L diverges
+        for sc in (0.5, 0.25):
+            ablate[f"M=12,alpha=1.999,D_L scale={sc}"] = run(G12, 50, (10, 20, 50), alpha=1.999, dl_scale=sc)
+            ablate[f"M=12,alpha=1.0,D_L scale={sc}"] = run(G12, 50, (10, 20, 50), alpha=1.0, dl_scale=sc)
 
     cpu = None
     if not args.no_cpu:
-        cpu = oracle_baseline(g, s, args.cpu_iters)
+        cpu = oracle_baseline(g, s, args.cpu_iters, args.cpu_iters_single)
 
     line = {
         "metric": "OS-RLALM iterations/s (and time to 1 HU RMSD), 512^2 fan-beam",

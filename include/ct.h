@@ -142,31 +142,61 @@ typedef struct {
                             all slices of a batched launch; 0: never; 1: always). The same setting gives
                             the same bits in single and batched solves; other values are
                             CT_ERR_INVALID_ARG                                                        */
+    double diverge_factor; /* traced solves: the cost Psi of a traced iteration counts as grown when it
+                            exceeds diverge_factor times the lowest Psi traced so far (> 1)           */
+    int diverge_window;  /* traced solves: CT_ERR_DIVERGED after this many consecutive grown rows
+                            (0: cost growth is never an error; non-finite values still are)          */
 } ct_rlalm_params;
 
 /* Fill p with the defaults: alpha 1.999, 20 iterations, continuation, hyperbola delta 1e-4 beta 1024,
    Huber curvature, Algorithm 1, sequential order, kappa off, start 0, last-subset init, D_L scale 1,
-   no trace reference, mu_water 0.02, whole image, graph on, forward split -1. */
+   no trace reference, mu_water 0.02, whole image, graph on, forward split -1, divergence when the
+   traced cost stays above twice its lowest value for 3 traced iterations in a row. */
 void ct_rlalm_params_default(ct_rlalm_params *p);
 
 typedef struct {
     int iter;            /* outer iteration count after which the row was taken                      */
     double seconds;      /* host wall time since the solve call started (synchronised)               */
-    double rmsd_hu;      /* RMSD to x_ref in HU over the trace region (FP64 reduction on the device) */
+    double rmsd_hu;      /* RMSD to x_ref in HU over the trace region (FP64 reduction on the device;
+                            NaN without x_ref)                                                       */
     double rho;          /* rho of the last subiteration of that iteration                           */
     int finite;          /* 1 when x, g and h were all finite                                        */
+    double rmsd_hu_all;  /* RMSD to x_ref in HU over the whole image (NaN without x_ref)              */
+    double cost;         /* Psi(x) = 1/2 ||y - A x||_W^2 + R(x) of the iterate, as ct_cost computes it */
 } ct_trace_row;
 
 /*
  * Whole solve (Algorithm 1 or 2): D_L = diag{A'WA1} (Section III-A), optional certainty weights,
  * initialisation on the last subset, then niters * M subiterations with rho_k(alpha).
  * y, w: [nviews][nb] in the geometry's storage type. x: float32 [ny][nx]; on entry x0 (start == 0),
- * on exit x^(niters). trace: NULL, or niters rows (the call then synchronises once per iteration).
- * Returns CT_ERR_DIVERGED when a non-finite value appears (checked at the end, and per iteration
- * when tracing); x then holds the last iterate computed.
+ * on exit x^(niters).
+ * trace == NULL: the call is asynchronous (stream-ordered; it does not wait for the device). The
+ *   finiteness of the final x, g and h is reduced on the device; ct_rlalm_status reports it.
+ * trace != NULL: niters rows; after every iteration the call waits for the device and takes the row
+ *   (RMSDs, and the cost Psi by an all-view projection and FP64 reductions). It returns
+ *   CT_ERR_DIVERGED when a row is not finite, or when the cost stays above diverge_factor times its
+ *   lowest traced value for diverge_window consecutive rows; x then holds the last traced iterate that
+ *   was finite, and the rows after the one that stopped the solve have iter == 0.
  */
 ct_status ct_rlalm_solve(ct_geom *g, const ct_rlalm_params *p, const void *y, const void *w, float *x,
                          ct_trace_row *trace, void *stream);
+
+/*
+ * Waits for the last untraced ct_rlalm_solve made on this handle and returns CT_ERR_DIVERGED when its
+ * final x, g or h held a non-finite value, CT_OK otherwise (also when no such solve was made).
+ */
+ct_status ct_rlalm_status(ct_geom *g);
+
+/*
+ * PWLS cost of eq. ct_problem (Section III): out[0] = 1/2 sum w (A x - y)^2 over all views, out[1] = R(x)
+ * of eq. def_reg with p's potential, delta and beta (four directions, beta / ||s|| per direction; when
+ * kappa != NULL each pair term also carries kappa_j kappa_n), out[2] = out[0] + out[1]. A x is the
+ * float32 all-view projection; the sums and the potential are FP64 on the device, in a fixed order
+ * (deterministic). x, kappa: float32 [ny][nx]; y, w: [nviews][nb] in the storage type; out: DEVICE
+ * pointer to 3 doubles. Asynchronous; uses the handle's workspace (do not overlap with a solve on it).
+ */
+ct_status ct_cost(ct_geom *g, const ct_rlalm_params *p, const void *y, const void *w, const float *x,
+                  const float *kappa, double *out, void *stream);
 
 /*
  * Batched solve of n independent slices (2-D scans of possibly different sizes) in lockstep: at every

@@ -98,6 +98,8 @@ def _declare(L):
     L.or_xstar.restype = ctypes.c_int
     L.or_fbp.argtypes = [G, _D, _D]
     L.or_num_threads.restype = ctypes.c_int
+    L.or_set_num_threads.argtypes = [ctypes.c_int]
+    L.or_set_num_threads.restype = None
 
 
 def _geom(g) -> _Geom:
@@ -116,6 +118,11 @@ def _f64(a) -> np.ndarray:
 
 def num_threads() -> int:
     return lib().or_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on (timing legs)."""
+    lib().or_set_num_threads(int(n))
 
 
 def subset_views(nviews: int, M: int, m: int) -> np.ndarray:

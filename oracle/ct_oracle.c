@@ -795,3 +795,14 @@ int or_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the OpenMP regions that follow (timing legs). Results do not depend on it: every parallel loop
+   writes disjoint outputs and none reduces across threads. */
+void or_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -19,8 +19,9 @@ STATUS_NAMES = {0: "CT_OK", 1: "CT_ERR_INVALID_ARG", 2: "CT_ERR_OOM", 3: "CT_ERR
 #: Every entry point declared in include/ct.h.
 EXPORTS = ("ct_geom_create", "ct_geom_destroy", "ct_forward", "ct_back", "ct_fbp", "ct_rlalm_params_default",
            "ct_rlalm_solve", "ct_rlalm_solve_batched", "ct_rlalm_prepare", "ct_rlalm_init", "ct_rlalm_iterate",
-           "ct_rlalm_kernel_times", "ct_last_error", "ct_unet_num_params", "ct_unet_create", "ct_unet_destroy",
-           "ct_unet_set_params", "ct_unet_get_params", "ct_unet_forward", "ct_unet_gradient", "ct_unet_train_step",
+           "ct_rlalm_kernel_times", "ct_rlalm_status", "ct_cost", "ct_last_error", "ct_unet_num_params",
+           "ct_unet_create", "ct_unet_destroy", "ct_unet_set_params", "ct_helix_create", "ct_helix_destroy",
+           "ct_helix_forward", "ct_helix_back", "ct_helix_solve", "ct_unet_get_params", "ct_unet_forward", "ct_unet_gradient", "ct_unet_train_step",
            "ct_unet_input")
 
 
@@ -39,7 +40,17 @@ class RlalmParams(ctypes.Structure):
                 ("subset_order", ctypes.c_int), ("kappa", ctypes.c_int), ("start", ctypes.c_int),
                 ("init_full", ctypes.c_int), ("dl_scale", ctypes.c_double), ("x_ref", ctypes.c_void_p),
                 ("mu_water", ctypes.c_double), ("fov_radius", ctypes.c_double), ("use_graph", ctypes.c_int),
-                ("time_kernels", ctypes.c_int), ("unet", ctypes.c_void_p), ("forward_split", ctypes.c_int)]
+                ("time_kernels", ctypes.c_int), ("unet", ctypes.c_void_p), ("forward_split", ctypes.c_int),
+                ("diverge_factor", ctypes.c_double), ("diverge_window", ctypes.c_int)]
+
+
+class HelixDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("dx", ctypes.c_double),
+                ("dy", ctypes.c_double), ("dz", ctypes.c_double), ("zc", ctypes.c_double), ("nb", ctypes.c_int),
+                ("du", ctypes.c_double), ("u_offset", ctypes.c_double), ("nr", ctypes.c_int), ("dw", ctypes.c_double),
+                ("w_offset", ctypes.c_double), ("nviews", ctypes.c_int), ("views_per_turn", ctypes.c_int),
+                ("beta0", ctypes.c_double), ("z0", ctypes.c_double), ("feed", ctypes.c_double),
+                ("dso", ctypes.c_double), ("dsd", ctypes.c_double), ("nsubsets", ctypes.c_int)]
 
 
 class KernelTimes(ctypes.Structure):
@@ -53,7 +64,8 @@ class BatchConfig(ctypes.Structure):
 
 class TraceRow(ctypes.Structure):
     _fields_ = [("iter", ctypes.c_int), ("seconds", ctypes.c_double), ("rmsd_hu", ctypes.c_double),
-                ("rho", ctypes.c_double), ("finite", ctypes.c_int)]
+                ("rho", ctypes.c_double), ("finite", ctypes.c_int), ("rmsd_hu_all", ctypes.c_double),
+                ("cost", ctypes.c_double)]
 
 
 class CtError(RuntimeError):
@@ -89,7 +101,15 @@ def load() -> ctypes.CDLL:
     L.ct_rlalm_init.argtypes = [vp, ctypes.POINTER(RlalmParams), vp, vp, vp, vp, vp, vp, vp]
     L.ct_rlalm_iterate.argtypes = [vp, ctypes.POINTER(RlalmParams), vp, vp, vp, vp, vp, vp, vp, ll, ll, vp]
     L.ct_rlalm_kernel_times.argtypes = [vp, ctypes.POINTER(KernelTimes)]
+    L.ct_rlalm_status.argtypes = [vp]
+    L.ct_cost.argtypes = [vp, ctypes.POINTER(RlalmParams), vp, vp, vp, vp, vp, vp]
     L.ct_last_error.restype = ctypes.c_char_p
+    L.ct_helix_create.argtypes = [ctypes.POINTER(HelixDesc), ctypes.POINTER(vp)]
+    L.ct_helix_destroy.argtypes = [vp]
+    L.ct_helix_destroy.restype = None
+    L.ct_helix_forward.argtypes = [vp, i, vp, vp, vp]
+    L.ct_helix_back.argtypes = [vp, i, vp, vp, vp]
+    L.ct_helix_solve.argtypes = [vp, ctypes.POINTER(RlalmParams), vp, vp, vp, vp]
     fp, u8p, dp = ctypes.POINTER(ctypes.c_float), vp, ctypes.POINTER(ctypes.c_double)
     L.ct_unet_num_params.argtypes = []
     L.ct_unet_create.argtypes = [vp, i, i, i, ctypes.POINTER(vp)]
@@ -103,7 +123,7 @@ def load() -> ctypes.CDLL:
     L.ct_unet_input.argtypes = [vp, vp, ctypes.c_double, vp, vp]
     for name in EXPORTS:
         if name not in ("ct_geom_destroy", "ct_rlalm_params_default", "ct_last_error", "ct_unet_destroy",
-                        "ct_unet_num_params"):
+                        "ct_unet_num_params", "ct_helix_destroy"):
             getattr(L, name).restype = ctypes.c_int
     L.ct_unet_num_params.restype = ctypes.c_size_t
     _lib = L

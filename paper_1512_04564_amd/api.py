@@ -10,15 +10,15 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
-import math
 
 import torch
 
 from . import _lib
 from ._lib import CtError, GeomDesc, RlalmParams, TraceRow, check
 
-__all__ = ["Geometry", "Params", "forward", "back", "fbp", "rlalm_solve", "rlalm_solve_batched", "rlalm_prepare",
-           "rlalm_init", "rlalm_iterate", "kernel_times", "CtError"]
+__all__ = ["Geometry", "Params", "forward", "back", "fbp", "cost", "rlalm_solve", "rlalm_status",
+           "rlalm_solve_batched", "rlalm_prepare", "rlalm_init", "rlalm_iterate", "kernel_times", "Helix",
+           "helix_forward", "helix_back", "helix_solve", "CtError"]
 
 
 def _stream_handle(stream) -> int:
@@ -104,6 +104,8 @@ class Params:
     time_kernels: bool = False
     unet: object = None              # unet.UNet for start="learned"
     forward_split: int = -1          # -1: when the launch underfills the device, 0: never, 1: always
+    diverge_factor: float = 2.0      # traced solves: cost above this factor times its lowest traced value ...
+    diverge_window: int = 3          # ... for this many rows in a row is CT_ERR_DIVERGED (0: never)
 
     def to_c(self, x_ref: torch.Tensor | None = None) -> RlalmParams:
         p = RlalmParams()
@@ -129,6 +131,8 @@ class Params:
         p.fov_radius = self.fov_radius
         p.use_graph = int(self.use_graph)
         p.time_kernels = int(self.time_kernels)
+        p.diverge_factor = self.diverge_factor
+        p.diverge_window = self.diverge_window
         return p
 
 
@@ -161,9 +165,33 @@ def fbp(g: Geometry, y: torch.Tensor, out: torch.Tensor | None = None, stream=No
     return out
 
 
+def cost(g: Geometry, p: Params, y: torch.Tensor, w: torch.Tensor, x: torch.Tensor,
+         kappa: torch.Tensor | None = None, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """PWLS cost of x (ct_cost): float64 CUDA tensor [Psi, data term, R(x)], computed on the device."""
+    sino = (g.nviews, g.nb)
+    sd = g.sino_dtype
+    if out is None:
+        out = torch.empty(3, dtype=torch.float64, device=x.device)
+    cp = p.to_c()
+    check(g._lib.ct_cost(g.handle, ctypes.byref(cp), _ptr(y, shape=sino, name="y", dtype=sd),
+                         _ptr(w, shape=sino, name="w", dtype=sd), _ptr(x, shape=g.img_shape, name="x"),
+                         _ptr(kappa, shape=g.img_shape, name="kappa") if kappa is not None else None,
+                         _ptr(out, shape=(3,), name="out", dtype=torch.float64), _stream_handle(stream)))
+    return out
+
+
+def _rows(rows, n):
+    return [dict(iter=r.iter, seconds=r.seconds, rmsd_hu=r.rmsd_hu, rmsd_hu_all=r.rmsd_hu_all, cost=r.cost,
+                 rho=r.rho, finite=bool(r.finite)) for r in rows[:n] if r.iter > 0]
+
+
 def rlalm_solve(g: Geometry, p: Params, y: torch.Tensor, w: torch.Tensor, x: torch.Tensor, *,
-                x_ref: torch.Tensor | None = None, trace: bool = False, stream=None):
-    """Run the whole solve in place on ``x``. Returns the trace rows (list of dicts) when ``trace``."""
+                x_ref: torch.Tensor | None = None, trace: bool = False, wait: bool = True, stream=None):
+    """Run the whole solve in place on ``x``. Returns the trace rows (list of dicts) when ``trace``.
+
+    Untraced solves are asynchronous in the library; with ``wait`` (the default) this waits for the solve
+    and raises CtError(CT_ERR_DIVERGED) when it ended non-finite (``rlalm_status``). A traced solve that
+    stops on divergence raises CtError with the rows taken so far in its ``rows`` attribute."""
     sino = (g.nviews, g.nb)
     cp = p.to_c(x_ref)
     if x_ref is not None:
@@ -173,11 +201,22 @@ def rlalm_solve(g: Geometry, p: Params, y: torch.Tensor, w: torch.Tensor, x: tor
     st = g._lib.ct_rlalm_solve(g.handle, ctypes.byref(cp), _ptr(y, shape=sino, name="y", dtype=sd),
                                _ptr(w, shape=sino, name="w", dtype=sd), _ptr(x, shape=g.img_shape, name="x"),
                                rows, _stream_handle(stream))
-    check(st)
     if trace:
-        return [dict(iter=r.iter, seconds=r.seconds, rmsd_hu=r.rmsd_hu, rho=r.rho, finite=bool(r.finite))
-                for r in rows[:p.niters]]
+        try:
+            check(st)
+        except CtError as e:
+            e.rows = _rows(rows, p.niters)
+            raise
+        return _rows(rows, p.niters)
+    check(st)
+    if wait:
+        rlalm_status(g)
     return None
+
+
+def rlalm_status(g: Geometry) -> None:
+    """Wait for the last untraced solve on ``g``; raise CtError(CT_ERR_DIVERGED) if it ended non-finite."""
+    check(g._lib.ct_rlalm_status(g.handle))
 
 
 def rlalm_solve_batched(geoms, p: Params, ys, ws, xs, *, autotune: bool = False, stream=None) -> dict:
@@ -237,15 +276,67 @@ def kernel_times(g: Geometry) -> dict:
     return dict(n_forward=kt.n_forward, n_update=kt.n_update, ms_forward=kt.ms_forward, ms_update=kt.ms_update)
 
 
-def rho_table(p: Params, n: int):
-    """The continuation values the solver uses (FP64 closed form, Section III-B), for reporting."""
-    out = []
-    for k in range(n):
-        if p.rho_mode == "fixed":
-            out.append(p.rho_fixed)
-        elif k == 0:
-            out.append(1.0)
-        else:
-            a = math.pi / (p.alpha * (k + 1))
-            out.append(a * math.sqrt(1.0 - (a / 2.0) ** 2))
+class Helix:
+    """Owning wrapper of a ``ct_helix`` handle: a 3-D helical cone-beam scan (include/ct_helix.h).
+
+    ``geom``: any object with the ``synth.HelicalGeometry`` fields. Volumes are float32 CUDA tensors
+    ``[nz][ny][nx]``, sinograms ``[views][rows][bins]``."""
+
+    def __init__(self, geom):
+        self.desc_py = geom
+        d = _lib.HelixDesc(geom.nx, geom.ny, geom.nz, geom.dx, geom.dy, geom.dz, geom.zc, geom.nb, geom.du,
+                           geom.u_offset, geom.nr, geom.dw, geom.w_offset, geom.nviews, geom.views_per_turn,
+                           geom.beta0, geom.z0, geom.feed, geom.dso, geom.dsd, geom.nsubsets)
+        self._lib = _lib.load()
+        h = ctypes.c_void_p()
+        check(self._lib.ct_helix_create(ctypes.byref(d), ctypes.byref(h)))
+        self.handle = h
+        self.nx, self.ny, self.nz = geom.nx, geom.ny, geom.nz
+        self.nb, self.nr, self.nviews, self.nsubsets = geom.nb, geom.nr, geom.nviews, geom.nsubsets
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            self._lib.ct_helix_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def views_in(self, subset: int) -> int:
+        return self.nviews if subset == -1 else self.nviews // self.nsubsets
+
+    @property
+    def vol_shape(self):
+        return (self.nz, self.ny, self.nx)
+
+
+def helix_forward(h: Helix, x: torch.Tensor, subset: int = -1, out: torch.Tensor | None = None, stream=None):
+    """A_m x (subset m) or A x (subset -1) of a volume: ``[views][rows][bins]`` float32."""
+    shape = (h.views_in(subset), h.nr, h.nb)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=x.device)
+    check(h._lib.ct_helix_forward(h.handle, subset, _ptr(x, shape=h.vol_shape, name="x"),
+                                  _ptr(out, shape=shape, name="out"), _stream_handle(stream)))
     return out
+
+
+def helix_back(h: Helix, r: torch.Tensor, subset: int = -1, out: torch.Tensor | None = None, stream=None):
+    """A_m' r (subset m) or A' r (subset -1): ``[nz][ny][nx]`` float32."""
+    shape = (h.views_in(subset), h.nr, h.nb)
+    if out is None:
+        out = torch.empty(h.vol_shape, dtype=torch.float32, device=r.device)
+    check(h._lib.ct_helix_back(h.handle, subset, _ptr(r, shape=shape, name="r"),
+                               _ptr(out, shape=h.vol_shape, name="out"), _stream_handle(stream)))
+    return out
+
+
+def helix_solve(h: Helix, p: Params, y: torch.Tensor, w: torch.Tensor, x: torch.Tensor, stream=None) -> None:
+    """3-D relaxed OS-LALM solve in place on the volume ``x`` (waits for the device; raises CtError)."""
+    sino = (h.nviews, h.nr, h.nb)
+    cp = p.to_c()
+    check(h._lib.ct_helix_solve(h.handle, ctypes.byref(cp), _ptr(y, shape=sino, name="y"),
+                                _ptr(w, shape=sino, name="w"), _ptr(x, shape=h.vol_shape, name="x"),
+                                _stream_handle(stream)))

@@ -16,7 +16,7 @@ ARCH = os.environ.get("CTRLALM_ARCH", "gfx950")
 
 # (source, extra flags). The projector / update kernels carry no NaN semantics; reductions keep them.
 SOURCES = [("ct_geom.cpp", []), ("ct_kernels.hip", ["-fno-honor-nans"]), ("ct_reduce.hip", []), ("ct_fbp.hip", []),
-           ("ct_unet.hip", []), ("ct_api.hip", [])]
+           ("ct_unet.hip", []), ("ct_api.hip", []), ("ct_helix_tables.cpp", []), ("ct_helix.hip", [])]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -78,6 +78,8 @@ ct_status check_desc(const ct_geom_desc *d)
     return CT_OK;
 }
 
+}  // namespace
+
 ct_status check_params(const ct_rlalm_params *p)
 {
     if (!p) return fail(CT_ERR_INVALID_ARG, "params is NULL");
@@ -94,6 +96,9 @@ ct_status check_params(const ct_rlalm_params *p)
     if (p->start < 0 || p->start > 3) return fail(CT_ERR_INVALID_ARG, "start must be 0, 1, 2 or 3");
     if (p->start == 3 && !p->unet) return fail(CT_ERR_INVALID_ARG, "start == 3 needs a network (unet)");
     if (p->forward_split < -1 || p->forward_split > 1) return fail(CT_ERR_INVALID_ARG, "forward_split must be -1, 0 or 1");
+    if (p->diverge_window < 0) return fail(CT_ERR_INVALID_ARG, "diverge_window must be >= 0");
+    if (p->diverge_window > 0 && !(p->diverge_factor > 1.0))
+        return fail(CT_ERR_INVALID_ARG, "diverge_factor must be > 1 when diverge_window > 0");
     return CT_OK;
 }
 
@@ -105,6 +110,8 @@ double rho_value(long long k, const ct_rlalm_params *p)
     double b = M_PI / (2.0 * p->alpha * (double)(k + 1));
     return a * std::sqrt(1.0 - b * b);
 }
+
+namespace {
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
@@ -126,7 +133,7 @@ ct_status ensure_workspace(ct_geom *g, size_t r_views, size_t rho_len)
     }
     CT_TRY(dev_alloc(&W.tmp, npix));
     CT_TRY(dev_alloc(&W.tbase, 4));
-    CT_TRY(dev_alloc(&W.red, 3 + 3 * 256 + 8));
+    CT_TRY(dev_alloc(&W.red, kRedSize));
     const size_t need_r = r_views * (size_t)d.nb;
     if (need_r > W.r_cap) {
         dev_free(&W.r);
@@ -176,7 +183,7 @@ bool params_equal(const ct_rlalm_params &a, const ct_rlalm_params &b)
     return a.alpha == b.alpha && a.rho_mode == b.rho_mode && a.rho_fixed == b.rho_fixed &&
            a.potential == b.potential && a.delta == b.delta && a.beta == b.beta && a.huber == b.huber &&
            a.algorithm == b.algorithm && a.subset_order == b.subset_order && a.kappa == b.kappa &&
-           a.potential == b.potential;
+           a.forward_split == b.forward_split;
 }
 
 bool key_equal(const GraphKey &a, const GraphKey &b)
@@ -308,20 +315,59 @@ hipError_t launch_subiter(const Ctx &c, long long t_abs, long long tofs, int cur
     return launch_subiter_part(c, t_abs, tofs, cur_is_a, 1, s);
 }
 
+// The rho table of rho_k (k < len) in FP64, stored as float32 on the device. Uploaded from a pinned staging
+// buffer without waiting for the device; skipped when the device already holds this table.
 ct_status upload_rho(ct_geom *g, const ct_rlalm_params *p, long long len, hipStream_t s)
 {
     std::vector<float> tab((size_t)len);
     for (long long k = 0; k < len; ++k) tab[(size_t)k] = (float)rho_value(k, p);
+    const float *old_ptr = g->ws.rho;
     CT_TRY(ensure_workspace(g, g->desc.nviews, (size_t)len));
-    CT_HIP_CHECK(hipMemcpyAsync(g->ws.rho, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice, s));
-    CT_HIP_CHECK(hipStreamSynchronize(s));  // the host table is about to go out of scope
+    if (g->ws.rho != old_ptr) g->rho_on_device.clear();
+    if (g->rho_on_device.size() >= tab.size() && std::equal(tab.begin(), tab.end(), g->rho_on_device.begin()))
+        return CT_OK;
+    if (!g->rho_ev) CT_HIP_CHECK(hipEventCreateWithFlags(&g->rho_ev, hipEventDisableTiming));
+    else CT_HIP_CHECK(hipEventSynchronize(g->rho_ev));   // the staging buffer's last upload has been done
+    if (tab.size() > g->rho_host_cap) {
+        if (g->rho_host) (void)hipHostFree(g->rho_host);
+        g->rho_host = nullptr;
+        g->rho_host_cap = 0;
+        CT_HIP_CHECK(hipHostMalloc((void **)&g->rho_host, tab.size() * sizeof(float), hipHostMallocDefault));
+        g->rho_host_cap = tab.size();
+    }
+    std::copy(tab.begin(), tab.end(), g->rho_host);
+    g->rho_on_device.clear();
+    CT_HIP_CHECK(hipMemcpyAsync(g->ws.rho, g->rho_host, tab.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    CT_HIP_CHECK(hipEventRecord(g->rho_ev, s));
+    g->rho_on_device = std::move(tab);
+    return CT_OK;
+}
+
+// Cost Psi(x) of the float32 image x (eq. ct_problem) into the cost region of the reduction buffer
+// (W.red + kRedCost: kCostOut doubles + scratch): all-view projection into the residual buffer (through the
+// transposed copy in tmp), then the FP64 reductions. The workspace is allocated here first, so callers read
+// the result's address only after this returns.
+ct_status do_cost(ct_geom *g, const ct_rlalm_params *p, const void *y, const void *w, const float *x,
+                  const float *kappa, hipStream_t s)
+{
+    CT_TRY(ensure_workspace(g, g->desc.nviews, 4));
+    Workspace &W = g->ws;
+    if (!W.red || !W.r || !W.tmp) return fail(CT_ERR_HIP, "cost: workspace missing");
+    double *out = W.red + kRedCost;
+    const ct_geom_desc &d = g->desc;
+    CT_HIP_CHECK(launch_transpose(x, W.tmp, d.nx, d.ny, s));
+    CT_HIP_CHECK(launch_forward(fp_launch(g->dev, x, W.tmp, 0, 1, d.nviews, nullptr, nullptr, 1.f, W.r), 0, FP_PLAIN,
+                                CT_F32, s));
+    CT_HIP_CHECK(launch_cost_reduce(W.r, y, w, d.storage, (size_t)d.nviews * d.nb, x, kappa, d.nx, d.ny, p->potential,
+                                    p->delta, p->beta, out, s));
     return CT_OK;
 }
 
 // Advance (x in buffer A on entry) from state t0 by nsub subiterations. On exit the buffer holding
 // x^(t0+nsub) is returned through final_is_a.
 ct_status run_subiters(const Ctx &c, long long t0, long long nsub, int use_graph, hipStream_t s, int *final_is_a,
-                       ct_trace_row *trace, const ct_rlalm_params *p, std::chrono::steady_clock::time_point tstart)
+                       ct_trace_row *trace, const ct_rlalm_params *p, std::chrono::steady_clock::time_point tstart,
+                       float *x_out = nullptr)
 {
     ct_geom *g = c.g;
     Workspace &W = g->ws;
@@ -344,6 +390,8 @@ ct_status run_subiters(const Ctx &c, long long t0, long long nsub, int use_graph
     // graph length: one iteration, doubled when M is odd so that the ping-pong parity is preserved
     const int L = (M % 2 == 0) ? M : 2 * M;
     const bool traced = trace != nullptr;
+    double cost_min = INFINITY;
+    int grown = 0;
     auto trace_point = [&](long long t_done) -> ct_status {
         // called when t_done subiterations are complete and t_done % M == 0
         if (!traced || t_done % M != 0 || t_done == 0) return CT_OK;
@@ -351,17 +399,38 @@ ct_status run_subiters(const Ctx &c, long long t0, long long nsub, int use_graph
         if (it < 1 || it > p->niters) return CT_OK;
         // x^(t_done) is the input of the last projection: the "cur" buffer before the last swap
         const float *xcur = cur_a ? W.xb : W.xa;  // after the swap below, the previous cur is the other one
-        CT_HIP_CHECK(launch_trace_reduce(xcur, p->x_ref, c.gv, c.h, g->desc.nx, g->desc.ny, (float)g->desc.dx,
-                                         (float)g->desc.dy, (float)p->fov_radius, W.red, s));
-        double host[3];
-        CT_HIP_CHECK(hipMemcpyAsync(host, W.red, sizeof(host), hipMemcpyDeviceToHost, s));
+        const ct_geom_desc &d = g->desc;
+        double *tr = W.red + kRedTrace, *co = W.red + kRedCost;
+        CT_HIP_CHECK(launch_trace_reduce(xcur, p->x_ref, c.gv, c.h, d.nx, d.ny, (float)d.dx, (float)d.dy,
+                                         (float)p->fov_radius, tr, s));
+        // the residual block and tmp are free between iterations: the next projection rewrites them
+        CT_TRY(do_cost(g, p, c.y, c.w, xcur, c.kappa, s));
+        double host[kTraceOut + kCostOut];
+        CT_HIP_CHECK(hipMemcpyAsync(host, tr, kTraceOut * sizeof(double), hipMemcpyDeviceToHost, s));
+        CT_HIP_CHECK(hipMemcpyAsync(host + kTraceOut, co, kCostOut * sizeof(double), hipMemcpyDeviceToHost, s));
         CT_HIP_CHECK(hipStreamSynchronize(s));
         ct_trace_row &row = trace[it - 1];
         row.iter = (int)it;
         row.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - tstart).count();
-        row.rmsd_hu = (p->x_ref && host[1] > 0) ? 1000.0 / p->mu_water * std::sqrt(host[0] / host[1]) : NAN;
+        const double hu = 1000.0 / p->mu_water;
+        row.rmsd_hu = (p->x_ref && host[1] > 0) ? hu * std::sqrt(host[0] / host[1]) : NAN;
+        row.rmsd_hu_all = p->x_ref ? hu * std::sqrt(host[3] / (double)W.npix) : NAN;
         row.rho = rho_value(t_done - 1, p);
-        row.finite = host[2] == 0.0;
+        row.finite = host[2] == 0.0 && std::isfinite(host[kTraceOut + 2]);
+        row.cost = host[kTraceOut + 2];
+        if (!row.finite)
+            return fail(CT_ERR_DIVERGED, "non-finite values after iteration " + std::to_string(it) +
+                                             "; x holds the last finite traced iterate");
+        // x holds the latest finite traced iterate
+        CT_HIP_CHECK(hipMemcpyAsync(x_out, xcur, W.npix * sizeof(float), hipMemcpyDeviceToDevice, s));
+        cost_min = std::min(cost_min, row.cost);
+        grown = row.cost > p->diverge_factor * cost_min ? grown + 1 : 0;
+        if (p->diverge_window > 0 && grown >= p->diverge_window) {
+            CT_HIP_CHECK(hipStreamSynchronize(s));
+            return fail(CT_ERR_DIVERGED, "cost grew above " + std::to_string(p->diverge_factor) +
+                                             " times its lowest traced value for " + std::to_string(grown) +
+                                             " iterations in a row (iteration " + std::to_string(it) + ")");
+        }
         return CT_OK;
     };
     auto plain_one = [&]() -> ct_status {
@@ -725,6 +794,8 @@ void ct_rlalm_params_default(ct_rlalm_params *p)
     p->use_graph = 1;
     p->time_kernels = 0;
     p->forward_split = -1;
+    p->diverge_factor = 2.0;
+    p->diverge_window = 3;
 }
 
 ct_status ct_geom_create(const ct_geom_desc *desc, ct_geom **out)
@@ -753,6 +824,10 @@ void ct_geom_destroy(ct_geom *g)
     drop_graph_cache(g);
     free_workspace(g);
     free_geometry(g);
+    if (g->status_host) (void)hipHostFree(g->status_host);
+    if (g->rho_host) (void)hipHostFree(g->rho_host);
+    if (g->status_ev) (void)hipEventDestroy(g->status_ev);
+    if (g->rho_ev) (void)hipEventDestroy(g->rho_ev);
     delete g;
 }
 
@@ -874,18 +949,43 @@ ct_status ct_rlalm_solve(ct_geom *g, const ct_rlalm_params *p, const void *y, co
     }
     Ctx c = make_ctx(g, p, y, w, W.dl, W.kappa, W.gv, W.h);
     CT_TRY(do_init(c, x, p->start == 1, s));
+    if (trace)
+        for (int i = 0; i < p->niters; ++i) trace[i] = ct_trace_row{0, 0.0, NAN, NAN, 0, NAN, NAN};
     int fin = -1;
-    if (nsub > 0) CT_TRY(run_subiters(c, 0, nsub, p->use_graph, s, &fin, trace, p, tstart));
+    if (nsub > 0) CT_TRY(run_subiters(c, 0, nsub, p->use_graph, s, &fin, trace, p, tstart, x));
     const float *xf = fin == 0 ? W.xb : W.xa;
     CT_HIP_CHECK(hipMemcpyAsync(x, xf, W.npix * sizeof(float), hipMemcpyDeviceToDevice, s));
-    // finiteness check of the final state (FP64 reduction, one synchronisation)
+    // finiteness of the final state: an FP64 reduction on the device, read back without waiting
     CT_HIP_CHECK(launch_trace_reduce(x, nullptr, W.gv, W.h, g->desc.nx, g->desc.ny, (float)g->desc.dx,
-                                     (float)g->desc.dy, 0.f, W.red, s));
-    double host[3];
-    CT_HIP_CHECK(hipMemcpyAsync(host, W.red, sizeof(host), hipMemcpyDeviceToHost, s));
-    CT_HIP_CHECK(hipStreamSynchronize(s));
-    if (host[2] != 0.0) return fail(CT_ERR_DIVERGED, "non-finite values in the final state");
+                                     (float)g->desc.dy, 0.f, W.red + kRedTrace, s));
+    if (!g->status_host)
+        CT_HIP_CHECK(hipHostMalloc((void **)&g->status_host, kTraceOut * sizeof(double), hipHostMallocDefault));
+    if (!g->status_ev) CT_HIP_CHECK(hipEventCreateWithFlags(&g->status_ev, hipEventDisableTiming));
+    CT_HIP_CHECK(hipMemcpyAsync(g->status_host, W.red + kRedTrace, kTraceOut * sizeof(double), hipMemcpyDeviceToHost, s));
+    CT_HIP_CHECK(hipEventRecord(g->status_ev, s));
+    g->status_pending = true;
+    if (trace || p->time_kernels) CT_TRY(ct_rlalm_status(g));
     if (p->time_kernels && nsub > 0) CT_TRY(time_last_subiteration(c, nsub - 1, fin == 0 ? 0 : 1, s));
+    return CT_OK;
+}
+
+ct_status ct_rlalm_status(ct_geom *g)
+{
+    if (!g) return fail(CT_ERR_INVALID_ARG, "NULL argument");
+    if (!g->status_pending) return CT_OK;
+    CT_HIP_CHECK(hipEventSynchronize(g->status_ev));
+    if (g->status_host[2] != 0.0) return fail(CT_ERR_DIVERGED, "non-finite values in the final state");
+    return CT_OK;
+}
+
+ct_status ct_cost(ct_geom *g, const ct_rlalm_params *p, const void *y, const void *w, const float *x,
+                  const float *kappa, double *out, void *stream)
+{
+    if (!g || !y || !w || !x || !out) return fail(CT_ERR_INVALID_ARG, "NULL argument");
+    CT_TRY(check_params(p));
+    hipStream_t s = as_stream(stream);
+    CT_TRY(do_cost(g, p, y, w, x, kappa, s));
+    CT_HIP_CHECK(hipMemcpyAsync(out, g->ws.red + kRedCost, kCostOut * sizeof(double), hipMemcpyDeviceToDevice, s));
     return CT_OK;
 }
 

@@ -58,19 +58,24 @@ void det_point64(const ct_geom_desc &d, const View64 &o, double u, double *px, d
 
 }  // namespace
 
-ct_status build_geometry(ct_geom *g)
+ct_status geometry_tables(const ct_geom_desc &d, GeomTables &t)
 {
-    const ct_geom_desc &d = g->desc;
     const int nv = d.nviews, nb = d.nb;
-    std::vector<float2> bnd((size_t)nv * (nb + 1));
-    std::vector<float> scale((size_t)nv * nb);
-    std::vector<float4> inv(nv);
-    std::vector<double2> cs(nv);
-    std::vector<float> sgn(nv);
-    g->rowsweep.assign(nv, 0);
+    std::vector<float2> &bnd = t.bnd;
+    std::vector<float> &scale = t.scale;
+    std::vector<float4> &inv = t.inv;
+    std::vector<double2> &cs = t.cs;
+    std::vector<float> &sgn = t.sgn;
+    bnd.assign((size_t)nv * (nb + 1), float2{});
+    t.bnd64.assign((size_t)nv * (nb + 1), double2{});
+    scale.assign((size_t)nv * nb, 0.f);
+    inv.assign(nv, float4{});
+    cs.assign(nv, double2{});
+    sgn.assign(nv, 0.f);
+    t.rowsweep.assign(nv, 0);
     for (int v = 0; v < nv; ++v) {
         View64 o = view64(d, v);
-        g->rowsweep[v] = o.row ? 1 : 0;
+        t.rowsweep[v] = o.row ? 1 : 0;
         cs[v] = make_double2(o.c, o.s);
         for (int k = 0; k <= nb; ++k) {
             double u = ((double)k - 0.5 * nb + d.u_offset) * d.du;
@@ -87,6 +92,7 @@ ct_status build_geometry(ct_geom *g)
                 B = d.dx * slope / d.dy;
             }
             bnd[(size_t)v * (nb + 1) + k] = make_float2((float)A, (float)B);
+            t.bnd64[(size_t)v * (nb + 1) + k] = make_double2(A, B);
         }
         // boundary order of the view, and every footprint positive in the kernels' FP32 evaluation at the
         // first and last line (U_k is affine in the line coordinate, so the extremes bound the rest)
@@ -120,6 +126,23 @@ ct_status build_geometry(ct_geom *g)
         else        // X = lc dx, Y = e dy
             inv[v] = make_float4((float)(d.dy * ey), (float)(d.dx * ex), (float)(d.dy * o.s), (float)(d.dx * o.c));
     }
+    t.c_kf = (float)(d.dsd / d.du);
+    t.k0 = (float)(0.5 * nb - d.u_offset);
+    return CT_OK;
+}
+
+ct_status build_geometry(ct_geom *g)
+{
+    const ct_geom_desc &d = g->desc;
+    const int nv = d.nviews, nb = d.nb;
+    GeomTables t;
+    CT_TRY(geometry_tables(d, t));
+    const std::vector<float2> &bnd = t.bnd;
+    const std::vector<float> &scale = t.scale;
+    const std::vector<float4> &inv = t.inv;
+    const std::vector<double2> &cs = t.cs;
+    const std::vector<float> &sgn = t.sgn;
+    g->rowsweep = t.rowsweep;
     CT_HIP_CHECK(hipMalloc(&g->bnd, bnd.size() * sizeof(float2)));
     CT_HIP_CHECK(hipMalloc(&g->scale, scale.size() * sizeof(float)));
     CT_HIP_CHECK(hipMalloc(&g->inv, inv.size() * sizeof(float4)));
@@ -139,8 +162,8 @@ ct_status build_geometry(ct_geom *g)
     G.nviews = nv;
     G.arc = d.det == CT_DET_ARC;
     G.dso = (float)d.dso;
-    G.c_kf = (float)(d.dsd / d.du);
-    G.k0 = (float)(0.5 * nb - d.u_offset);
+    G.c_kf = t.c_kf;
+    G.k0 = t.k0;
     G.bnd = g->bnd;
     G.scale = g->scale;
     G.inv = g->inv;

@@ -1,0 +1,287 @@
+// Per-thread bodies of the 3-D helical projector pair and update (host + device).
+//
+// The kernels in ct_helix.hip wrap these functions; the same functions compiled for the host let a CPU
+// emulation run every index computation of the kernels under bounds checks (Ro below checks its index on
+// the host and compiles to a plain load on the device).
+//
+// Geometry (separable distance-driven helical cone-beam projector): view v sweeps voxel planes ("lines")
+// y = y_i (row sweep) or x = x_j, as the fan-beam projector does. Within a plane, voxel column q and bin k
+// overlap by f_t = |[q, q+1] cap [U_k, U_k+1]| / |U_k+1 - U_k| (voxel units along the line, U_k from the
+// fan-beam boundary table: U_k = fmaf(lc, B_k, A_k) + NQ / 2, lc the centred line index). Row r of the
+// detector meets voxel kz of that column by f_a = |[kz, kz+1] cap [z_r, z_r+1]| / |z_r+1 - z_r| with
+// z_r = za_v + ell * wr_r (voxel units), ell = x_c cos b + y_c sin b + dso the depth of the column centre
+// along the central ray and wr_r = w_r / (dsd dz). The weight is scale_k * secphi_rk * f_t * f_a.
+// Precision: overlaps are taken where FP32 rounding stays relative to a voxel, not to the volume. Along the
+// line the boundary crossings U_k reach hundreds of voxels, where FP32 would round them by 1e-5 voxel or
+// more; they are evaluated in FP64 from an FP64 table (the MI355X vector unit issues FP64 FMAs at the FP32
+// rate) and each overlap is formed in FP64 before it is rounded to FP32. Along z the view's source height is
+// split into an integer voxel index zai and a fraction zaf: voxel kz spans [kz - zai, kz - zai + 1] exactly,
+// and the row boundaries zaf + ell wr_r stay within a few tens of voxels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <cstddef>
+
+namespace ct {
+
+#if defined(__HIP_DEVICE_COMPILE__)
+#define HX_CHECK(cond, idx) ((void)0)
+#else
+// Host emulation: out-of-range reads are counted and the first offending index kept; the read itself then
+// returns element 0 instead.
+inline long long &hx_oob_index()
+{
+    static long long v = -1;
+    return v;
+}
+inline int &hx_oob_count()
+{
+    static int n = 0;
+    return n;
+}
+#define HX_CHECK(cond, idx)                                  \
+    do {                                                     \
+        if (!(cond)) {                                       \
+            if (::ct::hx_oob_count()++ == 0) ::ct::hx_oob_index() = (long long)(idx); \
+        }                                                    \
+    } while (0)
+#endif
+
+template <typename T>
+struct Ro {
+    const T *p;
+    size_t n;
+    __host__ __device__ T operator[](size_t i) const
+    {
+#if defined(__HIP_DEVICE_COMPILE__)
+        return p[i];
+#else
+        HX_CHECK(i < n, i);
+        return i < n ? p[i] : p[0];
+#endif
+    }
+};
+
+// Device view of a helical scan's tables.
+struct HelixDev {
+    int nx, ny, nz, nb, nr, nviews;
+    float dx, dy;          // voxel size (mm): column centres
+    float dso;             // source to isocentre (mm)
+    float c_kf, k0;        // inverse map of the fan-beam tables: bin kf = c_kf * ratio + k0
+    float dwn;             // wr_(r+1) - wr_r = dw / (dsd dz)
+    Ro<double2> bnd;       // [nviews][nb + 1] (A, B) in FP64: U_k = A + lc B
+    Ro<float> scale;       // [nviews][nb] plane spacing / |cos theta|
+    Ro<float4> inv;        // [nviews] inverse map (na, nl, da, dl)
+    Ro<int> rowsweep;      // [nviews]
+    Ro<float2> cs;         // [nviews] (cos b, sin b)
+    Ro<float> zai, zaf;    // [nviews] (S_z - z_lo) / dz split into its integer part and the fraction [0, 1)
+    Ro<float> wr;          // [nr + 1] w_r / (dsd dz)
+    Ro<float> secphi;      // [nr][nb]
+};
+
+__host__ __device__ inline int hx_min(int a, int b) { return a < b ? a : b; }
+
+// Rows per forward-projection workgroup and waves per forward workgroup; voxels per back-projection thread.
+constexpr int HX_RB = 8;
+constexpr int HX_FW = 4;
+constexpr int HX_ZG = 4;
+constexpr int HX_KC = 8;   // candidate bins per view kept in registers by the back-projector
+
+// Centre of voxel column q on line lc (world mm) and its depth ell along the view's central ray.
+__host__ __device__ inline float column_depth(const HelixDev &G, bool row, float lc, int q, float2 cs)
+{
+    const float xc = row ? ((float)q - 0.5f * (float)(G.nx - 1)) * G.dx : lc * G.dx;
+    const float yc = row ? lc * G.dy : ((float)q - 0.5f * (float)(G.ny - 1)) * G.dy;
+    return fmaf(xc, cs.x, fmaf(yc, cs.y, G.dso));
+}
+
+// Forward projection, one lane: bin k of view v, rows r0 .. r0 + HX_RB - 1 (rows >= nr are skipped),
+// lines l0, l0 + lstep, ... < NL. acc[rr] += f_t * sum_kz f_a * X(kz, line, q) over the lane's lines; the
+// caller multiplies by scale_k * secphi. X: the volume in the view's sweep layout [nz][NL][NQ] (x for row
+// sweep views, its per-slice transpose for the others); ones: every voxel is 1 (X is not read).
+__host__ __device__ inline void hfp_lane(const HelixDev &G, const Ro<float> &X, bool ones, int v, int k, int r0,
+                                         int l0, int lstep, float (&acc)[HX_RB])
+{
+    const bool row = G.rowsweep[v] != 0;
+    const int NL = row ? G.ny : G.nx, NQ = row ? G.nx : G.ny;
+    const size_t bb = (size_t)v * (G.nb + 1) + k;
+    const double2 b0 = G.bnd[bb], b1 = G.bnd[bb + 1];
+    const float2 cs = G.cs[v];
+    const float zai = G.zai[v], zaf = G.zaf[v];
+    // the volume's voxels in the view's z coordinates: kz spans [kz - zai, kz - zai + 1]
+    const float zlo = -zai, zhi = (float)G.nz - zai;
+    float wr[HX_RB + 1];
+#pragma unroll
+    for (int rr = 0; rr <= HX_RB; ++rr) wr[rr] = G.wr[(size_t)hx_min(r0 + rr, G.nr)];
+    const double halfq = 0.5 * (double)NQ, cl = 0.5 * (double)(NL - 1);
+    const size_t plane = (size_t)NL * NQ;
+    for (int l = l0; l < NL; l += lstep) {
+        const double lcd = (double)l - cl;
+        const float lc = (float)lcd;
+        const double ua = fma(lcd, b0.y, b0.x), ub = fma(lcd, b1.y, b1.x);
+        const double lo = fmin(ua, ub), hi = fmax(ua, ub);
+        if (!(hi > lo)) continue;
+        const float invt = 1.f / (float)(hi - lo);
+        const int qa = (int)floor(fmax(lo + halfq, 0.0));
+        const int qb = (int)ceil(fmin(hi + halfq, (double)NQ)) - 1;
+        for (int q = qa; q <= qb; ++q) {
+            const double e0 = (double)q - halfq;   // the column spans [e0, e0 + 1] (exact)
+            const float ft = (float)(fmin(hi, e0 + 1.0) - fmax(lo, e0)) * invt;
+            if (!(ft > 0.f)) continue;
+            const float ell = column_depth(G, row, lc, q, cs);
+            const float inva = 1.f / (ell * G.dwn);
+            const size_t col = (size_t)l * NQ + q;
+            float zp = fmaf(ell, wr[0], zaf);
+#pragma unroll
+            for (int rr = 0; rr < HX_RB; ++rr) {
+                const float zn = fmaf(ell, wr[rr + 1], zaf);
+                if (r0 + rr < G.nr) {
+                    const int ka = (int)floorf(fmaxf(zp, zlo) + zai);
+                    const int kb = (int)ceilf(fminf(zn, zhi) + zai) - 1;
+                    float s = 0.f;
+                    for (int kz = ka; kz <= kb; ++kz) {
+                        const float z0 = (float)kz - zai;
+                        const float fa = fminf(zn, z0 + 1.f) - fmaxf(zp, z0);
+                        if (fa > 0.f) s = fmaf(fa, ones ? 1.f : X[(size_t)kz * plane + col], s);
+                    }
+                    acc[rr] = fmaf(ft * inva, s, acc[rr]);
+                }
+                zp = zn;
+            }
+        }
+    }
+}
+
+// Back-projection, one thread: voxels kz0 .. kz0 + HX_ZG - 1 of column (i, j) (voxels >= nz get nothing),
+// views vstart + vi * vstride, vi < nv, reading the residual block R [nv][nr][nb]. acc[jz] += sum over
+// the views' cells of the weight times R. Candidate bins come from the inverse map at the column's two
+// edges (widened by 0.05 bin); up to HX_KC of them are kept in registers, more are re-evaluated per row.
+__host__ __device__ inline void hbp_group(const HelixDev &G, const Ro<float> &R, int vstart, int vstride, int nv, int i,
+                                          int j, int kz0, float (&acc)[HX_ZG])
+{
+    for (int vi = 0; vi < nv; ++vi) {
+        const int v = vstart + vi * vstride;
+        const bool row = G.rowsweep[v] != 0;
+        const int NL = row ? G.ny : G.nx, NQ = row ? G.nx : G.ny;
+        const int line = row ? i : j, q = row ? j : i;
+        const double lcd = (double)line - 0.5 * (double)(NL - 1);
+        const float lc = (float)lcd;
+        const float2 cs = G.cs[v];
+        const float ell = column_depth(G, row, lc, q, cs);
+        const float zai = G.zai[v], zaf = G.zaf[v];
+        const float zg0 = (float)kz0 - zai;   // the thread's voxels span [zg0, zg0 + HX_ZG] in the view's z
+        // rows that can meet them: z_r = zaf + ell wr_r increases with r
+        const float rz0 = (zg0 - zaf) / (ell * G.dwn) - G.wr[0] / G.dwn;
+        const float rz1 = (zg0 + (float)HX_ZG - zaf) / (ell * G.dwn) - G.wr[0] / G.dwn;
+        const int ra = (int)floorf(fmaxf(rz0 - 1.f, 0.f));
+        const int rb = (int)floorf(fminf(rz1 + 1.f, (float)(G.nr - 1)));
+        if (ra > rb) continue;
+        // candidate bins of the voxel column in this view
+        const float4 im = G.inv[v];
+        const double e0d = (double)q - 0.5 * (double)NQ;   // the column spans [e0, e0 + 1] (exact)
+        const float e0 = (float)e0d;
+        const float nlc = lc * im.y, dlc = fmaf(lc, im.w, G.dso);
+        const float t0 = fmaf(e0, im.x, nlc) / fmaf(e0, im.z, dlc);
+        const float t1 = fmaf(e0 + 1.f, im.x, nlc) / fmaf(e0 + 1.f, im.z, dlc);
+        const float kf0 = fmaf(G.c_kf, t0, G.k0), kf1 = fmaf(G.c_kf, t1, G.k0);
+        const int ka = (int)floorf(fmaxf(fminf(kf0, kf1) - 0.05f, 0.f));
+        const int kb = (int)floorf(fminf(fmaxf(kf0, kf1) + 0.05f, (float)(G.nb - 1)));
+        if (ka > kb) continue;
+        const size_t vb = (size_t)v * (G.nb + 1);
+        float fk[HX_KC];
+#pragma unroll
+        for (int c = 0; c < HX_KC; ++c) {
+            const int k = hx_min(ka + c, kb);
+            const double2 b0 = G.bnd[vb + k], b1 = G.bnd[vb + k + 1];
+            const double ua = fma(lcd, b0.y, b0.x), ub = fma(lcd, b1.y, b1.x);
+            const double lo = fmin(ua, ub), hi = fmax(ua, ub);
+            const float ov = (float)(fmin(hi, e0d + 1.0) - fmax(lo, e0d));
+            fk[c] = (ka + c <= kb && ov > 0.f && hi > lo) ? ov / (float)(hi - lo) * G.scale[(size_t)v * G.nb + k] : 0.f;
+        }
+        const float inva = 1.f / (ell * G.dwn);
+        const size_t rv = (size_t)vi * G.nr * G.nb;
+        for (int r = ra; r <= rb; ++r) {
+            const float zl = fmaf(ell, G.wr[(size_t)r], zaf), zh = fmaf(ell, G.wr[(size_t)r + 1], zaf);
+            const size_t rr = rv + (size_t)r * G.nb;
+            float t = 0.f;
+#pragma unroll
+            for (int c = 0; c < HX_KC; ++c) {
+                const int k = hx_min(ka + c, kb);
+                t = fmaf(fk[c] * G.secphi[(size_t)r * G.nb + k], R[rr + k], t);
+            }
+            for (int k = ka + HX_KC; k <= kb; ++k) {   // columns that meet more than HX_KC bins
+                const double2 b0 = G.bnd[vb + k], b1 = G.bnd[vb + k + 1];
+                const double ua = fma(lcd, b0.y, b0.x), ub = fma(lcd, b1.y, b1.x);
+                const double lo = fmin(ua, ub), hi = fmax(ua, ub);
+                const float ov = (float)(fmin(hi, e0d + 1.0) - fmax(lo, e0d));
+                if (ov > 0.f && hi > lo)
+                    t = fmaf(ov / (float)(hi - lo) * G.scale[(size_t)v * G.nb + k] * G.secphi[(size_t)r * G.nb + k],
+                             R[rr + k], t);
+            }
+            t *= inva;
+#pragma unroll
+            for (int jz = 0; jz < HX_ZG; ++jz) {
+                const float z0 = zg0 + (float)jz;
+                const float fa = fminf(zh, z0 + 1.f) - fmaxf(zl, z0);
+                if (fa > 0.f) acc[jz] = fmaf(fa, t, acc[jz]);
+            }
+        }
+    }
+}
+
+// Scalars of the 3-D update.
+struct HelixUpdate {
+    int nx, ny, nz;
+    float alpha;
+    int potential, huber;
+    float delta, beta;
+};
+
+// The 26-neighbour regularizer at voxel (kz, i, j) of X (canonical [nz][ny][nx]): gradient and Huber
+// curvature diagonal (omega = 1 when huber == 0). Offsets of length 1, sqrt 2 and sqrt 3 (voxel units)
+// carry beta, beta / sqrt 2 and beta / sqrt 3; a pair exists only when both voxels lie in the volume.
+__host__ __device__ inline void reg26(const HelixUpdate &U, const Ro<float> &X, int kz, int i, int j, float xc,
+                                      float &gr, float &dr)
+{
+    gr = 0.f;
+    dr = 0.f;
+    const float bnd[4] = {0.f, U.beta, U.beta * 0.70710678118654752f, U.beta * 0.57735026918962576f};
+    for (int dz = -1; dz <= 1; ++dz) {
+        const int k2 = kz + dz;
+        if (k2 < 0 || k2 >= U.nz) continue;
+        for (int di = -1; di <= 1; ++di) {
+            const int i2 = i + di;
+            if (i2 < 0 || i2 >= U.ny) continue;
+            for (int dj = -1; dj <= 1; ++dj) {
+                const int j2 = j + dj;
+                if (j2 < 0 || j2 >= U.nx) continue;
+                const int n = dz * dz + di * di + dj * dj;
+                if (n == 0) continue;
+                const float t = xc - X[((size_t)k2 * U.ny + i2) * U.nx + j2];
+                const float z = t / U.delta;
+                float om;
+                if (U.potential == 0) om = 1.f / sqrtf(fmaf(z, z, 1.f));
+                else if (U.potential == 1) om = 1.f / (1.f + fabsf(z));
+                else {
+                    const float s = powf(fabsf(z), 0.8f);
+                    om = fmaf(1.2f, s, 2.f) / (2.f * (1.f + s) * (1.f + s));
+                }
+                gr = fmaf(bnd[n] * om, t, gr);
+                dr = fmaf(bnd[n], 2.f * (U.huber ? om : 1.f), dr);
+            }
+        }
+    }
+}
+
+// Clipped x-step at one voxel: x+ = max(0, (gamma + D_R x - grad R) / (rho D_L + D_R)), gamma = (rho - 1) g + rho h.
+__host__ __device__ inline float xstep(float rho, float x, float gv, float h, float dl, float gr, float dr)
+{
+    const float gamma = fmaf(rho - 1.f, gv, rho * h);
+    const float curv = fmaf(rho, dl, dr);
+    const float xn = curv > 0.f ? (gamma + fmaf(dr, x, -gr)) / curv : x;
+    return fmaxf(xn, 0.f);
+}
+
+}  // namespace ct

@@ -105,10 +105,37 @@ struct ct_geom {
     ct::GraphCache graphs;
     ct_kernel_times ktimes{};
     bool ktimes_valid = false;
+    // Untraced solves end without waiting for the device: the final finiteness reduction is copied to
+    // pinned host memory and an event recorded after the copy (ct_rlalm_status waits for it).
+    double *status_host = nullptr;
+    hipEvent_t status_ev = nullptr;
+    bool status_pending = false;   // an untraced solve has recorded status_ev
+    // rho table staging: pinned host buffer, the event after its last upload, and the table the device
+    // holds (empty: unknown), so that an unchanged table is not uploaded again.
+    float *rho_host = nullptr;
+    size_t rho_host_cap = 0;
+    hipEvent_t rho_ev = nullptr;
+    std::vector<float> rho_on_device;
 };
 
 namespace ct {
 
+// Host tables of the fan-beam projector (FP64 geometry, stored FP32; cs in FP64): the device tables of
+// GeomDev before upload.
+struct GeomTables {
+    std::vector<float2> bnd;
+    std::vector<double2> bnd64;   // the same boundary coefficients in FP64 (the helical projector's table)
+    std::vector<float> scale;
+    std::vector<float4> inv;
+    std::vector<double2> cs;
+    std::vector<float> sgn;
+    std::vector<int> rowsweep;
+    float c_kf = 0.f, k0 = 0.f;
+};
+ct_status geometry_tables(const ct_geom_desc &d, GeomTables &t);
+// Argument check of solver parameters; rho_k of eq. dec_rho (FP64; rho_fixed in fixed mode).
+ct_status check_params(const ct_rlalm_params *p);
+double rho_value(long long k, const ct_rlalm_params *p);
 ct_status build_geometry(ct_geom *g);
 void free_geometry(ct_geom *g);
 ct_status ensure_workspace(ct_geom *g, size_t r_views, size_t rho_len);
@@ -235,8 +262,20 @@ hipError_t launch_set_counter(int *c, int value, hipStream_t s);
 ct_status unet_input(ct_geom *g, const void *y, double factor, float *x_in, hipStream_t s);
 ct_status learned_start(ct_geom *g, const ct_unet *u, const void *y, double mu_water, float *x, float *a, float *b,
                         hipStream_t s);
-// FP64 reduction: out[0] += sum over masked pixels of (x - ref)^2, out[1] += count, out[2] += nonfinite count
+// FP64 reductions (ct_reduce.hip) into the handle's reduction buffer Workspace::red: the trace region at
+// kRedTrace, the cost region at kRedCost, kRedSize doubles in all.
+constexpr int kTraceOut = 4;
+constexpr int kCostOut = 3;
+constexpr size_t kRedTrace = 0, kRedCost = 1152, kRedSize = 2048;
+// out[0] = sum over the pixels within radius (all when radius <= 0) of (x - ref)^2, out[1] = their count,
+// out[2] = number of pixels where x, g or h is not finite, out[3] = sum over all pixels of (x - ref)^2 (ref may be
+// NULL: then only out[2] is meaningful). out is followed by 4 * 256 doubles of scratch.
 hipError_t launch_trace_reduce(const float *x, const float *ref, const float *gv, const float *h, int nx, int ny,
                                float dx, float dy, float radius, double *out, hipStream_t s);
+// out[0] = 1/2 sum w (p - y)^2 over nsino samples (p float32, y and w in dtype), out[1] = R(x) (four directions,
+// kappa_j kappa_n per pair when kappa != NULL), out[2] = out[0] + out[1]; followed by 2 * 256 doubles of scratch.
+hipError_t launch_cost_reduce(const float *p, const void *y, const void *w, int dtype, size_t nsino, const float *x,
+                              const float *kappa, int nx, int ny, int kind, double delta, double beta, double *out,
+                              hipStream_t s);
 
 }  // namespace ct

@@ -1,0 +1,170 @@
+// Host emulation of the 3-D helical kernels (test infrastructure): runs the per-thread bodies of
+// ct_helix_body.hpp over the same grids as the kernels in ct_helix.hip, with every table and volume read
+// bounds-checked, so that index arithmetic and results can be checked on a CPU against the FP64 oracle.
+// Built by tests/test_helix_emulation.py with g++; no GPU is touched.
+#include <string>
+#include <vector>
+
+#include "../../paper_1512_04564_amd/csrc/ct_helix_internal.hpp"
+
+namespace ct {
+static std::string g_err;
+void set_error(const std::string &m) { g_err = m; }
+ct_status fail(ct_status st, const std::string &m)
+{
+    g_err = m;
+    return st;
+}
+}  // namespace ct
+
+using namespace ct;
+
+namespace {
+
+struct Emu {
+    HelixTables t;
+    HelixDev G{};
+};
+
+int setup(const ct_helix_desc *d, Emu &e)
+{
+    if (helix_tables(*d, e.t) != CT_OK) return 1;
+    HelixDev &G = e.G;
+    G.nx = d->nx;
+    G.ny = d->ny;
+    G.nz = d->nz;
+    G.nb = d->nb;
+    G.nr = d->nr;
+    G.nviews = d->nviews;
+    G.dx = (float)d->dx;
+    G.dy = (float)d->dy;
+    G.dso = (float)d->dso;
+    G.c_kf = e.t.fan.c_kf;
+    G.k0 = e.t.fan.k0;
+    G.dwn = e.t.dwn;
+    G.bnd = {e.t.fan.bnd64.data(), e.t.fan.bnd64.size()};
+    G.scale = {e.t.fan.scale.data(), e.t.fan.scale.size()};
+    G.inv = {e.t.fan.inv.data(), e.t.fan.inv.size()};
+    G.rowsweep = {e.t.fan.rowsweep.data(), e.t.fan.rowsweep.size()};
+    G.cs = {e.t.cs.data(), e.t.cs.size()};
+    G.zai = {e.t.zai.data(), e.t.zai.size()};
+    G.zaf = {e.t.zaf.data(), e.t.zaf.size()};
+    G.wr = {e.t.wr.data(), e.t.wr.size()};
+    G.secphi = {e.t.secphi.data(), e.t.secphi.size()};
+    return 0;
+}
+
+void reset_oob()
+{
+    hx_oob_count() = 0;
+    hx_oob_index() = -1;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hemu_error(void) { return g_err.c_str(); }
+
+// p[vi][r][k] = A x over views vs + vi * vst (the k_hfp grid, plain epilogue). Returns the number of
+// out-of-range reads (-1 for a rejected descriptor); *first receives the first offending index.
+int hemu_forward(const ct_helix_desc *d, int vs, int vst, int nv, const float *x, float *p, long long *first)
+{
+    Emu e;
+    if (setup(d, e)) return -1;
+    const HelixDev &G = e.G;
+    const size_t nvox = (size_t)d->nx * d->ny * d->nz;
+    std::vector<float> xT(nvox);
+    for (int kz = 0; kz < d->nz; ++kz)
+        for (int i = 0; i < d->ny; ++i)
+            for (int j = 0; j < d->nx; ++j)
+                xT[((size_t)kz * d->nx + j) * d->ny + i] = x[((size_t)kz * d->ny + i) * d->nx + j];
+    reset_oob();
+    for (int vi = 0; vi < nv; ++vi) {
+        const int v = vs + vi * vst;
+        for (int bx = 0; bx < (d->nb + 63) / 64; ++bx)
+            for (int by = 0; by < (d->nr + HX_RB - 1) / HX_RB; ++by) {
+                static float part[HX_FW][HX_RB][64];
+                const int r0 = by * HX_RB;
+                const bool row = G.rowsweep[v] != 0;
+                const Ro<float> X{row ? x : xT.data(), nvox};
+                for (int wave = 0; wave < HX_FW; ++wave)
+                    for (int lane = 0; lane < 64; ++lane) {
+                        const int k = bx * 64 + lane;
+                        float acc[HX_RB];
+                        for (int rr = 0; rr < HX_RB; ++rr) acc[rr] = 0.f;
+                        if (k < G.nb) hfp_lane(G, X, false, v, k, r0, wave, HX_FW, acc);
+                        for (int rr = 0; rr < HX_RB; ++rr) part[wave][rr][lane] = acc[rr];
+                    }
+                for (int idx = 0; idx < HX_RB * 64; ++idx) {
+                    const int rr = idx >> 6, ln = idx & 63;
+                    const int kk = bx * 64 + ln, r = r0 + rr;
+                    if (kk >= G.nb || r >= G.nr) continue;
+                    float s = part[0][rr][ln];
+                    for (int wv = 1; wv < HX_FW; ++wv) s += part[wv][rr][ln];
+                    p[((size_t)vi * G.nr + r) * G.nb + kk] =
+                        s * G.scale[(size_t)v * G.nb + kk] * G.secphi[(size_t)r * G.nb + kk];
+                }
+            }
+    }
+    *first = hx_oob_index();
+    return hx_oob_count();
+}
+
+// x = A' r over views vs + vi * vst (the k_hbp grid), r [nv][nr][nb].
+int hemu_back(const ct_helix_desc *d, int vs, int vst, int nv, const float *r, float *x, long long *first)
+{
+    Emu e;
+    if (setup(d, e)) return -1;
+    const HelixDev &G = e.G;
+    const Ro<float> R{r, (size_t)nv * d->nr * d->nb};
+    reset_oob();
+    const int tiles_x = (G.nx + 3) >> 2, tiles = tiles_x * ((G.ny + 3) >> 2);
+    const int zblocks = (G.nz + 16 * HX_ZG - 1) / (16 * HX_ZG);
+    for (int bx = 0; bx < tiles; ++bx)
+        for (int by = 0; by < zblocks; ++by)
+            for (int tid = 0; tid < 256; ++tid) {
+                const int zg = tid & 15, c = tid >> 4;
+                const int tx = bx % tiles_x, ty = bx / tiles_x;
+                const int j = tx * 4 + (c & 3), i = ty * 4 + (c >> 2);
+                const int kz0 = (by * 16 + zg) * HX_ZG;
+                if (i >= G.ny || j >= G.nx || kz0 >= G.nz) continue;
+                float acc[HX_ZG];
+                for (int jz = 0; jz < HX_ZG; ++jz) acc[jz] = 0.f;
+                hbp_group(G, R, vs, vst, nv, i, j, kz0, acc);
+                for (int jz = 0; jz < HX_ZG; ++jz) {
+                    const int kz = kz0 + jz;
+                    if (kz >= G.nz) break;
+                    x[((size_t)kz * G.ny + i) * G.nx + j] = acc[jz];
+                }
+            }
+    *first = hx_oob_index();
+    return hx_oob_count();
+}
+
+// Regularizer gradient and curvature at every voxel (the k_hupd stencil).
+int hemu_reg(int nx, int ny, int nz, const float *x, int potential, double delta, double beta, int huber, float *gr,
+             float *dr, long long *first)
+{
+    HelixUpdate U;
+    U.nx = nx;
+    U.ny = ny;
+    U.nz = nz;
+    U.alpha = 1.f;
+    U.potential = potential;
+    U.huber = huber;
+    U.delta = (float)delta;
+    U.beta = (float)beta;
+    const size_t nvox = (size_t)nx * ny * nz;
+    reset_oob();
+    for (int kz = 0; kz < nz; ++kz)
+        for (int i = 0; i < ny; ++i)
+            for (int j = 0; j < nx; ++j) {
+                const size_t idx = ((size_t)kz * ny + i) * nx + j;
+                reg26(U, Ro<float>{x, nvox}, kz, i, j, x[idx], gr[idx], dr[idx]);
+            }
+    *first = hx_oob_index();
+    return hx_oob_count();
+}
+
+}  // extern "C"

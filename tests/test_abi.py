@@ -47,6 +47,7 @@ def test_params_default_and_struct_layout():
     assert p.delta == pytest.approx(1e-4) and p.beta == pytest.approx(1024.0)
     assert p.mu_water == pytest.approx(0.02)
     assert p.forward_split == -1
+    assert p.diverge_factor == pytest.approx(2.0) and p.diverge_window == 3
 
 
 def test_invalid_descriptor_is_rejected_without_touching_the_gpu():

@@ -6,7 +6,16 @@ one graph replay per iteration).
   2M subiterations and a plain tail both run).
 * The three full-size slice classes (256^2 / 492 views, 384^2 / 738, 512^2 / 984; constant 500 mm field,
   M = 41, bit-reversed order) against the oracle per slice, autotuned, in float32 (0.5 HU bar) and
-  bfloat16 storage (3.6 HU, the rounding-derived bar of the precision tests).
+  bfloat16 storage (3.6 HU, the rounding-derived bar of the precision tests), RMS over the field of view
+  and the whole image, max |dx| within ten times that: float32 over 20 iterations unrelaxed, both storage
+  types over the first 2 iterations (relaxed and unrelaxed). At 41 subsets the relaxed iteration is chaotic
+  on the 256^2 class (12 views per subset): the FP64 oracle runs away from the phantom, and two oracle runs
+  whose starts differ by 0.005 HU end more than 1 HU apart after 20 iterations (pinned on the CPU in
+  test_oracle_recursion), so no rounding-derived bar holds after 20 relaxed iterations there; the unrelaxed
+  iteration stays contractive. The bfloat16 bar is the fixed-point rounding residual of the projector's
+  image copy; over 20 iterations of 12-view subsets the per-step rounding accumulates past it on the 256^2
+  class (3.9 HU RMS measured), so the 20-iteration bfloat16 errors are reported per class on the benchmark
+  line rather than asserted.
 """
 import math
 
@@ -16,7 +25,7 @@ import pytest
 import oracle
 from paper_1512_04564_amd import synth
 
-from gpu_util import hu_rmsd, say, to_dev, to_np
+from gpu_util import image_parity, say, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -82,9 +91,7 @@ def test_batched_given_start_and_order_invariance(api):
         po = oracle.params(alpha=1.999, niters=4, nsubsets=g.nsubsets, subset_order="bitrev")
         xo, _, _ = oracle.rlalm_solve(g, po, scans[i].y.astype(np.float64), scans[i].w.astype(np.float64),
                                       x0s[i].astype(np.float64))
-        d = hu_rmsd(to_np(xs[i]), xo, oracle.fov_mask(g, synth.fov_radius(g)))
-        say(f"  slice {i} ({g.nx}^2): RMSD(gpu, oracle) = {d:.4f} HU")
-        assert d <= 0.5
+        image_parity(to_np(xs[i]), xo, g, tag=f"slice {i} ({g.nx}^2)")
     # same slices, reversed order in the call: same bits per slice (same launch shape via the cache
     # is not guaranteed for a new shape key, so force the default shape on both)
     xa = [to_dev(x0) for x0 in x0s]
@@ -97,9 +104,10 @@ def test_batched_given_start_and_order_invariance(api):
         assert torch.equal(xa[i], xb[2 - i])
 
 
-@pytest.mark.parametrize("storage", ["f32", "bf16"])
-def test_batched_full_size_classes_against_oracle(api, storage):
-    """One slice of each full-size class (the uneven batch's shapes, M = 41) for 2 iterations from zero."""
+@pytest.mark.parametrize("storage,alpha,niters", [("f32", 1.0, 20), ("f32", 1.999, 2), ("bf16", 1.999, 2),
+                                                  ("bf16", 1.0, 2)])
+def test_batched_full_size_classes_against_oracle(api, storage, alpha, niters):
+    """One slice of each full-size class (the uneven batch's shapes, M = 41) from zero."""
     import torch
     geoms = list(synth.BATCH_CLASSES)
     scans = [synth.noisy_scan(g, 300 + i, truth=False) for i, g in enumerate(geoms)]
@@ -107,17 +115,16 @@ def test_batched_full_size_classes_against_oracle(api, storage):
     cpu = [(torch.from_numpy(s.y).to(dt), torch.from_numpy(s.w).to(dt)) for s in scans]
     Gs = [api.Geometry(g, storage) for g in geoms]
     xs = [torch.zeros((g.ny, g.nx), device="cuda:0") for g in geoms]
-    p = api.Params(alpha=1.999, niters=2, subset_order="bitrev", start="zero")
+    p = api.Params(alpha=alpha, niters=niters, subset_order="bitrev", start="zero")
     cfg = api.rlalm_solve_batched(Gs, p, [y.cuda() for y, _ in cpu], [w.cuda() for _, w in cpu], xs, autotune=True)
     say(f"[batch {storage}] tuned: {cfg}")
     bar = {"f32": 0.5, "bf16": 3.6}[storage]   # bfloat16: the rounding-derived bar of test_gpu_precision
     for i, g in enumerate(geoms):
-        po = oracle.params(alpha=1.999, niters=2, nsubsets=g.nsubsets, subset_order="bitrev")
+        po = oracle.params(alpha=alpha, niters=niters, nsubsets=g.nsubsets, subset_order="bitrev")
         y64, w64 = (t.to(torch.float64).numpy() for t in cpu[i])
         xo, _, _ = oracle.rlalm_solve(g, po, y64, w64, np.zeros((g.ny, g.nx)))
-        d = hu_rmsd(to_np(xs[i]), xo, oracle.fov_mask(g, synth.fov_radius(g)))
-        say(f"  slice {i} ({g.nx}^2, {g.nviews} views): RMSD(gpu {storage}, oracle) = {d:.4f} HU (bar {bar})")
-        assert d <= bar
+        image_parity(to_np(xs[i]), xo, g, bar_rms=bar,
+                     tag=f"slice {i} ({g.nx}^2, {g.nviews} views, {storage}, alpha {alpha}, {niters} iterations)")
 
 
 def test_batched_argument_errors(api):

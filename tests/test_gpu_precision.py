@@ -8,7 +8,8 @@ is at most half a unit in the last place of the binade [2^-5, 2^-4): 2^-5 * 2^-1
 in float16 and 2^-5 * 2^-8 = 1.2e-4 mm^-1 = 6.1 HU in bfloat16. Uniform rounding has RMS 1/sqrt(3) of
 that (0.44 / 3.52 HU; body values, one binade lower, give half), and at the fixed point the image differs
 from the oracle's by its own rounding residual (the projector sees the rounded copy). Bars: float16 0.5 HU
-(the float32 bar), bfloat16 3.6 HU. float16 needs the weights in range: w and beta are scaled by 2^-6,
+(the float32 bar), bfloat16 3.6 HU, as RMSD over the field-of-view disk and over the whole image; the
+largest pixel difference may reach ten times the RMS bar (as for float32). float16 needs the weights in range: w and beta are scaled by 2^-6,
 which leaves the iterates unchanged (pinned on the oracle in test_oracle_algorithm).
 
 The 512^2 cases use the bit-reversed subset order: with the sequential order at M = 41 the iteration
@@ -22,7 +23,7 @@ import pytest
 import oracle
 from paper_1512_04564_amd import synth
 
-from gpu_util import hu_rmsd, rel_norm, say, to_dev, to_np
+from gpu_util import image_parity, rel_norm, say, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -65,10 +66,7 @@ def test_solve_parity_16bit_cfg1(api, storage):
     api.rlalm_solve(G, api.Params(alpha=1.999, niters=20, subset_order="bitrev", beta=1024.0 * c), y, w, x)
     po = oracle.params(alpha=1.999, niters=20, nsubsets=g.nsubsets, subset_order="bitrev", beta=1024.0 * c)
     xo, _, _ = oracle.rlalm_solve(g, po, y64, w64, np.zeros((g.ny, g.nx)))
-    mask = oracle.fov_mask(g, synth.fov_radius(g))
-    d = hu_rmsd(to_np(x), xo, mask)
-    say(f"  RMSD(gpu {storage}, oracle) = {d:.4f} HU (bar {BAR_HU[storage]})")
-    assert d <= BAR_HU[storage]
+    image_parity(to_np(x), xo, g, bar_rms=BAR_HU[storage], tag=storage)
 
 
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
@@ -83,10 +81,7 @@ def test_solve_parity_16bit_cfg2_first_iterations(api, storage):
     api.rlalm_solve(G, api.Params(alpha=1.999, niters=2, subset_order="bitrev", beta=1024.0 * c), y, w, x)
     po = oracle.params(alpha=1.999, niters=2, nsubsets=g.nsubsets, subset_order="bitrev", beta=1024.0 * c)
     xo, _, _ = oracle.rlalm_solve(g, po, y64, w64, np.zeros((g.ny, g.nx)))
-    mask = oracle.fov_mask(g, synth.fov_radius(g))
-    d = hu_rmsd(to_np(x), xo, mask)
-    say(f"  RMSD(gpu {storage}, oracle) = {d:.4f} HU (bar {BAR_HU[storage]})")
-    assert d <= BAR_HU[storage]
+    image_parity(to_np(x), xo, g, bar_rms=BAR_HU[storage], tag=storage)
 
 
 @pytest.mark.parametrize("storage", ["f16", "bf16"])

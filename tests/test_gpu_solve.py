@@ -1,10 +1,11 @@
 """GPU solver parity: the HIP relaxed OS-LALM (through the C ABI) against the FP64 oracle's Algorithm 1.
 
-Bar: image RMSD <= 0.5 HU (mu_water = 0.02 mm^-1) over the field-of-view disk after a fixed number of
-iterations. Cases: cfg1 (128^2, 220 views, M = 10, 20 iterations) for alpha = 1 and 1.999, and cfg2
-(512^2, 984 views, M = 41) for a few iterations at full size; one subiteration at full size compared
-element-wise on x, g and h; the state interface (init / iterate, checkpoint-resume) and graph replay
-compared bitwise against the plain launches.
+Bar: image RMSD <= 0.5 HU (mu_water = 0.02 mm^-1) over the field-of-view disk and over the whole image,
+and max |x_gpu - x_oracle| <= 5 HU over the whole image, after a fixed number of iterations. Cases: the
+128^2 scan (220 views, M = 10, 20 iterations) for alpha = 1 and 1.999 and the options; the 512^2 scan
+(984 views, M = 41) for a few iterations at full size, and long runs at M = 41, 12 and 1; one
+subiteration at full size compared norm-wise on x, g and h; the state interface (init / iterate,
+checkpoint-resume) and graph replay compared bitwise against the plain launches.
 """
 import math
 
@@ -14,7 +15,7 @@ import pytest
 import oracle
 from paper_1512_04564_amd import synth
 
-from gpu_util import hu_rmsd, rel_norm, say, to_dev, to_np
+from gpu_util import hu_rmsd, image_parity, rel_norm, say, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -85,10 +86,7 @@ def test_solve_parity_cfg1(api, case):
     say(f"[solve cfg1] {case}")
     xg = gpu_solve(api, g, s, x0, niters=20, **case)
     xo = oracle_solve(g, s, x0.astype(np.float64), niters=20, **case)
-    mask = oracle.fov_mask(g, synth.fov_radius(g))
-    d = hu_rmsd(xg, xo, mask)
-    say(f"  RMSD(gpu, oracle) = {d:.4f} HU; RMSD(oracle, truth) = {hu_rmsd(xo, s.truth, mask):.2f} HU")
-    assert d <= 0.5
+    image_parity(xg, xo, g)
 
 
 def test_solve_parity_cfg1_divergent_default(api):
@@ -98,13 +96,10 @@ def test_solve_parity_cfg1_divergent_default(api):
     g = synth.CFG1
     s = scan(g, 0)
     x0 = np.zeros((g.ny, g.nx), dtype=np.float32)
-    mask = oracle.fov_mask(g, synth.fov_radius(g))
     for k in (1, 2):
         xg = gpu_solve(api, g, s, x0, niters=k, alpha=1.999)
         xo = oracle_solve(g, s, x0.astype(np.float64), niters=k, alpha=1.999)
-        d = hu_rmsd(xg, xo, mask)
-        say(f"  k={k}: RMSD(gpu, oracle) = {d:.4f} HU")
-        assert d <= 0.5
+        image_parity(xg, xo, g, tag=f"k={k}")
 
 
 def test_state_interface_matches_solve_and_resumes_bitwise(api):
@@ -146,7 +141,7 @@ def test_state_interface_matches_solve_and_resumes_bitwise(api):
 
 
 def test_init_and_one_subiteration_parity_cfg2(api):
-    """Full-size cfg2: the initial state and one subiteration from it, element-wise against the oracle."""
+    """The 512^2 scan: the initial state and one subiteration from it, norm-wise against the oracle (1e-5)."""
     import torch
     g = synth.CFG2
     s = scan(g, 100)
@@ -183,10 +178,7 @@ def test_solve_parity_cfg2_first_iterations(api, alpha):
     say(f"[solve cfg2] alpha={alpha}, 2 iterations")
     xg = gpu_solve(api, g, s, x0, niters=2, alpha=alpha)
     xo = oracle_solve(g, s, x0.astype(np.float64), niters=2, alpha=alpha)
-    mask = oracle.fov_mask(g, synth.fov_radius(g))
-    d = hu_rmsd(xg, xo, mask)
-    say(f"  RMSD(gpu, oracle) = {d:.4f} HU")
-    assert d <= 0.5
+    image_parity(xg, xo, g)
 
 
 RAGGED = {
@@ -207,9 +199,8 @@ def test_solve_parity_ragged_and_arc(api, name):
     xg = gpu_solve(api, g, s, x0, **case)
     xo = oracle_solve(g, s, x0.astype(np.float64), **case)
     mask = oracle.fov_mask(g, synth.fov_radius(g))
-    d = hu_rmsd(xg, xo, mask)
-    say(f"[solve {name}] RMSD(gpu, oracle) = {d:.4f} HU over {int(mask.sum())} FOV pixels")
-    assert mask.sum() > 100 and d <= 0.5
+    assert mask.sum() > 100
+    image_parity(xg, xo, g, tag=name)
 
 
 def test_solve_parity_exp_weights(api):
@@ -221,10 +212,7 @@ def test_solve_parity_exp_weights(api):
     case = dict(alpha=1.999, subset_order="bitrev", niters=20, beta=1024.0 / 1e5)
     xg = gpu_solve(api, g, s, x0, **case)
     xo = oracle_solve(g, s, x0.astype(np.float64), **case)
-    mask = oracle.fov_mask(g, synth.fov_radius(g))
-    d = hu_rmsd(xg, xo, mask)
-    say(f"[solve exp weights] RMSD(gpu, oracle) = {d:.4f} HU; RMSD(oracle, truth) = {hu_rmsd(xo, s.truth, mask):.2f} HU")
-    assert d <= 0.5
+    image_parity(xg, xo, g, tag="exp weights")
 
 
 def test_solve_parity_potentials(api):
@@ -241,9 +229,7 @@ def test_solve_parity_potentials(api):
         case = dict(alpha=1.999, subset_order="bitrev", niters=20, beta=1e6, potential=pot)
         xg = gpu_solve(api, g, s, x0, **case)
         xo[pot] = oracle_solve(g, s, x0.astype(np.float64), **case)
-        d = hu_rmsd(xg, xo[pot], mask)
-        say(f"[solve potential {pot}, beta 1e6] RMSD(gpu, oracle) = {d:.4f} HU")
-        assert d <= 0.05
+        image_parity(xg, xo[pot], g, bar_rms=0.05, tag=f"potential {pot}, beta 1e6")
     for a, b in (("hyperbola", "fair"), ("hyperbola", "qggmrf"), ("fair", "qggmrf")):
         assert hu_rmsd(xo[a], xo[b], mask) > 0.3, (a, b)
 
@@ -273,6 +259,56 @@ def test_forward_split_with_unstaged_windows(api):
     mask = oracle.fov_mask(g, synth.fov_radius(g))
     xs = {k: gpu_solve(api, g, s, x0, niters=4, alpha=1.999, subset_order="bitrev", forward_split=k) for k in (0, 1)}
     xo = oracle_solve(g, s, x0.astype(np.float64), niters=4, alpha=1.999, subset_order="bitrev")
-    d01, d1o = hu_rmsd(xs[0], xs[1], mask), hu_rmsd(xs[1], xo, mask)
-    say(f"  RMSD(split, unsplit) = {d01:.2e} HU, RMSD(split, oracle) = {d1o:.4f} HU")
-    assert d01 <= 0.01 and d1o <= 0.5
+    d01 = hu_rmsd(xs[0], xs[1], mask)
+    say(f"  RMSD(split, unsplit) = {d01:.2e} HU")
+    assert d01 <= 0.01
+    image_parity(xs[1], xo, g, tag="split")
+
+
+LONG_CASES = [
+    # the named 41-subset configuration over 100 iterations, unrelaxed (alpha = 1 stays stable at 41 subsets
+    # on this scan; alpha = 1.999 falls into a limit cycle hundreds of HU wide there, whose phase the
+    # rounding difference between FP32 and FP64 decides, so it has only the short runs above)
+    dict(nsubsets=41, alpha=1.0, niters=100),
+    # the 12-subset configurations behind the time-to-1-HU, relaxation and ablation numbers
+    dict(nsubsets=12, alpha=1.999, niters=30),
+    dict(nsubsets=12, alpha=1.0, niters=30),
+    # one subset of all 984 views
+    dict(nsubsets=1, alpha=1.999, niters=20),
+]
+
+
+@pytest.mark.parametrize("case", LONG_CASES, ids=lambda c: "-".join(f"{k}={v}" for k, v in c.items()))
+def test_solve_parity_cfg2_long(api, case):
+    """The 512^2 scan over many iterations (bit-reversed subset order, FBP-like start computed by the
+    oracle for both sides), against the oracle over the whole image."""
+    case = dict(case)
+    M = case.pop("nsubsets")
+    g = synth.CFG2.replace(nsubsets=M)
+    s = scan(synth.CFG2, 100)
+    x0 = oracle.fbp(g, s.y.astype(np.float64)).astype(np.float32)
+    say(f"[solve 512^2 long] M={M} {case}")
+    xg = gpu_solve(api, g, s, x0, subset_order="bitrev", **case)
+    xo = oracle_solve(g, s, x0.astype(np.float64), subset_order="bitrev", **case)
+    image_parity(xg, xo, g, tag=f"M={M}")
+
+
+def test_graph_cache_follows_forward_split(api):
+    """Two solves on one handle that differ only in forward_split: the second must not replay the graph
+    captured for the first (its result equals that of a fresh handle, bit for bit)."""
+    import torch
+    g = synth.CFG1
+    s = scan(g, 0)
+    y, w = to_dev(s.y), to_dev(s.w)
+    G = api.Geometry(g)
+    outs = {}
+    for k in (1, 0):
+        x = torch.zeros((g.ny, g.nx), device="cuda:0")
+        api.rlalm_solve(G, api.Params(alpha=1.999, niters=4, subset_order="bitrev", forward_split=k), y, w, x)
+        outs[k] = x
+    x_fresh = torch.zeros((g.ny, g.nx), device="cuda:0")
+    api.rlalm_solve(api.Geometry(g), api.Params(alpha=1.999, niters=4, subset_order="bitrev", forward_split=0), y, w,
+                    x_fresh)
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], x_fresh)
+    assert not torch.equal(outs[0], outs[1])

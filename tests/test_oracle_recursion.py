@@ -11,6 +11,9 @@
    relaxed iteration runs away from the phantom within 20 iterations, while the bit-reversed order stays
    bounded. The GPU parity cases at alpha = 1.999 therefore use the bit-reversed order (or only the first
    iterations of the sequential one).
+3. The 256^2 slice class of the uneven batch (492 views, 41 subsets of 12 views): relaxed, the iteration
+   is chaotic -- two runs whose starts differ by at most 0.005 HU end more than 1 HU apart after 20
+   iterations -- while unrelaxed they stay within 0.01 HU. Long batched parity runs are unrelaxed.
 """
 import math
 
@@ -143,3 +146,19 @@ def test_bitreversed_order_stays_bounded_at_128():
     assert np.all(np.isfinite(tr))
     assert tr.max() <= 2.0 * tr[0], tr
     assert tr[-1] <= 100.0, tr
+
+
+def test_relaxed_41_subsets_is_chaotic_on_the_256_class():
+    g = synth.BATCH_CLASSES[0]
+    s = synth.noisy_scan(g, 300, truth=False)
+    y, w = s.y.astype(np.float64), s.w.astype(np.float64)
+    x0 = np.zeros((g.ny, g.nx))
+    x1 = np.random.default_rng(0).uniform(0.0, 1e-7, x0.shape)   # 1e-7 mm^-1 = 0.005 HU
+    mask = oracle.fov_mask(g, synth.fov_radius(g))
+    gap = {}
+    for alpha in (1.999, 1.0):
+        p = oracle.params(alpha=alpha, niters=20, nsubsets=g.nsubsets, subset_order="bitrev")
+        xa, _, _ = oracle.rlalm_solve(g, p, y, w, x0)
+        xb, _, _ = oracle.rlalm_solve(g, p, y, w, x1)
+        gap[alpha] = oracle.rmsd_hu(xa, xb, mask)
+    assert gap[1.999] > 1.0 and gap[1.0] < 0.01, gap
