@@ -14,8 +14,8 @@ imports it. Plain numpy in NCHW layout, float64 throughout, every step written o
 * Adam with bias correction (Kingma and Ba): m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
   w -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
 
-The warm start itself (not the paper's; an extension) feeds this network the image A'(w y) / D_L in
-units of mu_water. Parameters are one flat vector in canonical order: per layer the weight
+The warm start itself (not the paper's; an extension) feeds this network the FBP-like image of the scan
+in units of mu_water (the network adds a correction to it). Parameters are one flat vector in canonical order: per layer the weight
 [c_out][c_in][k][k] then the bias [c_out], layers as listed in LAYERS.
 """
 from __future__ import annotations

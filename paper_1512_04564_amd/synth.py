@@ -451,10 +451,22 @@ def _chords3(src, det, ellipsoids):
     return total
 
 
-def analytic_helical_sinogram(g: HelicalGeometry, ellipsoids, subrays: int = 2, views=None) -> np.ndarray:
+def _helical_chunk(a):
+    g, ell, subrays, views = a
+    return analytic_helical_sinogram(g, ell, subrays=subrays, views=views)
+
+
+def analytic_helical_sinogram(g: HelicalGeometry, ellipsoids, subrays: int = 2, views=None,
+                              workers: int = 1) -> np.ndarray:
     """Exact ellipsoid line integrals averaged over subrays x subrays rays per detector cell:
-    ``[views][nr][nb]`` float64."""
+    ``[views][nr][nb]`` float64. ``workers`` > 1 splits the views over forked processes (call it before the
+    calling process has initialised a GPU)."""
     v = np.arange(g.nviews) if views is None else np.asarray(views)
+    if workers > 1 and len(v) > workers:
+        import multiprocessing as mp
+        parts = np.array_split(v, workers * 4)
+        with mp.get_context("fork").Pool(workers) as pool:
+            return np.concatenate(pool.map(_helical_chunk, [(g, ellipsoids, subrays, pv) for pv in parts]))
     sub = (np.arange(subrays) + 0.5) / subrays
     u = ((np.arange(g.nb)[:, None] + sub[None, :]) - g.nb / 2.0 + g.u_offset) * g.du     # [nb][s]
     w = ((np.arange(g.nr)[:, None] + sub[None, :]) - g.nr / 2.0 + g.w_offset) * g.dw     # [nr][s]
@@ -479,12 +491,12 @@ class HelicalScan:
 
 
 def noisy_helical_scan(g: HelicalGeometry, seed: int, *, i0: float = 1e5, sigma: float = 5.0, subrays: int = 2,
-                       truth: bool = True) -> HelicalScan:
+                       truth: bool = True, workers: int = 1) -> HelicalScan:
     """One seeded helical scan: Poisson(I0 e^-l) + N(0, sigma^2) counts clamped at 1, y = log(I0 / Y),
-    w = Y^2 / (Y + sigma^2); y and w rounded to float32."""
+    w = Y^2 / (Y + sigma^2); y and w rounded to float32. ``workers``: processes for the line integrals."""
     rng = np.random.Generator(np.random.PCG64(seed))
     ell = random_ellipsoids(g, seed, rng=rng)
-    li = analytic_helical_sinogram(g, ell, subrays=subrays)
+    li = analytic_helical_sinogram(g, ell, subrays=subrays, workers=workers)
     counts = rng.poisson(i0 * np.exp(-li)).astype(np.float64) + rng.normal(0.0, sigma, li.shape)
     counts = np.maximum(counts, 1.0)
     y = np.log(i0 / counts).astype(np.float32)
