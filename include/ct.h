@@ -88,6 +88,17 @@ void ct_geom_destroy(ct_geom *g);
 ct_status ct_forward(const ct_geom *g, int subset, const float *x, float *p, void *stream);
 
 /*
+ * ct_forward for callers that cannot allocate device memory (code under stream or graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same result as ct_forward, bit for bit, but the
+ * transposed image copy the projector reads lives in a fixed scratch array of the library on each GPU
+ * (16 MiB: images of at most 4 Mi pixels; larger images are CT_ERR_INVALID_ARG, nothing launched) instead
+ * of the handle's workspace. The call allocates nothing (no hipMalloc, no library allocation); the
+ * geometry's device must be current. Every call on one GPU shares that GPU's array: calls that overlap in
+ * time on one GPU (other streams, other threads) race on it and must be ordered by the caller.
+ */
+ct_status ct_forward_noalloc(const ct_geom *g, int subset, const float *x, float *p, void *stream);
+
+/*
  * x = A_m' r : matched distance-driven back-projection (gather form, no atomics) of the float32
  * sinogram block r for subset m ([nviews/M][nb]) or all views (subset == -1, [nviews][nb]).
  * x ([ny][nx]) is overwritten.

@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "CT_OK", 1: "CT_ERR_INVALID_ARG", 2: "CT_ERR_OOM", 3: "CT_ERR
                 5: "CT_ERR_DIVERGED"}
 
 #: Every entry point declared in include/ct.h.
-EXPORTS = ("ct_geom_create", "ct_geom_destroy", "ct_forward", "ct_back", "ct_fbp", "ct_rlalm_params_default",
+EXPORTS = ("ct_geom_create", "ct_geom_destroy", "ct_forward", "ct_forward_noalloc", "ct_back", "ct_fbp", "ct_rlalm_params_default",
            "ct_rlalm_solve", "ct_rlalm_solve_batched", "ct_rlalm_prepare", "ct_rlalm_init", "ct_rlalm_iterate",
            "ct_rlalm_kernel_times", "ct_rlalm_status", "ct_cost", "ct_last_error", "ct_unet_num_params",
            "ct_unet_create", "ct_unet_destroy", "ct_unet_set_params", "ct_helix_create", "ct_helix_destroy",
@@ -90,6 +90,7 @@ def load() -> ctypes.CDLL:
     L.ct_geom_destroy.argtypes = [vp]
     L.ct_geom_destroy.restype = None
     L.ct_forward.argtypes = [vp, i, vp, vp, vp]
+    L.ct_forward_noalloc.argtypes = [vp, i, vp, vp, vp]
     L.ct_back.argtypes = [vp, i, vp, vp, vp]
     L.ct_fbp.argtypes = [vp, vp, vp, vp]
     L.ct_rlalm_params_default.argtypes = [ctypes.POINTER(RlalmParams)]

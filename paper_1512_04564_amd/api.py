@@ -16,7 +16,7 @@ import torch
 from . import _lib
 from ._lib import CtError, GeomDesc, RlalmParams, TraceRow, check
 
-__all__ = ["Geometry", "Params", "forward", "back", "fbp", "cost", "rlalm_solve", "rlalm_status",
+__all__ = ["Geometry", "Params", "forward", "forward_noalloc", "back", "fbp", "cost", "rlalm_solve", "rlalm_status",
            "rlalm_solve_batched", "rlalm_prepare", "rlalm_init", "rlalm_iterate", "kernel_times", "Helix",
            "helix_forward", "helix_back", "helix_solve", "CtError"]
 
@@ -143,6 +143,14 @@ def forward(g: Geometry, x: torch.Tensor, subset: int = -1, out: torch.Tensor | 
         out = torch.empty((nv, g.nb), dtype=torch.float32, device=x.device)
     check(g._lib.ct_forward(g.handle, subset, _ptr(x, shape=g.img_shape, name="x"),
                             _ptr(out, shape=(nv, g.nb), name="out"), _stream_handle(stream)))
+    return out
+
+
+def forward_noalloc(g: Geometry, x: torch.Tensor, out: torch.Tensor, subset: int = -1, stream=None):
+    """ct_forward_noalloc: A_m x into the caller's ``out`` with no device allocation in the library."""
+    nv = g.views_in(subset)
+    check(g._lib.ct_forward_noalloc(g.handle, subset, _ptr(x, shape=g.img_shape, name="x"),
+                                    _ptr(out, shape=(nv, g.nb), name="out"), _stream_handle(stream)))
     return out
 
 

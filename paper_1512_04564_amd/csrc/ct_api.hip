@@ -861,6 +861,61 @@ ct_status ct_forward(const ct_geom *gc, int subset, const float *x, float *p, vo
     return CT_OK;
 }
 
+}  // extern "C"
+
+// Scratch of ct_forward_noalloc: the projector's transposed image copy, in a file-scope device array that
+// each GPU holds until the process ends. Host code never uses the array's name as an address: its device
+// address is looked up once per device (hipGetSymbolAddress, with that device current) and kept.
+namespace {
+
+constexpr size_t kNoAllocFloats = (size_t)4 << 20;   // 16 MiB: images up to 4 Mi pixels (2048 x 2048)
+__device__ __align__(256) float scratch[kNoAllocFloats];
+
+std::mutex g_scratch_mu;
+std::map<int, float *> g_scratch_addr;
+
+ct_status scratch_address(int device, float **out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(device);
+    if (it != g_scratch_addr.end()) {
+        *out = it->second;
+        return CT_OK;
+    }
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(CT_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_addr[device] = static_cast<float *>(ptr);
+    *out = static_cast<float *>(ptr);
+    return CT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ct_status ct_forward_noalloc(const ct_geom *gc, int subset, const float *x, float *p, void *stream)
+{
+    if (!gc || !x || !p) return fail(CT_ERR_INVALID_ARG, "NULL argument");
+    int vs, vst, nv;
+    CT_TRY(subset_range(gc, subset, &vs, &vst, &nv));
+    const size_t npix = (size_t)gc->desc.nx * gc->desc.ny;
+    if (npix > kNoAllocFloats)
+        return fail(CT_ERR_INVALID_ARG, "image of " + std::to_string(npix) + " pixels exceeds the " +
+                                            std::to_string(kNoAllocFloats) + "-pixel scratch of ct_forward_noalloc");
+    int dev = -1;
+    CT_HIP_CHECK(hipGetDevice(&dev));
+    if (dev != gc->device) return fail(CT_ERR_INVALID_ARG, "the geometry's device must be the current device");
+    float *xt = nullptr;
+    CT_TRY(scratch_address(dev, &xt));
+    hipStream_t s = as_stream(stream);
+    CT_HIP_CHECK(launch_transpose(x, xt, gc->desc.nx, gc->desc.ny, s));
+    CT_HIP_CHECK(launch_forward(fp_launch(gc->dev, x, xt, vs, vst, nv, nullptr, nullptr, 1.f, p), 0, FP_PLAIN, CT_F32,
+                                s));
+    return CT_OK;
+}
+
 ct_status ct_back(const ct_geom *gc, int subset, const float *r, float *x, void *stream)
 {
     if (!gc || !r || !x) return fail(CT_ERR_INVALID_ARG, "NULL argument");
