@@ -156,6 +156,62 @@ def unet_workload():
     print(f"network workload done: {a.elapsed_time(b) / 10:.4f} ms per 512^2 inference", flush=True)
 
 
+def unet_train_setup(batch, g):
+    """Network, inputs, targets and mask of a training workload at batch x 512^2: the FBP-like inputs of
+    `batch` scans and targets a fixed smooth shift of them (the kernels' work does not depend on values)."""
+    import torch
+    from paper_1512_04564_amd import api, synth, unet
+    G = api.Geometry(g)
+    X = torch.empty((batch, g.ny, g.nx), device="cuda:0")
+    for i in range(batch):
+        s = synth.noisy_scan(g, 100 + i, truth=False)
+        unet.network_input(G, torch.as_tensor(s.y, device="cuda:0"), out=X[i])
+    T = (X * 0.98).contiguous()
+    yy, xx = np.mgrid[:g.ny, :g.nx]
+    r = np.hypot((xx - (g.nx - 1) / 2) * g.dx, (yy - (g.ny - 1) / 2) * g.dy)
+    mask = torch.as_tensor((r <= synth.fov_radius(g)).astype(np.uint8), device="cuda:0")
+    theta = np.load(UNET_WEIGHTS)["theta"] if os.path.exists(UNET_WEIGHTS) else synth.unet_params(1)
+    net = unet.UNet(theta, batch, g.ny, g.nx)
+    return net, X, T, mask
+
+
+def unet_train_workload():
+    """Short workload for a kernel trace of network training: 3 + 5 Adam steps at batch 4 x 512^2."""
+    import torch
+    from paper_1512_04564_amd import synth
+    net, X, T, mask = unet_train_setup(4, synth.CFG2)
+    for _ in range(8):
+        net.train_step(X, T, mask, 1e-5, want_loss=False)
+    torch.cuda.synchronize()
+    print("network training workload done", flush=True)
+
+
+def unet_train_rate(dev):
+    """Training steps of the warm-start network at batch 4 x 512^2 (forward, backward, Adam), timed
+    between HIP events; algorithmic flops: three times the forward pass per sample (the backward pass
+    computes the input gradient and the weight gradient, each a contraction of the forward's size)."""
+    import torch
+    from paper_1512_04564_amd import synth
+    g = synth.CFG2
+    batch, reps = 4, 10
+    net, X, T, mask = unet_train_setup(batch, g)
+    for _ in range(3):
+        net.train_step(X, T, mask, 1e-5, want_loss=False)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        net.train_step(X, T, mask, 1e-5, want_loss=False)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    fl = 3.0 * batch * unet_flops(g.ny, g.nx)
+    return {"batch": batch, "ms_per_step": round(ms, 3), "gflop_per_step": round(fl / 1e9, 1),
+            "tflops": round(fl / (ms * 1e-3) / 1e12, 1), "bound": "mfma", "peak_tflops": MFMA_BF16_PEAK_TFLOPS,
+            "frac": round(fl / (ms * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS, 4)}
+
+
 def dd_work_counts(g):
     """Distance-driven work per outer iteration (all views), FP64 geometry written out here:
     nonzeros of A, (bin, line) pairs, (pixel, view) pairs."""
@@ -250,6 +306,135 @@ def oracle_class_rmsd(geoms, ys64, ws64, xs_gpu, niters, alpha):
     return out
 
 
+HELIX_SEED = 200
+
+
+def helix_work_counts(g, views):
+    """Separable distance-driven work of the helical projector for the listed views, counted in FP64 from
+    the geometry (written out here): transaxial (plane, bin, column) overlaps, and (plane, bin, column,
+    row, voxel) nonzeros of A."""
+    u = (np.arange(g.nb + 1) - g.nb / 2.0 + g.u_offset) * g.du
+    wb = (np.arange(g.nr + 1) - g.nr / 2.0 + g.w_offset) * g.dw
+    zlo = g.zc - 0.5 * g.nz * g.dz
+    pairs = nnz = 0
+    for v in views:
+        beta = g.beta0 + 2 * math.pi * v / g.views_per_turn
+        c, s_ = math.cos(beta), math.sin(beta)
+        S = np.array([-g.dso * c, -g.dso * s_])
+        sz = g.z0 + g.feed * v / g.views_per_turn
+        P = np.stack([(g.dsd - g.dso) * c - u * s_, (g.dsd - g.dso) * s_ + u * c], axis=1)
+        row = abs(s_) >= abs(c) - 1e-12
+        nl, nq = (g.ny, g.nx) if row else (g.nx, g.ny)
+        dl, dq = (g.dy, g.dx) if row else (g.dx, g.dy)
+        al, aq = (1, 0) if row else (0, 1)
+        cl = (np.arange(nl) - (nl - 1) / 2.0) * dl
+        t = (cl[:, None] - S[al]) / (P[None, :, al] - S[al])
+        b = (S[aq] + t * (P[None, :, aq] - S[aq])) / dq + nq / 2.0            # [lines][nb + 1]
+        lo = np.clip(np.minimum(b[:, :-1], b[:, 1:]), 0, nq)
+        hi = np.clip(np.maximum(b[:, :-1], b[:, 1:]), 0, nq)
+        q0 = np.floor(lo).astype(np.int64)
+        q1 = np.ceil(hi).astype(np.int64)
+        n_t = np.where(hi > lo, q1 - q0, 0)
+        pairs += int(n_t.sum())
+        # axial nonzeros per column: rows meeting the volume plus the voxel faces inside their span
+        cq = (np.arange(nq) - (nq - 1) / 2.0) * dq
+        X = cq[None, :] if row else cl[:, None]
+        Y = cl[:, None] if row else cq[None, :]
+        ell = (X - S[0]) * c + (Y - S[1]) * s_                                    # [lines][nq]
+        z = (sz + wb[None, None, :] * ell[:, :, None] / g.dsd - zlo) / g.dz       # [lines][nq][nr + 1]
+        za, zb = np.clip(z[..., 0], 0, g.nz), np.clip(z[..., -1], 0, g.nz)
+        inside = ((z[..., 1:] > 0) & (z[..., :-1] < g.nz)).sum(axis=-1)
+        faces = np.maximum(np.ceil(zb) - np.floor(za) - 1, 0)
+        ax = (inside + faces).astype(np.int64)                                    # [lines][nq]
+        lidx = np.repeat(np.arange(nl)[:, None], g.nb, axis=1)
+        for d in range(int(n_t.max()) if n_t.size else 0):
+            m = n_t > d
+            qq = np.minimum(q0 + d, nq - 1)
+            nnz += int(ax[lidx[m], qq[m]].sum())
+    return dict(transaxial_pairs=pairs, nnz=nnz)
+
+
+def helix_section(api, scan, niters, dev):
+    """3-D helical workload: a timed relaxed OS-LALM solve (12 subsets of 246 views), and the projector
+    pair's per-launch time on one subset between HIP events on the stream the kernels run on."""
+    import torch
+    from paper_1512_04564_amd import synth
+    g = synth.CFG3
+    Hh = api.Helix(g)
+    y = torch.as_tensor(scan.y, device=dev)
+    w = torch.as_tensor(scan.w, device=dev)
+    x = torch.zeros((g.nz, g.ny, g.nx), device=dev)
+    stream = torch.cuda.current_stream()
+    p1 = api.Params(alpha=1.999, niters=1, subset_order=ORDER, start="zero")
+    api.helix_solve(Hh, p1, y, w, x)
+    p = api.Params(alpha=1.999, niters=niters, subset_order=ORDER, start="zero")
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    api.helix_solve(Hh, p, y, w, x)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_solve = e0.elapsed_time(e1) / 1e3
+    # kernels of one subset (the solve's projection kernel with a plain epilogue, and the back-projection)
+    m, reps = 5, 5
+    pm = api.helix_forward(Hh, x, subset=m)
+    xb = api.helix_back(Hh, pm, subset=m)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record(stream)
+    for _ in range(reps):
+        api.helix_forward(Hh, x, subset=m, out=pm)
+    ev[1].record(stream)
+    for _ in range(reps):
+        api.helix_back(Hh, pm, subset=m, out=xb)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    t_fp = ev[0].elapsed_time(ev[1]) / reps / 1e3
+    t_bp = ev[1].elapsed_time(ev[2]) / reps / 1e3
+    views = np.arange(m, g.nviews, g.nsubsets)
+    sample = views[::41]                       # 6 of the subset's 246 views, spread over the three turns
+    wk = helix_work_counts(g, sample)
+    scale = len(views) / len(sample)
+    nnz, pairs = wk["nnz"] * scale, wk["transaxial_pairs"] * scale
+    # per-unit figures: 6 VALU ops per nonzero (overlap clamp and FMA), 8 per transaxial pair and row
+    # (row boundary FMA, voxel range, normalisation), as for the fan-beam projector
+    ops = 6 * nnz + 8 * pairs * g.nr
+    out = {"workload": "3-D helical cone beam, 512x512x64 at 0.69x0.69x0.625 mm, flat 888 x 1.0239 mm x 32 rows, "
+                       "3 turns of 984 views, pitch 1.0, 12 subsets (bit-reversed), alpha 1.999, zero start, seed "
+                       f"{HELIX_SEED}",
+           "iters_per_solve": niters, "seconds_per_solve": round(t_solve, 4), "iters_per_s": round(niters / t_solve, 3),
+           "ms_forward_subset": round(t_fp * 1e3, 3), "ms_back_subset": round(t_bp * 1e3, 3),
+           "nnz_per_subset": nnz, "roofline": {}}
+    for name, t in (("forward", t_fp), ("back", t_bp)):
+        ach = ops / t / 1e12
+        out["roofline"][name] = {"bound": "alu", "achieved": round(ach, 3), "peak": round(VALU_PEAK_TOPS, 2),
+                                 "unit": "TOP/s", "frac": round(ach / VALU_PEAK_TOPS, 4), "ops_per_launch": ops,
+                                 "nnz_per_s": round(nnz / t / 1e9, 2)}
+    del Hh
+    return out
+
+
+def helix_workload():
+    """Short workload for a kernel trace of the 3-D path: a 2-iteration solve on the quarter-sampled helical
+    scan, then 3 forward and 3 back-projections of one subset of the full-size scan (zero data)."""
+    import torch
+    from paper_1512_04564_amd import api, synth
+    gs = synth.HELICAL_SMALL
+    s = synth.noisy_helical_scan(gs, HELIX_SEED, truth=False)
+    Hs = api.Helix(gs)
+    x = torch.zeros((gs.nz, gs.ny, gs.nx), device="cuda:0")
+    api.helix_solve(Hs, api.Params(alpha=1.999, niters=2, subset_order=ORDER, start="zero"),
+                    torch.as_tensor(s.y, device="cuda:0"), torch.as_tensor(s.w, device="cuda:0"), x)
+    g = synth.CFG3
+    Hh = api.Helix(g)
+    vol = torch.full((g.nz, g.ny, g.nx), 0.02, device="cuda:0")
+    for _ in range(3):
+        p = api.helix_forward(Hh, vol, subset=5)
+        api.helix_back(Hh, p, subset=5, out=vol)
+    torch.cuda.synchronize()
+    print("helical workload done", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -262,10 +447,14 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--cpu-iters-single", type=int, default=2, help="iterations of the one-thread oracle leg")
     ap.add_argument("--no-batch-oracle", action="store_true", help="skip the per-slice oracle comparison of the batch")
+    ap.add_argument("--no-helix", action="store_true", help="skip the 3-D helical workload")
+    ap.add_argument("--helix-iters", type=int, default=30, help="iterations of the timed 3-D solve")
+    ap.add_argument("--helix-workload", action="store_true", help="run the short 3-D kernel workload and exit")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven 32-slice batch")
     ap.add_argument("--batch-iters", type=int, default=20)
     ap.add_argument("--pmc-workload", action="store_true", help="run the short counter workload and exit")
     ap.add_argument("--unet-workload", action="store_true", help="run the network inference workload and exit")
+    ap.add_argument("--unet-train-workload", action="store_true", help="run the network training workload and exit")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the traffic record from the two counter runs and exit (no GPU)")
     args = ap.parse_args()
@@ -275,6 +464,9 @@ def main():
     if args.unet_workload:
         unet_workload()
         return
+    if args.unet_train_workload:
+        unet_train_workload()
+        return
     if args.write_traffic:
         write_traffic(*args.write_traffic)
         return
@@ -282,6 +474,17 @@ def main():
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU design is described "
               f"in DESIGN.md and not implemented.", file=sys.stderr)
         sys.exit(2)
+    if args.helix_workload:
+        helix_workload()
+        return
+
+    # the 3-D helical scan is simulated in worker processes before this process touches the GPU
+    helix_scan = None
+    if not args.no_helix:
+        from paper_1512_04564_amd import synth as _synth
+        t_h = time.perf_counter()
+        helix_scan = _synth.noisy_helical_scan(_synth.CFG3, HELIX_SEED, subrays=1, truth=False, workers=16)
+        print(f"helical scan simulated in {time.perf_counter() - t_h:.1f} s", file=sys.stderr, flush=True)
 
     import torch
     from paper_1512_04564_amd import api, synth
@@ -413,6 +616,13 @@ def main():
                    "seconds_one_by_one": round(t_seq, 4),
                    "slice_iters_per_s": round(n * args.batch_iters / t_batch, 1),
                    "speedup_vs_one_by_one": round(t_seq / t_batch, 3), "launch_shape": cfg}
+        # both launch forms on the same batch: the lockstep graph at its tuned shape and the single persistent
+        # launch (grid barriers between the phases) at the occupancy the library sizes it to
+        cfg_p = api.rlalm_solve_batched(Gb, pb, ys_b, ws_b, xs_b, autotune="persistent")
+        t_pers = timed(lambda: api.rlalm_solve_batched(Gb, pb, ys_b, ws_b, xs_b, autotune="persistent"), 2)
+        batched["persistent_launch"] = {"seconds_batched": round(t_pers, 4),
+                                        "slice_iters_per_s": round(n * args.batch_iters / t_pers, 1),
+                                        "launch_shape": cfg_p}
         # bfloat16 storage of the same batch
         Gb16 = [api.Geometry(gc, "bf16") for gc in geoms]
         ys16 = [yb.to(torch.bfloat16) for yb in ys_b]
@@ -457,7 +667,8 @@ def main():
         fl = unet_flops(g.ny, g.nx)
         unet_line = {"ms_forward_512": round(t_inf * 1e3, 4), "gflop_per_forward": round(fl / 1e9, 2),
                      "tflops": round(fl / t_inf / 1e12, 1), "bound": "mfma", "peak_tflops": MFMA_BF16_PEAK_TFLOPS,
-                     "frac": round(fl / t_inf / 1e12 / MFMA_BF16_PEAK_TFLOPS, 4)}
+                     "frac": round(fl / t_inf / 1e12 / MFMA_BF16_PEAK_TFLOPS, 4),
+                     "training": unet_train_rate(dev)}
 
     # time to 1 HU against the oracle's converged reference x*, when it is available. Wall time of a whole
     # solve (D_L, start image, initialisation, K iterations) for the first K whose iterate is within 1 HU
@@ -563,6 +774,10 @@ def main():
             ablate[f"M=12,alpha=1.999,D_L scale={sc}"] = run(G12, 50, (10, 20, 50), alpha=1.999, dl_scale=sc)
             ablate[f"M=12,alpha=1.0,D_L scale={sc}"] = run(G12, 50, (10, 20, 50), alpha=1.0, dl_scale=sc)
 
+    helix = None
+    if helix_scan is not None:
+        helix = helix_section(api, helix_scan, args.helix_iters, dev)
+
     cpu = None
     if not args.no_cpu:
         cpu = oracle_baseline(g, s, args.cpu_iters, args.cpu_iters_single)
@@ -594,6 +809,7 @@ def main():
         "relaxation_rmsd_hu_12_subsets": relax,
         "ablations_rmsd_hu": ablate,
         "roofline": roofline,
+        "helical_3d": helix,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

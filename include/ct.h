@@ -210,25 +210,36 @@ ct_status ct_cost(ct_geom *g, const ct_rlalm_params *p, const void *y, const voi
                   const float *kappa, double *out, void *stream);
 
 /*
- * Batched solve of n independent slices (2-D scans of possibly different sizes) in lockstep: at every
- * subiteration one forward-projection launch and one fused update launch cover all slices (a 1-D grid
- * whose workgroups look up their slice), and each outer iteration is replayed from one captured
- * hipGraph. The arithmetic per slice is that of ct_rlalm_solve (Algorithm 1 with rho_k(alpha)).
+ * Batched solve of n independent slices (2-D scans of possibly different sizes), the arithmetic per slice
+ * that of ct_rlalm_solve (Algorithm 1 with rho_k(alpha)). Two launch forms:
+ *   lockstep: at every subiteration one forward-projection launch and one fused update launch cover all
+ *     slices (a 1-D grid whose workgroups look up their slice); each outer iteration is replayed from a
+ *     captured hipGraph;
+ *   persistent: one captured hipGraph holds every slice's initialisation and ONE persistent launch that
+ *     runs all niters * M subiterations: its resident workgroups take the forward work items of every
+ *     slice, then the update tiles, with a grid-wide barrier after each phase (every barrier wait is
+ *     bounded; if the grid was not fully resident the call returns CT_ERR_HIP instead of hanging).
  *   g[i]: a distinct handle per slice; all share nsubsets (M) and storage. y[i], w[i]: that slice's
  *     sinograms in the storage type; x[i]: its float32 image (x0 on entry when p->start == 0, result
  *     on exit). p applies to every slice; trace and time_kernels are not available here (CT_ERR_UNSUPPORTED).
- *   autotune: 0 = default launch shape (16-wave projection workgroups, slices in the given order; with
- *     n == 1 the result equals ct_rlalm_solve bit for bit); 1 = time the candidate shapes (8 or 16 waves
- *     per projection workgroup; given order or largest slice first) on this set of slice shapes and
- *     keep the fastest, cached per process for that set. The order never changes a result; the wave
- *     count changes the projection's summation order.
+ *   autotune: 0 = lockstep with the default shape (16-wave projection workgroups, slices in the given
+ *     order; with n == 1 the result equals ct_rlalm_solve bit for bit); 1 = time the candidates on this
+ *     set of slice shapes -- lockstep with 8 or 16 waves per projection workgroup, persistent with 1, 2 or
+ *     4 resident workgroups per CU, each with the slices in the given order or largest first -- and keep
+ *     the fastest, cached per process and on disk (a text file per GPU architecture and shape set under
+ *     $CTRLALM_TUNE_DIR, else $XDG_CACHE_HOME/ctrlalm/tune, else ~/.cache/ctrlalm/tune); 2 = persistent
+ *     at the resident capacity, slices in the given order. The slice order never changes a result; the
+ *     forward workgroup's wave count changes the projection's summation order (the persistent form uses 8).
  *   chosen: if non-NULL, receives the launch shape used.
- * Returns CT_ERR_DIVERGED (message names the slice) if any slice ends non-finite.
+ * Waits for the device at the end. Returns CT_ERR_DIVERGED (message names the slice) if any slice ends
+ * non-finite.
  */
 typedef struct {
     int fp_waves;          /* waves per forward-projection workgroup (8 or 16)                       */
     int largest_first;     /* 1: slices ordered by decreasing work in the batched grids              */
-    double ms_subiteration;/* timed cost of one batched subiteration (autotune only; else 0)          */
+    double ms_subiteration;/* timed cost of one batched subiteration (tuned shapes; else 0)           */
+    int persistent;        /* 1: the persistent single-launch form                                   */
+    int blocks_per_cu;     /* persistent form: resident workgroups per CU                            */
 } ct_batch_config;
 ct_status ct_rlalm_solve_batched(ct_geom *const *g, int n, const ct_rlalm_params *p, const void *const *y,
                                  const void *const *w, float *const *x, int autotune, ct_batch_config *chosen,

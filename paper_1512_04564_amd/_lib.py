@@ -59,7 +59,8 @@ class KernelTimes(ctypes.Structure):
 
 
 class BatchConfig(ctypes.Structure):
-    _fields_ = [("fp_waves", ctypes.c_int), ("largest_first", ctypes.c_int), ("ms_subiteration", ctypes.c_double)]
+    _fields_ = [("fp_waves", ctypes.c_int), ("largest_first", ctypes.c_int), ("ms_subiteration", ctypes.c_double),
+                ("persistent", ctypes.c_int), ("blocks_per_cu", ctypes.c_int)]
 
 
 class TraceRow(ctypes.Structure):

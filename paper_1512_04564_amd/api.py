@@ -227,10 +227,12 @@ def rlalm_status(g: Geometry) -> None:
     check(g._lib.ct_rlalm_status(g.handle))
 
 
-def rlalm_solve_batched(geoms, p: Params, ys, ws, xs, *, autotune: bool = False, stream=None) -> dict:
-    """Solve len(geoms) independent slices in lockstep (one launch per kernel per subiteration for all
-    slices, one graph replay per iteration), in place on each ``xs[i]``. Returns the launch shape used:
-    ``{"fp_waves", "largest_first", "ms_subiteration"}``."""
+def rlalm_solve_batched(geoms, p: Params, ys, ws, xs, *, autotune=False, stream=None) -> dict:
+    """Solve len(geoms) independent slices in place on each ``xs[i]`` (ct_rlalm_solve_batched).
+    ``autotune``: False / 0 lockstep default shape, True / 1 tuned (lockstep or persistent), 2 or
+    "persistent" the single persistent launch. Returns the launch shape used:
+    ``{"fp_waves", "largest_first", "ms_subiteration", "persistent", "blocks_per_cu"}``."""
+    autotune = 2 if autotune == "persistent" else int(autotune)
     n = len(geoms)
     if not (len(ys) == len(ws) == len(xs) == n) or n == 0:
         raise ValueError("geoms, ys, ws and xs must be non-empty and of equal length")
@@ -241,9 +243,10 @@ def rlalm_solve_batched(geoms, p: Params, ys, ws, xs, *, autotune: bool = False,
     wp = VP(*[_ptr(w, shape=(g.nviews, g.nb), name="w", dtype=g.sino_dtype) for g, w in zip(geoms, ws)])
     xp = VP(*[_ptr(x, shape=g.img_shape, name="x") for g, x in zip(geoms, xs)])
     cfg = _lib.BatchConfig()
-    check(geoms[0]._lib.ct_rlalm_solve_batched(hs, n, ctypes.byref(cp), yp, wp, xp, int(autotune), ctypes.byref(cfg),
+    check(geoms[0]._lib.ct_rlalm_solve_batched(hs, n, ctypes.byref(cp), yp, wp, xp, autotune, ctypes.byref(cfg),
                                                _stream_handle(stream)))
-    return dict(fp_waves=cfg.fp_waves, largest_first=bool(cfg.largest_first), ms_subiteration=cfg.ms_subiteration)
+    return dict(fp_waves=cfg.fp_waves, largest_first=bool(cfg.largest_first), ms_subiteration=cfg.ms_subiteration,
+                persistent=bool(cfg.persistent), blocks_per_cu=cfg.blocks_per_cu)
 
 
 def rlalm_prepare(g: Geometry, p: Params, w: torch.Tensor, dl: torch.Tensor, kappa: torch.Tensor | None = None,

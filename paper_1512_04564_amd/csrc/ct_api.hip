@@ -5,9 +5,13 @@
 // x-step of subiteration t+1). An outer iteration (M subiterations) is captured once as a hipGraph and
 // replayed; the subiteration index is read from a device counter that a one-thread kernel at the end of
 // the graph advances, so one captured graph serves every iteration.
+#include <sys/stat.h>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -717,8 +721,55 @@ ct_status tune_batch(const std::vector<Ctx> &cs, hipStream_t s, ct_batch_config 
     ct_status st = CT_OK;
     best->ms_subiteration = 1e30;
     const int M = cs[0].M;
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
+    const int max_bpc = persistent_blocks_per_cu(cs[0].dtype);
+    std::vector<int> ord(cs[0].order);
+    int *dorder = nullptr;
+    if (cus > 0 && max_bpc > 0) {
+        st = dev_alloc(&dorder, ord.size());
+        if (st == CT_OK && hipMemcpy(dorder, ord.data(), ord.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+            st = fail(CT_ERR_HIP, "batch tuning: order upload failed");
+    }
     for (int lf = 0; lf < 2 && st == CT_OK; ++lf) {
         if (lf == 1 && largest == given) continue;
+        // the persistent launch: 1, 2 or 4 resident workgroups per CU (within the occupancy limit)
+        for (int bpc : {1, 2, 4}) {
+            if (!dorder || bpc > max_bpc || st != CT_OK) continue;
+            int nfp = 0, nbp = 0;
+            std::vector<SliceDev> tab = slice_table(cs, lf ? largest : given, 8, &nfp, &nbp);
+            SliceDev *dtab = nullptr;
+            st = upload_table(tab, &dtab, s);
+            if (st != CT_OK) break;
+            const BatchUpdate u = batch_update(cs[0], 0);
+            int *state = cs[0].g->ws.tbase;
+            hipError_t e = launch_batch_persistent(dtab, n, nfp, nbp, dorder, M, 0, 2, 1, u, state, bpc * cus,
+                                                   cs[0].dtype, s);
+            if (e == hipSuccess) e = hipEventRecord(e0, s);
+            if (e == hipSuccess)
+                e = launch_batch_persistent(dtab, n, nfp, nbp, dorder, M, 0, kReps, 1, u, state, bpc * cus,
+                                            cs[0].dtype, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            int flag = 0;
+            if (e == hipSuccess) e = hipMemcpy(&flag, state + 3, sizeof(int), hipMemcpyDeviceToHost);
+            (void)hipFree(dtab);
+            if (e != hipSuccess) {
+                st = fail(CT_ERR_HIP, std::string("batch tuning: ") + hipGetErrorString(e));
+                break;
+            }
+            const double per = ms / kReps;
+            if (flag == 0 && per < best->ms_subiteration) {
+                best->ms_subiteration = per;
+                best->fp_waves = 8;
+                best->largest_first = lf;
+                best->persistent = 1;
+                best->blocks_per_cu = bpc;
+            }
+        }
         for (int waves : {16, 8}) {
             int nfp = 0, nbp = 0;
             std::vector<SliceDev> tab = slice_table(cs, lf ? largest : given, waves, &nfp, &nbp);
@@ -748,12 +799,146 @@ ct_status tune_batch(const std::vector<Ctx> &cs, hipStream_t s, ct_batch_config 
                 best->ms_subiteration = per;
                 best->fp_waves = waves;
                 best->largest_first = lf;
+                best->persistent = 0;
+                best->blocks_per_cu = 0;
             }
         }
     }
+    if (dorder) (void)hipFree(dorder);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return st;
+}
+
+// On-disk cache of tuned launch shapes: one text file per (device architecture, slice-shape set) under
+// $CTRLALM_TUNE_DIR, else $XDG_CACHE_HOME/ctrlalm/tune, else ~/.cache/ctrlalm/tune. Empty path: no cache.
+std::string tune_file(int device, const BatchKey &key)
+{
+    std::string dir;
+    if (const char *e = std::getenv("CTRLALM_TUNE_DIR")) dir = e;
+    else if (const char *x = std::getenv("XDG_CACHE_HOME")) dir = std::string(x) + "/ctrlalm/tune";
+    else if (const char *h = std::getenv("HOME")) dir = std::string(h) + "/.cache/ctrlalm/tune";
+    if (dir.empty()) return std::string();
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return std::string();
+    std::string arch(prop.gcnArchName);
+    arch = arch.substr(0, arch.find(':'));
+    unsigned long long h = 1469598103934665603ull;   // FNV-1a of the shape set
+    for (int v : key.shape) {
+        h ^= (unsigned long long)(unsigned)v;
+        h *= 1099511628211ull;
+    }
+    char name[64];
+    std::snprintf(name, sizeof(name), "/%016llx.txt", h);
+    return dir + "/" + arch + name;
+}
+
+bool read_tuned(const std::string &path, ct_batch_config *cfg, int max_bpc)
+{
+    FILE *f = std::fopen(path.c_str(), "r");
+    if (!f) return false;
+    ct_batch_config c{};
+    const int got = std::fscanf(f, "fp_waves %d largest_first %d persistent %d blocks_per_cu %d ms %lf", &c.fp_waves,
+                                &c.largest_first, &c.persistent, &c.blocks_per_cu, &c.ms_subiteration);
+    std::fclose(f);
+    const bool ok = got == 5 && (c.fp_waves == 8 || c.fp_waves == 16) && (c.largest_first == 0 || c.largest_first == 1) &&
+                    (c.persistent == 0 || (c.persistent == 1 && c.blocks_per_cu >= 1 && c.blocks_per_cu <= max_bpc));
+    if (ok) *cfg = c;
+    return ok;
+}
+
+void write_tuned(const std::string &path, const ct_batch_config &c)
+{
+    // create the directories on the way (best effort: without them the cache is simply not written)
+    for (size_t pos = path.find('/', 1); pos != std::string::npos; pos = path.find('/', pos + 1))
+        (void)mkdir(path.substr(0, pos).c_str(), 0755);
+    const std::string tmp = path + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "fp_waves %d largest_first %d persistent %d blocks_per_cu %d ms %.6f\n", c.fp_waves,
+                 c.largest_first, c.persistent, c.blocks_per_cu, c.ms_subiteration);
+    std::fclose(f);
+    (void)std::rename(tmp.c_str(), path.c_str());
+}
+
+// The batched solve as one captured graph: every slice's initialisation and first x-step, then one
+// persistent launch of all nsub subiterations. Waits for the device at the end (finiteness and the
+// barrier's error flag).
+template <typename Init>
+ct_status persistent_batched(ct_geom *const *gs, int n, const ct_rlalm_params *p, float *const *x,
+                             const std::vector<Ctx> &cs, const ct_batch_config &cfg, int cus, Init init_all,
+                             hipStream_t s)
+{
+    const Workspace &W0 = gs[0]->ws;
+    const long long nsub = (long long)p->niters * cs[0].M;
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    if (cfg.largest_first)
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            auto work = [&](int i) { return (double)gs[i]->desc.nx * gs[i]->desc.ny * cs[(size_t)i].nvm; };
+            return work(a) > work(b);
+        });
+    int nfp = 0, nbp = 0;
+    std::vector<SliceDev> tab = slice_table(cs, order, 8, &nfp, &nbp);
+    SliceDev *dtab = nullptr;
+    CT_TRY(upload_table(tab, &dtab, s));
+    int *dorder = nullptr;
+    ct_status st = dev_alloc(&dorder, cs[0].order.size());
+    if (st == CT_OK &&
+        hipMemcpy(dorder, cs[0].order.data(), cs[0].order.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+        st = fail(CT_ERR_HIP, "order upload failed");
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (st == CT_OK && hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+        st = fail(CT_ERR_HIP, "capture stream");
+    if (st == CT_OK) {
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) st = fail(CT_ERR_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+        if (st == CT_OK) st = init_all(cap);
+        if (st == CT_OK) {
+            e = launch_batch_persistent(dtab, n, nfp, nbp, dorder, cs[0].M, 0, nsub, 1, batch_update(cs[0], 0), W0.tbase,
+                                        cfg.blocks_per_cu * cus, cs[0].dtype, cap);
+            if (e != hipSuccess) st = fail(CT_ERR_HIP, std::string("persistent launch: ") + hipGetErrorString(e));
+        }
+        e = hipStreamEndCapture(cap, &graph);
+        if (st == CT_OK && e != hipSuccess) st = fail(CT_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        if (st == CT_OK && (e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) != hipSuccess)
+            st = fail(CT_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        if (st == CT_OK && (e = hipGraphLaunch(exec, s)) != hipSuccess)
+            st = fail(CT_ERR_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+    }
+    // x^(nsub) is the input of the last projection: buffer B (index 1) after an odd number of
+    // subiterations' swaps from B, A otherwise (nothing ran: A)
+    const int fin = nsub > 0 ? (int)((1 + nsub - 1) & 1) : 0;
+    std::vector<double> host(3 * (size_t)n);
+    int flag = 0;
+    for (int i = 0; i < n && st == CT_OK; ++i) {
+        ct_geom *g = gs[i];
+        Workspace &W = g->ws;
+        hipError_t e = hipMemcpyAsync(x[i], fin ? W.xb : W.xa, W.npix * sizeof(float), hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = launch_trace_reduce(x[i], nullptr, W.gv, W.h, g->desc.nx, g->desc.ny, (float)g->desc.dx,
+                                    (float)g->desc.dy, 0.f, W.red, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&host[3 * (size_t)i], W.red, 3 * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) st = fail(CT_ERR_HIP, std::string("batched result: ") + hipGetErrorString(e));
+    }
+    if (st == CT_OK && hipMemcpyAsync(&flag, W0.tbase + 3, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
+        st = fail(CT_ERR_HIP, "barrier flag readback");
+    const hipError_t es = hipStreamSynchronize(s);
+    if (st == CT_OK && es != hipSuccess) st = fail(CT_ERR_HIP, std::string("batched solve: ") + hipGetErrorString(es));
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (dorder) (void)hipFree(dorder);
+    (void)hipFree(dtab);
+    if (st != CT_OK) return st;
+    if (flag) return fail(CT_ERR_HIP, "persistent batched launch: a grid barrier wait gave up (workgroups not resident)");
+    for (int i = 0; i < n; ++i)
+        if (host[3 * (size_t)i + 2] != 0.0)
+            return fail(CT_ERR_DIVERGED, "non-finite values in the final state of slice " + std::to_string(i));
+    return CT_OK;
 }
 
 }  // namespace
@@ -1051,7 +1236,7 @@ ct_status ct_rlalm_solve_batched(ct_geom *const *gs, int n, const ct_rlalm_param
     if (!gs || !y || !w || !x || n < 1) return fail(CT_ERR_INVALID_ARG, "NULL argument or n < 1");
     CT_TRY(check_params(p));
     if (p->time_kernels) return fail(CT_ERR_UNSUPPORTED, "time_kernels is not available in the batched solve");
-    if (autotune != 0 && autotune != 1) return fail(CT_ERR_INVALID_ARG, "autotune must be 0 or 1");
+    if (autotune < 0 || autotune > 2) return fail(CT_ERR_INVALID_ARG, "autotune must be 0, 1 or 2");
     for (int i = 0; i < n; ++i) {
         if (!gs[i] || !y[i] || !w[i] || !x[i]) return fail(CT_ERR_INVALID_ARG, "NULL slice argument");
         if (gs[i]->desc.nsubsets != gs[0]->desc.nsubsets || gs[i]->desc.storage != gs[0]->desc.storage)
@@ -1082,8 +1267,11 @@ ct_status ct_rlalm_solve_batched(ct_geom *const *gs, int n, const ct_rlalm_param
     // every slice reads the rho table and subiteration counter of slice 0
     const Workspace &W0 = gs[0]->ws;
 
-    ct_batch_config cfg{16, 0, 0.0};
-    if (autotune) {
+    ct_batch_config cfg{16, 0, 0.0, 0, 0};
+    int dev = 0, cus = 0;
+    CT_HIP_CHECK(hipGetDevice(&dev));
+    CT_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (autotune == 1) {
         BatchKey key{gs[0]->device, {}};
         for (int i = 0; i < n; ++i) {
             const ct_geom_desc &d = gs[i]->desc;
@@ -1098,30 +1286,44 @@ ct_status ct_rlalm_solve_batched(ct_geom *const *gs, int n, const ct_rlalm_param
                 have = true;
             }
         }
+        const std::string path = tune_file(dev, key);
+        if (!have && !path.empty()) have = read_tuned(path, &cfg, persistent_blocks_per_cu(cs[0].dtype));
         if (!have) {
             CT_TRY(tune_batch(cs, s, &cfg));
-            std::lock_guard<std::mutex> lk(g_tune_mu);
-            g_tune_cache[key] = cfg;
+            if (!path.empty()) write_tuned(path, cfg);
         }
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = cfg;
+    } else if (autotune == 2) {
+        const int bpc = persistent_blocks_per_cu(cs[0].dtype);
+        if (bpc < 1) return fail(CT_ERR_UNSUPPORTED, "the persistent batched kernel cannot be resident on this device");
+        cfg = ct_batch_config{8, 0, 0.0, 1, bpc};
     }
     if (chosen) *chosen = cfg;
 
-    // initial state of every slice, then the x-step of subiteration 0 (A -> B)
-    for (int i = 0; i < n; ++i) {
-        const Ctx &c = cs[(size_t)i];
-        CT_TRY(do_init(c, x[i], p->start == 1, s));
-        Workspace &W = c.g->ws;
-        UpdateArgs U = make_update(c);
-        U.rho = W0.rho;
-        U.tbase = W0.tbase;
-        U.x = W.xa;
-        U.x_next = W.xb;
-        U.xc_next = proj_copy(W, c.dtype, 0);
-        U.xT_next = W.xtb;
-        U.tofs = 0;
-        CT_HIP_CHECK(launch_set_counter(W0.tbase, 0, s));
-        CT_HIP_CHECK(launch_back_update(bp_launch(c.g->dev, nullptr, 0, 1, 0, nullptr, U), BP_XSTEP, c.dtype, c.dtype, s));
-    }
+    // initial state of every slice, then the x-step of subiteration 0 (A -> B): eager for the lockstep
+    // launches, part of the one captured graph for the persistent launch
+    auto init_all = [&](hipStream_t st) -> ct_status {
+        for (int i = 0; i < n; ++i) {
+            const Ctx &c = cs[(size_t)i];
+            CT_TRY(do_init(c, x[i], p->start == 1, st));
+            Workspace &W = c.g->ws;
+            UpdateArgs U = make_update(c);
+            U.rho = W0.rho;
+            U.tbase = W0.tbase;
+            U.x = W.xa;
+            U.x_next = W.xb;
+            U.xc_next = proj_copy(W, c.dtype, 0);
+            U.xT_next = W.xtb;
+            U.tofs = 0;
+            CT_HIP_CHECK(launch_set_counter(W0.tbase, 0, st));
+            CT_HIP_CHECK(launch_back_update(bp_launch(c.g->dev, nullptr, 0, 1, 0, nullptr, U), BP_XSTEP, c.dtype, c.dtype,
+                                            st));
+        }
+        return CT_OK;
+    };
+    if (cfg.persistent) return persistent_batched(gs, n, p, x, cs, cfg, cus, init_all, s);
+    CT_TRY(init_all(s));
     std::vector<int> order(n);
     std::iota(order.begin(), order.end(), 0);
     if (cfg.largest_first)

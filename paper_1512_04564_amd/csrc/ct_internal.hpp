@@ -237,6 +237,14 @@ hipError_t launch_forward_batch(const SliceDev *tab, int ns, int nwg_fp, int m, 
                                 hipStream_t s);
 hipError_t launch_update_batch(const SliceDev *tab, int ns, int nwg_bp, int m, int par, const BatchUpdate &u,
                                int dtype, hipStream_t s);
+// The whole batched iteration as one persistent launch of `blocks` workgroups (at most the resident
+// capacity: persistent_blocks_per_cu per CU), subiterations t0 .. t0 + nsub - 1 with subsets order[t % M],
+// images from buffer par0; state: the 4-int barrier state (zeroed by the launch sequence; state[3] != 0
+// afterwards when a barrier wait gave up).
+hipError_t launch_batch_persistent(const SliceDev *tab, int ns, int nwg_fp, int nwg_bp, const int *order, int M,
+                                   long long t0, long long nsub, int par0, const BatchUpdate &u, int *state,
+                                   int blocks, int dtype, hipStream_t s);
+int persistent_blocks_per_cu(int dtype);
 int forward_workgroups(const GeomDev &G, int nv, int fp_waves, bool split);   // per-launch workgroup count
 // Whether the residual projection of nv views (of nviews) splits each block's lines over two workgroups:
 // it can (float32, both planes fit the residual block) and its launch alone would underfill the device.

@@ -28,6 +28,7 @@
 // Finiteness checks live in ct_reduce.hip, which keeps them.
 #include <type_traits>
 
+#include "ct_grid_barrier.hpp"
 #include "ct_internal.hpp"
 
 namespace ct {
@@ -374,13 +375,12 @@ __device__ __forceinline__ int find_slice(const SliceDev *__restrict__ tab, int 
     return s;
 }
 
-// Batched forward projection of subset m with the residual epilogue, every slice reading image buffer par.
+// Batched forward projection of subset m with the residual epilogue, every slice reading image buffer par:
+// the work of workgroup b of the batched grid.
 template <int WAVES, typename T>
-__global__ __launch_bounds__(FP_BINS *WAVES) void k_forward_batch(const SliceDev *__restrict__ tab, int ns, int m,
-                                                                   int par)
+__device__ __forceinline__ void forward_item(const SliceDev *__restrict__ tab, int ns, int m, int par, int b, float *win)
 {
-    __shared__ float win[WAVES * (FP_WIN + 4)];
-    const int s = find_slice<true>(tab, ns, blockIdx.x);
+    const int s = find_slice<true>(tab, ns, b);
     const SliceDev &S = tab[s];
     FpLaunch a;
     a.G = S.G;
@@ -394,13 +394,21 @@ __global__ __launch_bounds__(FP_BINS *WAVES) void k_forward_batch(const SliceDev
     a.vstride = S.M;
     a.nv = S.nvm;
     a.mscale = (float)S.M;
-    const int local = blockIdx.x - S.fp_begin;
+    const int local = b - S.fp_begin;
     const int nbx = (S.G.nb + FP_BINS - 1) / FP_BINS, per_view = S.r2 ? 2 * nbx : nbx;
     const int rem = local % per_view;
     if (S.r2)   // split: float32 residual planes
         fp_body<FP_RESIDUAL, false, WAVES, T, T, float>(a, rem % nbx, local / per_view, rem / nbx, win);
     else
         fp_body<FP_RESIDUAL, false, WAVES, T, T, T>(a, rem % nbx, local / per_view, -1, win);
+}
+
+template <int WAVES, typename T>
+__global__ __launch_bounds__(FP_BINS *WAVES) void k_forward_batch(const SliceDev *__restrict__ tab, int ns, int m,
+                                                                   int par)
+{
+    __shared__ float win[WAVES * (FP_WIN + 4)];
+    forward_item<WAVES, T>(tab, ns, m, par, blockIdx.x, win);
 }
 
 // Back-projection of one pixel for one view: bins whose interval meets the pixel [e0, e0 + 1] on line
@@ -864,13 +872,12 @@ __global__ __launch_bounds__(2 * BP_TX *BP_TY) __attribute__((amdgpu_waves_per_e
 }
 
 // Batched fused back-projection / relaxed update of subset m: every slice reads image buffer par and
-// its residual block, and writes image buffer par ^ 1 (and its copies).
+// its residual block, and writes image buffer par ^ 1 (and its copies). The work of workgroup b.
 template <typename T>
-__global__ __launch_bounds__(2 * BP_TX *BP_TY) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_update_batch(const SliceDev *__restrict__ tab, int ns, int m,
-                                                                    int par, BatchUpdate u)
+__device__ __forceinline__ void update_item(const SliceDev *__restrict__ tab, int ns, int m, int par,
+                                            const BatchUpdate &u, int b, BpShared &sh)
 {
-    __shared__ BpShared sh;
-    const int s = find_slice<false>(tab, ns, blockIdx.x);
+    const int s = find_slice<false>(tab, ns, b);
     const SliceDev &S = tab[s];
     BpLaunch a;
     a.G = S.G;
@@ -897,7 +904,7 @@ __global__ __launch_bounds__(2 * BP_TX *BP_TY) __attribute__((amdgpu_waves_per_e
     a.U.beta_ax = u.beta_ax;
     a.U.beta_dg = u.beta_dg;
     a.U.huber = u.huber;
-    const int local = blockIdx.x - S.bp_begin;
+    const int local = b - S.bp_begin;
     const int tilesx = (S.G.nx + BP_TX - 1) / BP_TX;
     if constexpr (std::is_same<T, float>::value) {
         bp_body<BP_FULL, float, float, 2>(a, local % tilesx, local / tilesx, sh);
@@ -905,6 +912,81 @@ __global__ __launch_bounds__(2 * BP_TX *BP_TY) __attribute__((amdgpu_waves_per_e
         if (S.r2) bp_body<BP_FULL, float, T, 1>(a, local % tilesx, local / tilesx, sh);
         else bp_body<BP_FULL, T, T, 0>(a, local % tilesx, local / tilesx, sh);
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(2 * BP_TX *BP_TY) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_update_batch(const SliceDev *__restrict__ tab, int ns, int m,
+                                                                    int par, BatchUpdate u)
+{
+    __shared__ BpShared sh;
+    update_item<T>(tab, ns, m, par, u, blockIdx.x, sh);
+}
+
+// Memory operations of the grid barrier in a kernel: the workgroup's first thread arrives and waits with
+// agent-scope atomics and fences (the release fence writes this XCD's L2 back, the acquire fence drops
+// stale lines, so the next phase sees every workgroup's results on every XCD); the outcome reaches the
+// other threads through LDS.
+struct DevBarrierOps {
+    int *flag;
+    __device__ void block_sync() { __syncthreads(); }
+    __device__ bool leader() { return threadIdx.x == 0; }
+    __device__ int load(int *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+    __device__ int load_acquire(int *p) { return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT); }
+    __device__ void store(int *p, int v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+    __device__ void store_release(int *p, int v) { __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT); }
+    __device__ int fetch_add(int *p, int v)
+    {
+        return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ void release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+    __device__ void acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+    __device__ void pause() { __builtin_amdgcn_s_sleep(2); }
+    __device__ void set_block_flag(int v) { *flag = v; }
+    __device__ int block_flag() { return *flag; }
+};
+
+union PersistentShared {
+    BpShared bp;
+    float win[8 * (FP_WIN + 4)];
+};
+
+// The whole batched iteration in one launch: subiterations t0 .. t0 + nsub - 1, each a forward phase over
+// the batched forward grid's nwg_fp work items and an update phase over the nwg_bp update tiles, the items
+// taken by the resident workgroups in strides of the grid, with a grid barrier after each phase. The
+// forward items run the 8-wave body (the workgroup is the update's 512 threads). Images ping-pong from
+// buffer par0 at t0. state: 4 ints, zero at launch (barrier arrivals, generation, error flag in 1..3).
+template <typename T>
+__global__ __launch_bounds__(2 * BP_TX *BP_TY) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_batch_persistent(
+    const SliceDev *__restrict__ tab, int ns, int nwg_fp, int nwg_bp, const int *__restrict__ order, int M, long long t0,
+    long long nsub, int par0, BatchUpdate u, int *state, unsigned spin_limit)
+{
+    __shared__ PersistentShared sh;
+    __shared__ int flag;
+    DevBarrierOps ops{&flag};
+    const int nblk = (int)gridDim.x;
+    u.tbase = nullptr;   // rho index = tofs = t
+    for (long long k = 0; k < nsub; ++k) {
+        const long long t = t0 + k;
+        const int m = order[(int)(t % M)];
+        const int par = (par0 + (int)(k & 1)) & 1;
+        for (int b = (int)blockIdx.x; b < nwg_fp; b += nblk) {
+            forward_item<8, T>(tab, ns, m, par, b, sh.win);
+            __syncthreads();
+        }
+        if (!grid_barrier(ops, state, nblk, spin_limit)) return;
+        u.tofs = t;
+        for (int b = (int)blockIdx.x; b < nwg_bp; b += nblk) {
+            update_item<T>(tab, ns, m, par, u, b, sh.bp);
+            __syncthreads();
+        }
+        if (!grid_barrier(ops, state, nblk, spin_limit)) return;
+    }
+}
+
+__global__ void k_fill_int(int *p, int n, int v)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) p[i] = v;
 }
 
 __global__ void k_transpose(const float *__restrict__ x, float *__restrict__ xT, int nx, int ny)
@@ -1111,6 +1193,35 @@ hipError_t launch_update_batch(const SliceDev *tab, int ns, int nwg_bp, int m, i
     else if (dtype == CT_F16) hipLaunchKernelGGL(k_update_batch<_Float16>, grid, block, 0, s, tab, ns, m, par, u);
     else if (dtype == CT_BF16) hipLaunchKernelGGL(k_update_batch<__bf16>, grid, block, 0, s, tab, ns, m, par, u);
     else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+int persistent_blocks_per_cu(int dtype)
+{
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    if (dtype == CT_F32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_persistent<float>, 2 * BP_TX * BP_TY, 0);
+    else if (dtype == CT_F16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_persistent<_Float16>, 2 * BP_TX * BP_TY, 0);
+    else if (dtype == CT_BF16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_persistent<__bf16>, 2 * BP_TX * BP_TY, 0);
+    return e == hipSuccess ? n : 0;
+}
+
+hipError_t launch_batch_persistent(const SliceDev *tab, int ns, int nwg_fp, int nwg_bp, const int *order, int M,
+                                   long long t0, long long nsub, int par0, const BatchUpdate &u, int *state,
+                                   int blocks, int dtype, hipStream_t s)
+{
+    if (ns <= 0 || nsub <= 0) return hipSuccess;
+    if (blocks < 1) return hipErrorInvalidValue;
+    constexpr unsigned kSpinLimit = 1u << 20;   // polls of about 50 ns: a waiting workgroup gives up after ~50 ms
+    const dim3 grid(blocks), block(2 * BP_TX * BP_TY);
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, state, 4, 0);
+#define CT_PB(T) hipLaunchKernelGGL(k_batch_persistent<T>, grid, block, 0, s, tab, ns, nwg_fp, nwg_bp, order, M, t0, nsub, \
+                                    par0, u, state, kSpinLimit)
+    if (dtype == CT_F32) CT_PB(float);
+    else if (dtype == CT_F16) CT_PB(_Float16);
+    else if (dtype == CT_BF16) CT_PB(__bf16);
+    else return hipErrorInvalidValue;
+#undef CT_PB
     return hipGetLastError();
 }
 

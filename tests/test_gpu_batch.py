@@ -25,7 +25,7 @@ import pytest
 import oracle
 from paper_1512_04564_amd import synth
 
-from gpu_util import image_parity, say, to_dev, to_np
+from gpu_util import hu_rmsd, image_parity, say, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -144,3 +144,64 @@ def test_batched_argument_errors(api):
     with pytest.raises(api.CtError) as ei:
         api.rlalm_solve_batched([Ga], api.Params(niters=1, time_kernels=True), [ya], [ya], [xa])
     assert ei.value.status == 4
+
+
+@pytest.mark.parametrize("M,niters", [(10, 3), (5, 3)])
+def test_persistent_launch_matches_lockstep_and_oracle(api, M, niters):
+    """The single persistent launch (grid barriers between the phases, 8-wave forward workgroups) against
+    the lockstep launches and the oracle; M odd gives an odd number of subiterations."""
+    import torch
+    geoms = small_classes(M)
+    scans = [synth.noisy_scan(g, 80 + i) for i, g in enumerate(geoms)]
+    p = api.Params(alpha=1.999, niters=niters, subset_order="bitrev", start="zero")
+    ys = [to_dev(s.y) for s in scans]
+    ws = [to_dev(s.w) for s in scans]
+    xp = [torch.zeros((g.ny, g.nx), device="cuda:0") for g in geoms]
+    cfg = api.rlalm_solve_batched([api.Geometry(g) for g in geoms], p, ys, ws, xp, autotune="persistent")
+    say(f"  persistent: {cfg}")
+    assert cfg["persistent"] and cfg["blocks_per_cu"] >= 1 and cfg["fp_waves"] == 8
+    xl = [torch.zeros((g.ny, g.nx), device="cuda:0") for g in geoms]
+    api.rlalm_solve_batched([api.Geometry(g) for g in geoms], p, ys, ws, xl)
+    torch.cuda.synchronize()
+    for i, g in enumerate(geoms):
+        d = hu_rmsd(to_np(xp[i]), to_np(xl[i]))
+        say(f"  slice {i} ({g.nx}^2): RMSD(persistent, lockstep) = {d:.2e} HU")
+        assert d <= 0.01
+        po = oracle.params(alpha=1.999, niters=niters, nsubsets=M, subset_order="bitrev")
+        xo, _, _ = oracle.rlalm_solve(g, po, scans[i].y.astype(np.float64), scans[i].w.astype(np.float64),
+                                      np.zeros((g.ny, g.nx)))
+        image_parity(to_np(xp[i]), xo, g, tag=f"persistent slice {i} ({g.nx}^2)")
+
+
+def test_persistent_full_size_classes_against_oracle(api):
+    """The three full-size classes in one persistent launch, 20 unrelaxed iterations at 41 subsets."""
+    import torch
+    geoms = list(synth.BATCH_CLASSES)
+    scans = [synth.noisy_scan(g, 300 + i, truth=False) for i, g in enumerate(geoms)]
+    xs = [torch.zeros((g.ny, g.nx), device="cuda:0") for g in geoms]
+    p = api.Params(alpha=1.0, niters=20, subset_order="bitrev", start="zero")
+    api.rlalm_solve_batched([api.Geometry(g) for g in geoms], p, [to_dev(s.y) for s in scans],
+                            [to_dev(s.w) for s in scans], xs, autotune="persistent")
+    for i, g in enumerate(geoms):
+        po = oracle.params(alpha=1.0, niters=20, nsubsets=g.nsubsets, subset_order="bitrev")
+        xo, _, _ = oracle.rlalm_solve(g, po, scans[i].y.astype(np.float64), scans[i].w.astype(np.float64),
+                                      np.zeros((g.ny, g.nx)))
+        image_parity(to_np(xs[i]), xo, g, tag=f"persistent slice {i} ({g.nx}^2, {g.nviews} views)")
+
+
+def test_tuned_shape_is_cached_on_disk(api, tmp_path, monkeypatch):
+    """autotune = 1 writes the chosen shape to the on-disk cache, one text file per GPU architecture and set
+    of slice shapes."""
+    import torch
+    monkeypatch.setenv("CTRLALM_TUNE_DIR", str(tmp_path))
+    geoms = small_classes(10)[:2]
+    scans = [synth.noisy_scan(g, 90 + i, truth=False) for i, g in enumerate(geoms)]
+    p = api.Params(alpha=1.999, niters=1, subset_order="bitrev", start="zero")
+    xs = [torch.zeros((g.ny, g.nx), device="cuda:0") for g in geoms]
+    cfg = api.rlalm_solve_batched([api.Geometry(g) for g in geoms], p, [to_dev(s.y) for s in scans],
+                                  [to_dev(s.w) for s in scans], xs, autotune=True)
+    files = list(tmp_path.rglob("*.txt"))
+    say(f"  tuned {cfg}; cache files {[str(f.relative_to(tmp_path)) for f in files]}")
+    assert len(files) == 1 and files[0].parent.name.startswith("gfx")
+    text = files[0].read_text()
+    assert f"persistent {int(cfg['persistent'])}" in text and f"fp_waves {cfg['fp_waves']}" in text
