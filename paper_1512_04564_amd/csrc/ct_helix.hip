@@ -4,9 +4,15 @@
 // Kernels (per-thread arithmetic in ct_helix_body.hpp):
 //   k_hfp     forward projection of a view block: workgroup = (64 bins, HX_RB rows, view); its HX_FW waves
 //             take interleaved planes, lanes are bins; the waves' partial sums are added in LDS in a fixed
-//             order; the epilogue writes A x, the weighted residual M w (A x - y), or w (A 1).
-//   k_hbp     gather back-projection, no atomics: workgroup = a 4 x 4 voxel column tile x 64 voxels in z,
-//             each thread HX_ZG consecutive voxels of one column; writes or accumulates A' r.
+//             order; the epilogue writes A x, the weighted residual M w (A x - y), or w (A 1), the last two
+//             optionally prescaled for the back-projector (hx_prescale).
+//   k_hbp     gather back-projection, no atomics: a wave is an 8 x 8 tile of voxel columns, every lane the
+//             same HX_ZG voxels in z of its column, so that the lanes of a wave meet the same few detector
+//             rows and neighbouring bins of each view (a few cache lines per load) and enter and leave the
+//             cone together; the 4 waves of a workgroup take 4 consecutive z groups of the tile. Workgroups
+//             are ordered so that each XCD takes a contiguous band of tiles (its L2 then holds the detector
+//             region that band projects to). Writes or accumulates A' r from the prescaled residual.
+//   k_hprescale  r' = scale secphi r for a plain sinogram handed to the back-projector.
 //   k_hupd    per voxel: the dual updates g+, h+ of subiteration t, then the clipped x-step of subiteration
 //             t + 1 with the 26-neighbour regularizer gradient and Huber curvature; writes the new volume in
 //             both projector layouts (canonical [nz][ny][nx] for row-sweep views, per-slice transposed
@@ -46,17 +52,18 @@ enum HfpEpi { HFP_PLAIN = 0, HFP_RESIDUAL = 1, HFP_WEIGHTED_ONES = 2 };
 enum HupdMode { HUPD_CLIP = 0, HUPD_INIT = 1, HUPD_FULL = 2, HUPD_XSTEP = 3 };
 
 constexpr int HFP_THREADS = 64 * HX_FW;
-constexpr int HBP_THREADS = 256;   // 16 columns (4 x 4) x 16 groups of HX_ZG voxels
-constexpr int HBP_ZSPAN = 16 * HX_ZG;
+constexpr int HBP_THREADS = 256;   // 4 waves; a wave = 8 x 8 columns x HX_ZG voxels
+constexpr int HBP_ZSPAN = 4 * HX_ZG;
+constexpr int HBP_XCDS = 8;
 constexpr int HUPD_T = 16;         // update tile edge
 
 // Forward projection of views vstart + vi * vstride (vi = blockIdx.z). Bins blockIdx.x * 64 + lane, rows
 // blockIdx.y * HX_RB + rr. Output block out[vi][r][k]; y, w indexed by the full view v.
 __global__ __launch_bounds__(HFP_THREADS) void k_hfp(HelixDev G, const float *__restrict__ x,
                                                      const float *__restrict__ xT, size_t nvox, int vstart,
-                                                     int vstride, int epi, const float *__restrict__ y,
-                                                     const float *__restrict__ w, float mscale,
-                                                     float *__restrict__ out)
+                                                     int vstride, int epi, int prescale,
+                                                     const float *__restrict__ y, const float *__restrict__ w,
+                                                     float mscale, float *__restrict__ out)
 {
     __shared__ float part[HX_FW][HX_RB][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -82,39 +89,58 @@ __global__ __launch_bounds__(HFP_THREADS) void k_hfp(HelixDev G, const float *__
         float s = part[0][rr][ln];
 #pragma unroll
         for (int wv = 1; wv < HX_FW; ++wv) s += part[wv][rr][ln];
-        const float val = s * G.scale[(size_t)v * G.nb + kk] * G.secphi[(size_t)r * G.nb + kk];
+        const float sv = hx_prescale(G, v, r, kk);
+        const float val = s * sv;
         const size_t o = ((size_t)vi * G.nr + r) * G.nb + kk;
         const size_t src = ((size_t)v * G.nr + r) * G.nb + kk;
-        if (epi == HFP_PLAIN) out[o] = val;
-        else if (epi == HFP_RESIDUAL) out[o] = mscale * w[src] * (val - y[src]);
-        else out[o] = w[src] * val;
+        float res;
+        if (epi == HFP_PLAIN) res = val;
+        else if (epi == HFP_RESIDUAL) res = mscale * w[src] * (val - y[src]);
+        else res = w[src] * val;
+        out[o] = prescale ? res * sv : res;
     }
 }
 
-// Back-projection: blockIdx.x = 4 x 4 column tile, blockIdx.y = block of HBP_ZSPAN voxels in z. Thread
-// tid: group zg = tid & 15 of HX_ZG voxels, column c = tid >> 4 of the tile. out = A' r (accumulate:
-// out += A' r).
-__global__ __launch_bounds__(HBP_THREADS) void k_hbp(HelixDev G, const float *__restrict__ r, size_t rlen, int vstart,
+// Back-projection: blockIdx.x = 8 x 8 column tile (XCD-ordered), blockIdx.y = block of HBP_ZSPAN voxels in
+// z. Wave w takes voxels (blockIdx.y * 4 + w) * HX_ZG .. of the 64 columns; lane l is column
+// (8 ty + l / 8, 8 tx + l % 8). Rp is the prescaled residual; out = A' r (accumulate: out += A' r).
+__global__ __launch_bounds__(HBP_THREADS) void k_hbp(HelixDev G, const float *__restrict__ rp, size_t rlen, int vstart,
                                                      int vstride, int nv, float *__restrict__ out, int accumulate)
 {
-    const int tid = threadIdx.x;
-    const int zg = tid & 15, c = tid >> 4;
-    const int tiles_x = (G.nx + 3) >> 2;
-    const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
-    const int j = tx * 4 + (c & 3), i = ty * 4 + (c >> 2);
-    const int kz0 = (blockIdx.y * 16 + zg) * HX_ZG;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tiles_x = (G.nx + 7) >> 3, ntiles = tiles_x * ((G.ny + 7) >> 3);
+    // workgroups go round-robin over the XCDs: give XCD x the tiles [x n / 8, (x + 1) n / 8)
+    const int bid = blockIdx.x;
+    const int full = ntiles - ntiles % HBP_XCDS;
+    const int tile = bid < full ? (bid % HBP_XCDS) * (full / HBP_XCDS) + bid / HBP_XCDS : bid;
+    const int tx = tile % tiles_x, ty = tile / tiles_x;
+    const int j = tx * 8 + (lane & 7), i = ty * 8 + (lane >> 3);
+    const int kz0 = (blockIdx.y * 4 + wave) * HX_ZG;
     if (i >= G.ny || j >= G.nx || kz0 >= G.nz) return;   // no barrier in this kernel
     float acc[HX_ZG];
 #pragma unroll
-    for (int jz = 0; jz < HX_ZG; ++jz) acc[jz] = 0.f;
-    const Ro<float> R{r, rlen};
-    hbp_group(G, R, vstart, vstride, nv, i, j, kz0, acc);
+    for (int b = 0; b < HX_ZG; ++b) acc[b] = 0.f;
+    const Ro<float> R{rp, rlen};
+    hbp_lane(G, R, vstart, vstride, nv, i, j, kz0, acc);
 #pragma unroll
-    for (int jz = 0; jz < HX_ZG; ++jz) {
-        const int kz = kz0 + jz;
+    for (int b = 0; b < HX_ZG; ++b) {
+        const int kz = kz0 + b;
         if (kz >= G.nz) break;
         const size_t idx = ((size_t)kz * G.ny + i) * G.nx + j;
-        out[idx] = accumulate ? out[idx] + acc[jz] : acc[jz];
+        out[idx] = accumulate ? out[idx] + acc[b] : acc[b];
+    }
+}
+
+// r' = scale secphi r over the view block [nv][nr][nb] of views vstart + vi * vstride.
+__global__ __launch_bounds__(256) void k_hprescale(HelixDev G, const float *__restrict__ r, int vstart, int vstride,
+                                                   int nv, float *__restrict__ out)
+{
+    const size_t n = (size_t)nv * G.nr * G.nb;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+        const int k = (int)(e % (size_t)G.nb);
+        const size_t vr = e / (size_t)G.nb;
+        const int rr = (int)(vr % (size_t)G.nr), vi = (int)(vr / (size_t)G.nr);
+        out[e] = r[e] * hx_prescale(G, vstart + vi * vstride, rr, k);
     }
 }
 
@@ -263,12 +289,23 @@ ct_status subset_of(const ct_helix *h, int subset, int *vs, int *vst, int *nv)
     return CT_OK;
 }
 
+// prescale: write r' = scale secphi (epilogue value), the back-projector's input.
 hipError_t launch_hfp(const ct_helix *h, const float *x, const float *xT, int vs, int vst, int nv, int epi,
-                      const float *y, const float *w, float mscale, float *out, hipStream_t s)
+                      int prescale, const float *y, const float *w, float mscale, float *out, hipStream_t s)
 {
     const ct_helix_desc &d = h->desc;
     const dim3 grid((unsigned)((d.nb + 63) / 64), (unsigned)((d.nr + HX_RB - 1) / HX_RB), (unsigned)nv);
-    hipLaunchKernelGGL(k_hfp, grid, dim3(HFP_THREADS), 0, s, h->dev, x, xT, h->nvox, vs, vst, epi, y, w, mscale, out);
+    hipLaunchKernelGGL(k_hfp, grid, dim3(HFP_THREADS), 0, s, h->dev, x, xT, h->nvox, vs, vst, epi, prescale, y, w,
+                       mscale, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_hprescale(const ct_helix *h, const float *r, int vs, int vst, int nv, float *out, hipStream_t s)
+{
+    const ct_helix_desc &d = h->desc;
+    const size_t n = (size_t)nv * d.nr * d.nb;
+    const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_hprescale, dim3(std::max(blocks, 1u)), dim3(256), 0, s, h->dev, r, vs, vst, nv, out);
     return hipGetLastError();
 }
 
@@ -276,7 +313,7 @@ hipError_t launch_hbp(const ct_helix *h, const float *r, int vs, int vst, int nv
                       hipStream_t s)
 {
     const ct_helix_desc &d = h->desc;
-    const unsigned tiles = (unsigned)(((d.nx + 3) / 4) * ((d.ny + 3) / 4));
+    const unsigned tiles = (unsigned)(((d.nx + 7) / 8) * ((d.ny + 7) / 8));
     const dim3 grid(tiles, (unsigned)((d.nz + HBP_ZSPAN - 1) / HBP_ZSPAN));
     const size_t rlen = (size_t)nv * d.nr * d.nb;
     hipLaunchKernelGGL(k_hbp, grid, dim3(HBP_THREADS), 0, s, h->dev, r, rlen, vs, vst, nv, out, accumulate);
@@ -381,7 +418,7 @@ ct_status ct_helix_forward(ct_helix *h, int subset, const float *x, float *p, vo
     CT_TRY(ensure_views(h, 0));
     hipStream_t s = hs(stream);
     CT_HIP_CHECK(launch_htranspose(h, x, h->xta, s));
-    CT_HIP_CHECK(launch_hfp(h, x, h->xta, vs, vst, nv, HFP_PLAIN, nullptr, nullptr, 1.f, p, s));
+    CT_HIP_CHECK(launch_hfp(h, x, h->xta, vs, vst, nv, HFP_PLAIN, 0, nullptr, nullptr, 1.f, p, s));
     return CT_OK;
 }
 
@@ -390,7 +427,10 @@ ct_status ct_helix_back(ct_helix *h, int subset, const float *r, float *x, void 
     if (!h || !r || !x) return fail(CT_ERR_INVALID_ARG, "NULL argument");
     int vs, vst, nv;
     CT_TRY(subset_of(h, subset, &vs, &vst, &nv));
-    CT_HIP_CHECK(launch_hbp(h, r, vs, vst, nv, x, 0, hs(stream)));
+    CT_TRY(ensure_views(h, nv));
+    hipStream_t s = hs(stream);
+    CT_HIP_CHECK(launch_hprescale(h, r, vs, vst, nv, h->r, s));
+    CT_HIP_CHECK(launch_hbp(h, h->r, vs, vst, nv, x, 0, s));
     return CT_OK;
 }
 
@@ -427,7 +467,7 @@ ct_status ct_helix_solve(ct_helix *h, const ct_rlalm_params *p, const float *y, 
     // D_L = dl_scale * sum_m A_m' (w_m .* A_m 1)
     for (int m = 0; m < M; ++m) {
         // the ones pass reads no volume; zeta stands in as a valid pointer
-        CT_HIP_CHECK(launch_hfp(h, h->zeta, h->zeta, m, M, nvm, HFP_WEIGHTED_ONES, nullptr, w, 1.f, h->r, s));
+        CT_HIP_CHECK(launch_hfp(h, h->zeta, h->zeta, m, M, nvm, HFP_WEIGHTED_ONES, 1, nullptr, w, 1.f, h->r, s));
         CT_HIP_CHECK(launch_hbp(h, h->r, m, M, nvm, h->dl, m > 0, s));
     }
     if (p->dl_scale != 1.0) CT_HIP_CHECK(launch_scale(h->dl, nvox, (float)p->dl_scale, s));
@@ -435,12 +475,12 @@ ct_status ct_helix_solve(ct_helix *h, const ct_rlalm_params *p, const float *y, 
     CT_HIP_CHECK(launch_hupd(h, U, HUPD_CLIP, p->start == 1, x, 0.f, 0.f, h->xa, h->xta, s));
     if (p->init_full) {
         for (int m = 0; m < M; ++m) {
-            CT_HIP_CHECK(launch_hfp(h, h->xa, h->xta, m, M, nvm, HFP_RESIDUAL, y, w, 1.f, h->r, s));
+            CT_HIP_CHECK(launch_hfp(h, h->xa, h->xta, m, M, nvm, HFP_RESIDUAL, 1, y, w, 1.f, h->r, s));
             CT_HIP_CHECK(launch_hbp(h, h->r, m, M, nvm, h->zeta, m > 0, s));
         }
     } else {
         const int m = order[(size_t)M - 1];
-        CT_HIP_CHECK(launch_hfp(h, h->xa, h->xta, m, M, nvm, HFP_RESIDUAL, y, w, (float)M, h->r, s));
+        CT_HIP_CHECK(launch_hfp(h, h->xa, h->xta, m, M, nvm, HFP_RESIDUAL, 1, y, w, (float)M, h->r, s));
         CT_HIP_CHECK(launch_hbp(h, h->r, m, M, nvm, h->zeta, 0, s));
     }
     CT_HIP_CHECK(launch_hupd(h, U, HUPD_INIT, 0, h->xa, 0.f, 0.f, nullptr, nullptr, s));
@@ -453,7 +493,7 @@ ct_status ct_helix_solve(ct_helix *h, const ct_rlalm_params *p, const float *y, 
         std::swap(xcT, xoT);
         for (long long t = 0; t < nsub; ++t) {
             const int m = order[(size_t)(t % M)];
-            CT_HIP_CHECK(launch_hfp(h, xc, xcT, m, M, nvm, HFP_RESIDUAL, y, w, (float)M, h->r, s));
+            CT_HIP_CHECK(launch_hfp(h, xc, xcT, m, M, nvm, HFP_RESIDUAL, 1, y, w, (float)M, h->r, s));
             CT_HIP_CHECK(launch_hbp(h, h->r, m, M, nvm, h->zeta, 0, s));
             CT_HIP_CHECK(launch_hupd(h, U, HUPD_FULL, 0, xc, (float)rho_value(t, p), (float)rho_value(t + 1, p), xo,
                                      xoT, s));

@@ -86,8 +86,8 @@ __host__ __device__ inline int hx_min(int a, int b) { return a < b ? a : b; }
 // Rows per forward-projection workgroup and waves per forward workgroup; voxels per back-projection thread.
 constexpr int HX_RB = 8;
 constexpr int HX_FW = 4;
-constexpr int HX_ZG = 4;
-constexpr int HX_KC = 8;   // candidate bins per view kept in registers by the back-projector
+constexpr int HX_ZG = 8;
+constexpr int HX_KC = 4;   // candidate bins per view kept in registers by the back-projector
 
 // Centre of voxel column q on line lc (world mm) and its depth ell along the view's central ray.
 __host__ __device__ inline float column_depth(const HelixDev &G, bool row, float lc, int q, float2 cs)
@@ -154,12 +154,39 @@ __host__ __device__ inline void hfp_lane(const HelixDev &G, const Ro<float> &X, 
     }
 }
 
-// Back-projection, one thread: voxels kz0 .. kz0 + HX_ZG - 1 of column (i, j) (voxels >= nz get nothing),
-// views vstart + vi * vstride, vi < nv, reading the residual block R [nv][nr][nb]. acc[jz] += sum over
-// the views' cells of the weight times R. Candidate bins come from the inverse map at the column's two
-// edges (widened by 0.05 bin); up to HX_KC of them are kept in registers, more are re-evaluated per row.
-__host__ __device__ inline void hbp_group(const HelixDev &G, const Ro<float> &R, int vstart, int vstride, int nv, int i,
-                                          int j, int kz0, float (&acc)[HX_ZG])
+// Residual prescaling: the back-projector reads r'[v][r][k] = scale_vk secphi_rk r[v][r][k], so that its
+// inner loop carries only the transaxial and axial overlaps. The forward epilogue writes r' directly when its
+// output feeds the back-projector; a plain sinogram is prescaled by a separate pass.
+__host__ __device__ inline float hx_prescale(const HelixDev &G, int v, int r, int k)
+{
+    return G.scale[(size_t)v * G.nb + k] * G.secphi[(size_t)r * G.nb + k];
+}
+
+// Approximate reciprocal (one ulp on the device), for weights and candidate ranges.
+__host__ __device__ inline float hx_rcp(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.f / x;
+#endif
+}
+
+__host__ __device__ inline float hx_clamp01(float x) { return fminf(fmaxf(x, 0.f), 1.f); }
+
+// Back-projection, one lane: voxels kz0 .. kz0 + HX_ZG - 1 of column (i, j) (voxels >= nz are computed and
+// dropped by the caller), views vstart + vi * vstride, vi < nv, reading the prescaled residual block
+// Rp [nv][nr][nb]. acc[b] += sum over the views' cells of f_t f_a Rp.
+//
+// Per view: the candidate bins come from the inverse map at the column's two edges (widened by 0.05 bin);
+// their boundary crossings are evaluated once each in FP64 (HX_KC + 1 of them) and the first HX_KC bins'
+// transaxial weights kept in registers; a column that meets more bins (a depth close to the source, a coarse
+// detector) re-evaluates the rest per row. Along z the thread walks the rows that can meet its voxels;
+// row r spans [z_r, z_r+1] in the group's coordinates (voxel b spans [b, b+1]) and meets voxel b by
+// clamp01(z_r+1 - b) - clamp01(z_r - b): the clamps at the row's upper face are those at the next row's lower
+// face, so each (row, voxel) costs one clamp, one difference and one FMA.
+__host__ __device__ inline void hbp_lane(const HelixDev &G, const Ro<float> &Rp, int vstart, int vstride, int nv, int i,
+                                         int j, int kz0, float (&acc)[HX_ZG])
 {
     for (int vi = 0; vi < nv; ++vi) {
         const int v = vstart + vi * vstride;
@@ -171,10 +198,13 @@ __host__ __device__ inline void hbp_group(const HelixDev &G, const Ro<float> &R,
         const float2 cs = G.cs[v];
         const float ell = column_depth(G, row, lc, q, cs);
         const float zai = G.zai[v], zaf = G.zaf[v];
-        const float zg0 = (float)kz0 - zai;   // the thread's voxels span [zg0, zg0 + HX_ZG] in the view's z
+        const float zg0 = (float)kz0 - zai;   // the group's voxels span [zg0, zg0 + HX_ZG] in the view's z
+        const float hrow = ell * G.dwn;       // row height in voxels at this depth
+        const float inva = hx_rcp(hrow);
         // rows that can meet them: z_r = zaf + ell wr_r increases with r
-        const float rz0 = (zg0 - zaf) / (ell * G.dwn) - G.wr[0] / G.dwn;
-        const float rz1 = (zg0 + (float)HX_ZG - zaf) / (ell * G.dwn) - G.wr[0] / G.dwn;
+        const float rw0 = G.wr[0] / G.dwn;
+        const float rz0 = (zg0 - zaf) * inva - rw0;
+        const float rz1 = rz0 + (float)HX_ZG * inva;
         const int ra = (int)floorf(fmaxf(rz0 - 1.f, 0.f));
         const int rb = (int)floorf(fminf(rz1 + 1.f, (float)(G.nr - 1)));
         if (ra > rb) continue;
@@ -183,49 +213,55 @@ __host__ __device__ inline void hbp_group(const HelixDev &G, const Ro<float> &R,
         const double e0d = (double)q - 0.5 * (double)NQ;   // the column spans [e0, e0 + 1] (exact)
         const float e0 = (float)e0d;
         const float nlc = lc * im.y, dlc = fmaf(lc, im.w, G.dso);
-        const float t0 = fmaf(e0, im.x, nlc) / fmaf(e0, im.z, dlc);
-        const float t1 = fmaf(e0 + 1.f, im.x, nlc) / fmaf(e0 + 1.f, im.z, dlc);
+        const float t0 = fmaf(e0, im.x, nlc) * hx_rcp(fmaf(e0, im.z, dlc));
+        const float t1 = fmaf(e0 + 1.f, im.x, nlc) * hx_rcp(fmaf(e0 + 1.f, im.z, dlc));
         const float kf0 = fmaf(G.c_kf, t0, G.k0), kf1 = fmaf(G.c_kf, t1, G.k0);
         const int ka = (int)floorf(fmaxf(fminf(kf0, kf1) - 0.05f, 0.f));
         const int kb = (int)floorf(fminf(fmaxf(kf0, kf1) + 0.05f, (float)(G.nb - 1)));
         if (ka > kb) continue;
         const size_t vb = (size_t)v * (G.nb + 1);
+        // boundary crossings relative to the column's lower edge, in FP64: d_c = U_(ka+c) - e0
         float fk[HX_KC];
+        double up;
+        {
+            const double2 b = G.bnd[vb + ka];
+            up = fma(lcd, b.y, b.x) - e0d;
+        }
 #pragma unroll
         for (int c = 0; c < HX_KC; ++c) {
-            const int k = hx_min(ka + c, kb);
-            const double2 b0 = G.bnd[vb + k], b1 = G.bnd[vb + k + 1];
-            const double ua = fma(lcd, b0.y, b0.x), ub = fma(lcd, b1.y, b1.x);
-            const double lo = fmin(ua, ub), hi = fmax(ua, ub);
-            const float ov = (float)(fmin(hi, e0d + 1.0) - fmax(lo, e0d));
-            fk[c] = (ka + c <= kb && ov > 0.f && hi > lo) ? ov / (float)(hi - lo) * G.scale[(size_t)v * G.nb + k] : 0.f;
+            const double2 b = G.bnd[vb + hx_min(ka + c + 1, kb + 1)];
+            const double un = fma(lcd, b.y, b.x) - e0d;
+            const float lo = (float)fmin(up, un), hi = (float)fmax(up, un), wd = (float)fabs(un - up);
+            const float ov = fminf(hi, 1.f) - fmaxf(lo, 0.f);
+            fk[c] = (ka + c <= kb && ov > 0.f && wd > 0.f) ? ov * hx_rcp(wd) * inva : 0.f;
+            up = un;
         }
-        const float inva = 1.f / (ell * G.dwn);
         const size_t rv = (size_t)vi * G.nr * G.nb;
+        const float zoff = zaf - zg0;   // row boundaries in the group's coordinates: fmaf(ell, wr_r, zoff)
+        float cl[HX_ZG];
+        {
+            const float zl = fmaf(ell, G.wr[(size_t)ra], zoff);
+#pragma unroll
+            for (int b = 0; b < HX_ZG; ++b) cl[b] = hx_clamp01(zl - (float)b);
+        }
         for (int r = ra; r <= rb; ++r) {
-            const float zl = fmaf(ell, G.wr[(size_t)r], zaf), zh = fmaf(ell, G.wr[(size_t)r + 1], zaf);
+            const float zh = fmaf(ell, G.wr[(size_t)r + 1], zoff);
             const size_t rr = rv + (size_t)r * G.nb;
             float t = 0.f;
 #pragma unroll
-            for (int c = 0; c < HX_KC; ++c) {
-                const int k = hx_min(ka + c, kb);
-                t = fmaf(fk[c] * G.secphi[(size_t)r * G.nb + k], R[rr + k], t);
-            }
+            for (int c = 0; c < HX_KC; ++c) t = fmaf(fk[c], Rp[rr + hx_min(ka + c, kb)], t);
             for (int k = ka + HX_KC; k <= kb; ++k) {   // columns that meet more than HX_KC bins
                 const double2 b0 = G.bnd[vb + k], b1 = G.bnd[vb + k + 1];
-                const double ua = fma(lcd, b0.y, b0.x), ub = fma(lcd, b1.y, b1.x);
-                const double lo = fmin(ua, ub), hi = fmax(ua, ub);
-                const float ov = (float)(fmin(hi, e0d + 1.0) - fmax(lo, e0d));
-                if (ov > 0.f && hi > lo)
-                    t = fmaf(ov / (float)(hi - lo) * G.scale[(size_t)v * G.nb + k] * G.secphi[(size_t)r * G.nb + k],
-                             R[rr + k], t);
+                const double ua = fma(lcd, b0.y, b0.x) - e0d, ub = fma(lcd, b1.y, b1.x) - e0d;
+                const float lo = (float)fmin(ua, ub), hi = (float)fmax(ua, ub), wd = (float)fabs(ub - ua);
+                const float ov = fminf(hi, 1.f) - fmaxf(lo, 0.f);
+                if (ov > 0.f && wd > 0.f) t = fmaf(ov * hx_rcp(wd) * inva, Rp[rr + k], t);
             }
-            t *= inva;
 #pragma unroll
-            for (int jz = 0; jz < HX_ZG; ++jz) {
-                const float z0 = zg0 + (float)jz;
-                const float fa = fminf(zh, z0 + 1.f) - fmaxf(zl, z0);
-                if (fa > 0.f) acc[jz] = fmaf(fa, t, acc[jz]);
+            for (int b = 0; b < HX_ZG; ++b) {
+                const float ch = hx_clamp01(zh - (float)b);
+                acc[b] = fmaf(t, ch - cl[b], acc[b]);
+                cl[b] = ch;
             }
         }
     }

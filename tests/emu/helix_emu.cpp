@@ -111,33 +111,50 @@ int hemu_forward(const ct_helix_desc *d, int vs, int vst, int nv, const float *x
     return hx_oob_count();
 }
 
-// x = A' r over views vs + vi * vst (the k_hbp grid), r [nv][nr][nb].
+// x = A' r over views vs + vi * vst, r [nv][nr][nb]: the k_hprescale pass, then the k_hbp grid with its
+// XCD-ordered tiles (every tile must be visited exactly once).
 int hemu_back(const ct_helix_desc *d, int vs, int vst, int nv, const float *r, float *x, long long *first)
 {
     Emu e;
     if (setup(d, e)) return -1;
     const HelixDev &G = e.G;
-    const Ro<float> R{r, (size_t)nv * d->nr * d->nb};
+    const size_t n = (size_t)nv * d->nr * d->nb;
+    std::vector<float> rp(n);
     reset_oob();
-    const int tiles_x = (G.nx + 3) >> 2, tiles = tiles_x * ((G.ny + 3) >> 2);
-    const int zblocks = (G.nz + 16 * HX_ZG - 1) / (16 * HX_ZG);
-    for (int bx = 0; bx < tiles; ++bx)
+    for (size_t el = 0; el < n; ++el) {
+        const int k = (int)(el % (size_t)G.nb);
+        const size_t vr = el / (size_t)G.nb;
+        const int rr = (int)(vr % (size_t)G.nr), vi = (int)(vr / (size_t)G.nr);
+        rp[el] = r[el] * hx_prescale(G, vs + vi * vst, rr, k);
+    }
+    const Ro<float> R{rp.data(), n};
+    const int tiles_x = (G.nx + 7) >> 3, ntiles = tiles_x * ((G.ny + 7) >> 3);
+    const int zblocks = (G.nz + 4 * HX_ZG - 1) / (4 * HX_ZG);
+    std::vector<int> seen((size_t)ntiles, 0);
+    for (int bid = 0; bid < ntiles; ++bid) {
+        const int full = ntiles - ntiles % 8;
+        const int tile = bid < full ? (bid % 8) * (full / 8) + bid / 8 : bid;
+        if (tile < 0 || tile >= ntiles || seen[(size_t)tile]++) {
+            g_err = "back-projection tile order is not a permutation";
+            return -1;
+        }
+        const int tx = tile % tiles_x, ty = tile / tiles_x;
         for (int by = 0; by < zblocks; ++by)
             for (int tid = 0; tid < 256; ++tid) {
-                const int zg = tid & 15, c = tid >> 4;
-                const int tx = bx % tiles_x, ty = bx / tiles_x;
-                const int j = tx * 4 + (c & 3), i = ty * 4 + (c >> 2);
-                const int kz0 = (by * 16 + zg) * HX_ZG;
+                const int lane = tid & 63, wave = tid >> 6;
+                const int j = tx * 8 + (lane & 7), i = ty * 8 + (lane >> 3);
+                const int kz0 = (by * 4 + wave) * HX_ZG;
                 if (i >= G.ny || j >= G.nx || kz0 >= G.nz) continue;
                 float acc[HX_ZG];
-                for (int jz = 0; jz < HX_ZG; ++jz) acc[jz] = 0.f;
-                hbp_group(G, R, vs, vst, nv, i, j, kz0, acc);
-                for (int jz = 0; jz < HX_ZG; ++jz) {
-                    const int kz = kz0 + jz;
+                for (int b = 0; b < HX_ZG; ++b) acc[b] = 0.f;
+                hbp_lane(G, R, vs, vst, nv, i, j, kz0, acc);
+                for (int b = 0; b < HX_ZG; ++b) {
+                    const int kz = kz0 + b;
                     if (kz >= G.nz) break;
-                    x[((size_t)kz * G.ny + i) * G.nx + j] = acc[jz];
+                    x[((size_t)kz * G.ny + i) * G.nx + j] = acc[b];
                 }
             }
+    }
     *first = hx_oob_index();
     return hx_oob_count();
 }

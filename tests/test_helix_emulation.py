@@ -92,9 +92,13 @@ def check_close(a, b, tol=1e-5):
 GEOMS = {
     "tiny_ties": synth.HelicalGeometry(5, 4, 3, 1.3, 0.9, 1.1, 0.2, 7, 2.0, 0.3, 4, 1.7, -0.2, 12, 8, 0.0, -2.0, 3.0,
                                        20.0, 40.0, 3),
-    # ragged sizes: not multiples of the 64-bin block, the 8-row block, the 4 x 4 tile or the 64-voxel z span
+    # ragged sizes: not multiples of the 64-bin block, the 8-row block, the 8 x 8 tile or the 32-voxel z span
     "ragged": synth.HelicalGeometry(37, 29, 70, 1.1, 0.9, 0.6, 0.4, 97, 1.7, -0.3, 11, 1.2, 0.25, 40, 16, 0.1, -9.0,
                                     6.0, 300.0, 560.0, 4),
+    # channels four times finer than the voxels: columns meet 5 to 9 bins, more than the back-projector keeps in
+    # registers, and rows thinner than the voxels (the fallback paths of both loops)
+    "fine_detector": synth.HelicalGeometry(11, 9, 6, 2.0, 2.0, 1.5, 0.0, 61, 0.9, 0.2, 9, 0.7, 0.1, 24, 12, 0.3,
+                                           -4.0, 4.0, 60.0, 110.0, 2),
     # a quarter of the 512^2 x 64 helical scan's sampling in each direction: 128^2 x 16, 222 x 8, 3 x 220 views
     "helical_small": synth.HELICAL_SMALL,
 }
