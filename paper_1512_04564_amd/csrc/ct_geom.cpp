@@ -58,6 +58,28 @@ void det_point64(const ct_geom_desc &d, const View64 &o, double u, double *px, d
 
 }  // namespace
 
+// Whether the back-projector may locate the bins of a lane's run of pixel edges by a quadratic in the
+// edge index m = 0 .. 4 instead of one division per edge (flat detector only). Along a line the detector
+// coordinate of edge m is t(m) = (n0 + a m) / (d0 + c m) = a/c + K / (1 + eps m), eps = c / d0, so the
+// quadratic Taylor polynomial about m = 0 misses it by t'(0) eps^2 m^3 / (1 + eps m). With R the image's
+// half diagonal, every depth d0 + c m is at least dso - R, |a|, |c| are at most the pixel size p and
+// |t| at most R / (dso - R): |eps| <= p / (dso - R) and |t'| <= (1 + R / (dso - R)) p / (dso - R). The
+// kernel's estimate only has to land within one bin of the true one (it then steps to the neighbour);
+// the bound is required below a quarter bin.
+static int quadratic_bin_estimate_ok(const ct_geom_desc &d)
+{
+    if (d.det == CT_DET_ARC) return 0;
+    const double R = 0.5 * std::hypot(d.nx * d.dx, d.ny * d.dy);
+    const double depth = d.dso - R;
+    if (!(depth > 0.0)) return 0;
+    const double p = std::max(d.dx, d.dy);
+    const double eps = p / depth, np = 4.0;
+    if (!(np * eps < 0.5)) return 0;
+    const double slope = d.dsd / d.du * (1.0 + R / depth) * p / depth;   // bins per edge step, at most
+    const double miss = slope * eps * eps * np * np * np / (1.0 - np * eps);
+    return miss < 0.25 ? 1 : 0;
+}
+
 ct_status geometry_tables(const ct_geom_desc &d, GeomTables &t)
 {
     const int nv = d.nviews, nb = d.nb;
@@ -128,6 +150,7 @@ ct_status geometry_tables(const ct_geom_desc &d, GeomTables &t)
     }
     t.c_kf = (float)(d.dsd / d.du);
     t.k0 = (float)(0.5 * nb - d.u_offset);
+    t.poly = quadratic_bin_estimate_ok(d);
     return CT_OK;
 }
 
@@ -161,6 +184,7 @@ ct_status build_geometry(ct_geom *g)
     G.nb = nb;
     G.nviews = nv;
     G.arc = d.det == CT_DET_ARC;
+    G.poly = t.poly;
     G.dso = (float)d.dso;
     G.c_kf = t.c_kf;
     G.k0 = t.k0;

@@ -46,6 +46,7 @@ constexpr int kBpTile = 16;   // back-projection tile edge (pixels)
 struct GeomDev {
     int nx, ny, nb, nviews;
     int arc;
+    int poly;     // the back-projector may estimate edge bins by a quadratic along the line (see ct_geom.cpp)
     float dso;
     float c_kf;   // dsd / du
     float k0;     // nb/2 - u_offset
@@ -131,6 +132,7 @@ struct GeomTables {
     std::vector<float> sgn;
     std::vector<int> rowsweep;
     float c_kf = 0.f, k0 = 0.f;
+    int poly = 0;
 };
 ct_status geometry_tables(const ct_geom_desc &d, GeomTables &t);
 // Argument check of solver parameters; rho_k of eq. dec_rho (FP64; rho_fixed in fixed mode).

@@ -490,26 +490,45 @@ __device__ __forceinline__ float cum_value(const CumBin &c, float u)
 // Back-projection of view onto the NP pixels [ex + m, ex + m + 1] (m < NP) of line lc from the cumulative
 // form: the NP + 1 edges are evaluated once each, one after the other, each pixel taking the difference
 // of its two edges' values. kofs = k0 - kw0 (the detector coordinate from the window's first bin), n the
-// window's bins, pos the boundary order.
-template <int NP>
-__device__ __forceinline__ void bp_line(const GeomDev &G, const float4 im, float lc, float ex, bool pos, int n,
-                                        float kofs, const float4 *__restrict__ E, float (&val)[NP])
+// window's bins, POS the view's boundary order (a template parameter, so that the sign flips are operand
+// modifiers). POLY: the edges' detector coordinates come from the quadratic Taylor polynomial in m about
+// the first edge (t(m) = a/c + K / (1 + eps m) along the line, so t'' / 2 = -eps t'); the host allows it
+// only where the polynomial stays within a quarter bin of the true coordinate, and the step to the
+// neighbouring entry below absorbs that as it absorbs the reciprocal's error. Otherwise one division per
+// edge (and the arc detector's arctangent).
+template <int NP, bool POS, bool POLY>
+__device__ __forceinline__ void bp_line(const GeomDev &G, const float4 im, float lc, float ex, int n, float kofs,
+                                        const float4 *__restrict__ E, float (&val)[NP])
 {
     const float nlc = lc * im.y;
     const float dlc = fmaf(lc, im.w, G.dso);
+    float K0 = 0.f, K1 = 0.f, K2 = 0.f;
+    if constexpr (POLY) {
+        const float rd = rcp_approx(fmaf(ex, im.z, dlc));
+        const float t0 = fmaf(ex, im.x, nlc) * rd;
+        K0 = fmaf(G.c_kf, t0, kofs);
+        K1 = G.c_kf * (fmaf(-t0, im.z, im.x) * rd);   // d kf / dm at m = 0
+        K2 = -K1 * (im.z * rd);                        // half the second derivative
+    }
     float Fp = 0.f;
 #pragma unroll
     for (int m = 0; m <= NP; ++m) {
         const float em = ex + (float)m;
-        float t = fmaf(em, im.x, nlc) * rcp_approx(fmaf(em, im.z, dlc));
-        if (G.arc) t = atanf(t);
-        const int e = min(max((int)floorf(fmaf(G.c_kf, t, kofs)), 0), n - 1);
-        const float u = pos ? em : -em;   // the edge in signed coordinates
+        float kf;
+        if constexpr (POLY) {
+            kf = m == 0 ? K0 : fmaf((float)m, fmaf((float)m, K2, K1), K0);
+        } else {
+            float t = fmaf(em, im.x, nlc) * rcp_approx(fmaf(em, im.z, dlc));
+            if (G.arc) t = atanf(t);
+            kf = fmaf(G.c_kf, t, kofs);
+        }
+        const int e = min(max((int)floorf(kf), 0), n - 1);
+        const float u = POS ? em : -em;   // the edge in signed coordinates
         CumBin c = cum_bin(E, e, lc);
-        if ((u < c.ua) | (u > c.ub))   // the estimate missed its edge's bin by a hair: the neighbouring entry
+        if ((u < c.ua) | (u > c.ub))   // the estimate missed its edge's bin: the neighbouring entry
             c = cum_bin(E, min(max(u < c.ua ? e - 1 : e + 1, 0), n - 1), lc);
         const float F = cum_value(c, u);
-        if (m > 0) val[m - 1] = pos ? F - Fp : Fp - F;
+        if (m > 0) val[m - 1] = POS ? F - Fp : Fp - F;
         Fp = F;
     }
 }
@@ -583,13 +602,14 @@ __device__ __forceinline__ int2 tile_window(const GeomDev &G, int v, int i0, int
 }
 
 // Fused back-projection and relaxed update over one 16 x 16 pixel tile. The workgroup's eight waves are
-// view groups: wave w back-projects the views w, w + 8, w + 16, ... onto the whole tile, each lane a 2 x 2
-// block of pixels. Each wave computes its views' bin windows and descriptors one view per lane (read
-// back with readlane) and stages its current view in its own LDS slot (boundaries, residual x scale and
-// their running sum over the window: one wave prefix sum), the next view's loads in flight meanwhile; the
-// view loop needs no workgroup barrier. On the two lines of a block the pixels share edges, so a view
-// costs six edge evaluations for four pixels. The eight partial sums are added in a fixed order, then the
-// first 256 threads carry out the update, one pixel each.
+// view groups: wave w back-projects the views w, w + 8, w + 16, ... onto the whole tile, each lane four
+// consecutive pixels along the view's lines (1 x 4 for row sweep views, 4 x 1 for column sweep views).
+// Each wave computes its views' bin windows and descriptors one view per lane (read back with readlane)
+// and stages its current view in its own LDS slot (boundaries, residual x scale and their running sum
+// over the window: one wave prefix sum), the next view's loads in flight meanwhile; the view loop needs no
+// workgroup barrier. The lane's four pixels share their inner edges, so a view costs five edge
+// evaluations for four pixels. The eight partial sums are added in a fixed order, then the first 256
+// threads carry out the update, one pixel each.
 constexpr int BP_NT = BP_TX * BP_TY;
 constexpr int BP_GROUPS = 8;    // view groups (waves) per workgroup
 constexpr int BP_SWIN = 125;    // widest window staged (bins); wider ones read the tables directly
@@ -751,7 +771,14 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
                     const float lc0 = row ? lc_row : lc_col, ex = row ? ex_row : ex_col;
                     float val[4];   // the lane's four pixels along the line
                     if (ne > 0) {
-                        bp_line<4>(G, im, lc0, ex, pos, ne - 1, G.k0 - (float)kw0, E, val);
+                        const float kofs = G.k0 - (float)kw0;
+                        if (G.poly) {
+                            if (pos) bp_line<4, true, true>(G, im, lc0, ex, ne - 1, kofs, E, val);
+                            else bp_line<4, false, true>(G, im, lc0, ex, ne - 1, kofs, E, val);
+                        } else {
+                            if (pos) bp_line<4, true, false>(G, im, lc0, ex, ne - 1, kofs, E, val);
+                            else bp_line<4, false, false>(G, im, lc0, ex, ne - 1, kofs, E, val);
+                        }
                     } else {   // window wider than the staging slots: read the tables directly
                         const int vi = wave + BP_GROUPS * (c0 + ci);
                         const int v = vstart + vi * vstride;
