@@ -227,9 +227,12 @@ ct_status ct_cost(ct_geom *g, const ct_rlalm_params *p, const void *y, const voi
  *     set of slice shapes -- lockstep with 8 or 16 waves per projection workgroup, persistent with 1, 2 or
  *     4 resident workgroups per CU, each with the slices in the given order or largest first -- and keep
  *     the fastest, cached per process and on disk (a text file per GPU architecture and shape set under
- *     $CTRLALM_TUNE_DIR, else $XDG_CACHE_HOME/ctrlalm/tune, else ~/.cache/ctrlalm/tune); 2 = persistent
- *     at the resident capacity, slices in the given order. The slice order never changes a result; the
- *     forward workgroup's wave count changes the projection's summation order (the persistent form uses 8).
+ *     $CTRLALM_TUNE_DIR, else $XDG_CACHE_HOME/ctrlalm/tune, else ~/.cache/ctrlalm/tune); 2 = persistent,
+ *     its candidates (1, 2 or 4 workgroups per CU, either slice order) timed on this batch and the fastest
+ *     kept (not cached). The slice order never changes a result; the forward workgroup's wave count changes
+ *     the projection's summation order (the persistent form uses 8). Persistent launches pay two grid
+ *     barriers per subiteration, each with an agent-scope release and acquire per workgroup (a write-back
+ *     and an invalidation of its XCD's L2): on large batches lockstep is usually faster.
  *   chosen: if non-NULL, receives the launch shape used.
  * Waits for the device at the end. Returns CT_ERR_DIVERGED (message names the slice) if any slice ends
  * non-finite.

@@ -230,7 +230,8 @@ def rlalm_status(g: Geometry) -> None:
 def rlalm_solve_batched(geoms, p: Params, ys, ws, xs, *, autotune=False, stream=None) -> dict:
     """Solve len(geoms) independent slices in place on each ``xs[i]`` (ct_rlalm_solve_batched).
     ``autotune``: False / 0 lockstep default shape, True / 1 tuned (lockstep or persistent), 2 or
-    "persistent" the single persistent launch. Returns the launch shape used:
+    "persistent" the single persistent launch at its fastest shape on this batch. Returns the launch
+    shape used:
     ``{"fp_waves", "largest_first", "ms_subiteration", "persistent", "blocks_per_cu"}``."""
     autotune = 2 if autotune == "persistent" else int(autotune)
     n = len(geoms)

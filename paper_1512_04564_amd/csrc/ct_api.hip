@@ -685,10 +685,10 @@ ct_status upload_table(const std::vector<SliceDev> &tab, SliceDev **dtab, hipStr
     return CT_OK;
 }
 
-// Times each candidate launch shape on the prepared slices (two subiterations of warm-up, then kReps
-// timed); it overwrites the slices' ping-pong images, g, h and residual blocks, which the
-// initialisation that follows rewrites.
-ct_status tune_batch(const std::vector<Ctx> &cs, hipStream_t s, ct_batch_config *best)
+// Times each candidate launch shape of the selected forms on the prepared slices (two subiterations of
+// warm-up, then kReps timed); it overwrites the slices' ping-pong images, g, h and residual blocks, which
+// the initialisation that follows rewrites.
+ct_status tune_batch(const std::vector<Ctx> &cs, hipStream_t s, ct_batch_config *best, bool lockstep, bool persistent)
 {
     constexpr int kReps = 6;
     const int n = (int)cs.size();
@@ -727,7 +727,7 @@ ct_status tune_batch(const std::vector<Ctx> &cs, hipStream_t s, ct_batch_config 
     const int max_bpc = persistent_blocks_per_cu(cs[0].dtype);
     std::vector<int> ord(cs[0].order);
     int *dorder = nullptr;
-    if (cus > 0 && max_bpc > 0) {
+    if (persistent && cus > 0 && max_bpc > 0) {
         st = dev_alloc(&dorder, ord.size());
         if (st == CT_OK && hipMemcpy(dorder, ord.data(), ord.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
             st = fail(CT_ERR_HIP, "batch tuning: order upload failed");
@@ -771,6 +771,7 @@ ct_status tune_batch(const std::vector<Ctx> &cs, hipStream_t s, ct_batch_config 
             }
         }
         for (int waves : {16, 8}) {
+            if (!lockstep) break;
             int nfp = 0, nbp = 0;
             std::vector<SliceDev> tab = slice_table(cs, lf ? largest : given, waves, &nfp, &nbp);
             SliceDev *dtab = nullptr;
@@ -1289,15 +1290,17 @@ ct_status ct_rlalm_solve_batched(ct_geom *const *gs, int n, const ct_rlalm_param
         const std::string path = tune_file(dev, key);
         if (!have && !path.empty()) have = read_tuned(path, &cfg, persistent_blocks_per_cu(cs[0].dtype));
         if (!have) {
-            CT_TRY(tune_batch(cs, s, &cfg));
+            CT_TRY(tune_batch(cs, s, &cfg, true, true));
             if (!path.empty()) write_tuned(path, cfg);
         }
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune_cache[key] = cfg;
     } else if (autotune == 2) {
-        const int bpc = persistent_blocks_per_cu(cs[0].dtype);
-        if (bpc < 1) return fail(CT_ERR_UNSUPPORTED, "the persistent batched kernel cannot be resident on this device");
-        cfg = ct_batch_config{8, 0, 0.0, 1, bpc};
+        // the persistent launch, its workgroups per CU and slice order tuned on this batch (not cached)
+        if (persistent_blocks_per_cu(cs[0].dtype) < 1)
+            return fail(CT_ERR_UNSUPPORTED, "the persistent batched kernel cannot be resident on this device");
+        CT_TRY(tune_batch(cs, s, &cfg, false, true));
+        if (cfg.persistent != 1) return fail(CT_ERR_HIP, "no persistent launch shape completed its grid barriers");
     }
     if (chosen) *chosen = cfg;
 

@@ -316,13 +316,15 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvSrc S, const bf16 *__r
 }
 
 // Weight gradient partials of a 3x3 convolution: part[split][c_out][tap][c_in] over the pixels
-// [split * pps, min((split + 1) * pps, npix)) (pps a multiple of 32; the last chunk of 32 may be
+// [split * pps, min((split + 1) * pps, npix)) (pps a multiple of 64; the last chunk of 64 may be
 // partial, its missing pixels count as zero). One wave per (split, tap, 32 x 32 channel block); grid
-// (splits, 9, (c_out / 32) * (c_in / 32)).
+// (splits, 9, (c_out / 32) * (c_in / 32)). Each LDS fill holds 64 pixels of both operands (two MFMA
+// K-steps per pair of barriers).
 __global__ __launch_bounds__(64) void k_conv3x3_wgrad(ConvSrc S, const bf16 *__restrict__ dz, int cout, int n, int h,
                                                       int w, int pps, float *__restrict__ part)
 {
-    constexpr int LD = 40;   // padded LDS row (bf16): 80 bytes keeps rows 16-byte aligned
+    constexpr int KC = 64;        // pixels per LDS fill
+    constexpr int LD = KC + 8;    // padded LDS row (bf16): 144 bytes keeps rows 16-byte aligned
     __shared__ __attribute__((aligned(16))) bf16 sA[32 * LD];   // [c_out][pixel]
     __shared__ __attribute__((aligned(16))) bf16 sB[32 * LD];   // [c_in][pixel]
     const int lane = threadIdx.x;
@@ -340,10 +342,10 @@ __global__ __launch_bounds__(64) void k_conv3x3_wgrad(ConvSrc S, const bf16 *__r
 #pragma unroll
         for (int q = 0; q < 2; ++q) acc[m][q] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bf16x8 zero8 = {};
-    for (int pc = pb; pc < pe; pc += 32) {
-        // 32 pixels x 32 channels of each operand: 128 16-byte pieces, two per lane
+    for (int pc = pb; pc < pe; pc += KC) {
+        // 64 pixels x 32 channels of each operand: 256 16-byte pieces, four per lane
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < 4; ++t) {
             const int idx = lane + 64 * t;
             const int q = idx >> 2, c8 = (idx & 3) * 8;
             const bool in = pc + q < pe;
@@ -363,15 +365,19 @@ __global__ __launch_bounds__(64) void k_conv3x3_wgrad(ConvSrc S, const bf16 *__r
             }
         }
         __syncthreads();
-        bf16x8 a[2], b[2];
 #pragma unroll
-        for (int m = 0; m < 2; ++m) a[m] = *reinterpret_cast<const bf16x8 *>(sA + (16 * m + r) * LD + 8 * g);
+        for (int kk = 0; kk < KC / 32; ++kk) {
+            bf16x8 a[2], b[2];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) b[q] = *reinterpret_cast<const bf16x8 *>(sB + (16 * q + r) * LD + 8 * g);
+            for (int m = 0; m < 2; ++m) a[m] = *reinterpret_cast<const bf16x8 *>(sA + (16 * m + r) * LD + 32 * kk + 8 * g);
 #pragma unroll
-        for (int m = 0; m < 2; ++m)
+            for (int q = 0; q < 2; ++q) b[q] = *reinterpret_cast<const bf16x8 *>(sB + (16 * q + r) * LD + 32 * kk + 8 * g);
 #pragma unroll
-            for (int q = 0; q < 2; ++q) acc[m][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[q], acc[m][q], 0, 0, 0);
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    acc[m][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[q], acc[m][q], 0, 0, 0);
+        }
         __syncthreads();
     }
 #pragma unroll
@@ -385,40 +391,93 @@ __global__ __launch_bounds__(64) void k_conv3x3_wgrad(ConvSrc S, const bf16 *__r
             }
 }
 
-// grad[co][ci][dy][dx] (canonical) = sum over splits of part[split][co][tap][ci]
-__global__ void k_wgrad_reduce(const float *__restrict__ part, int nsplit, int cout, int cin, float *__restrict__ grad)
+// grad[co][ci][dy][dx] (canonical) = sum over splits of part[split][co][tap][ci]: 32 outputs per workgroup,
+// 8 lanes over the splits (k = lane, lane + 8, ...), their sums added in lane order.
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float *__restrict__ part, int nsplit, int cout, int cin,
+                                                      float *__restrict__ grad)
 {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;   // canonical index
+    __shared__ float red[8][32];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const size_t i = (size_t)blockIdx.x * 32 + tx;   // canonical index
     const size_t total = (size_t)cout * cin * 9;
-    if (i >= total) return;
-    const int tap = (int)(i % 9);
-    const int ci = (int)((i / 9) % cin);
-    const int co = (int)(i / (9 * (size_t)cin));
-    const size_t stride = (size_t)cout * 9 * cin;
-    const size_t o = ((size_t)co * 9 + tap) * cin + ci;
     float s = 0.f;
-    for (int k = 0; k < nsplit; ++k) s += part[k * stride + o];
-    grad[i] = s;
+    if (i < total) {
+        const int tap = (int)(i % 9);
+        const int ci = (int)((i / 9) % cin);
+        const int co = (int)(i / (9 * (size_t)cin));
+        const size_t stride = (size_t)cout * 9 * cin;
+        const size_t o = ((size_t)co * 9 + tap) * cin + ci;
+        for (int k = ty; k < nsplit; k += 8) s += part[k * stride + o];
+    }
+    red[ty][tx] = s;
+    __syncthreads();
+    if (ty == 0 && i < total) {
+        float t = red[0][tx];
+#pragma unroll
+        for (int l = 1; l < 8; ++l) t += red[l][tx];
+        grad[i] = t;
+    }
 }
 
-// Bias gradient partials: part[split][c] = sum over the split's pixels of dz[p][c] (blockDim = c).
-__global__ void k_bias_part(const bf16 *__restrict__ dz, int c, int npix, int pps, float *__restrict__ part)
+// Bias gradient partials: part[split][c] = sum over the split's pixels of dz[p][c] (c a multiple of 8,
+// c / 8 dividing 256). The 256 threads are c / 8 channel groups (16-byte loads) x 2048 / c pixel lanes;
+// the pixel lanes' sums are added in LDS in lane order.
+__global__ __launch_bounds__(256) void k_bias_part(const bf16 *__restrict__ dz, int c, int npix, int pps,
+                                                   float *__restrict__ part)
 {
-    const int ch = threadIdx.x;
+    __shared__ float red[256 * 8];
+    const int ng = c / 8, nl = 256 / ng;
+    const int cg = threadIdx.x % ng, pl = threadIdx.x / ng;
     const int pb = blockIdx.x * pps, pe = min(pb + pps, npix);
-    float s = 0.f;
-    for (int p = pb; p < pe; ++p) s += (float)dz[(size_t)p * c + ch];
-    part[(size_t)blockIdx.x * c + ch] = s;
+    float sum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int p = pb + pl; p < pe; p += nl) {
+        const bf16x8 v = *reinterpret_cast<const bf16x8 *>(dz + (size_t)p * c + 8 * cg);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) sum[i] += (float)v[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) red[threadIdx.x * 8 + i] = sum[i];   // [pixel lane][channel]
+    __syncthreads();
+    for (int ch = threadIdx.x; ch < c; ch += 256) {
+        float t = 0.f;
+        for (int l = 0; l < nl; ++l) t += red[l * c + ch];
+        part[(size_t)blockIdx.x * c + ch] = t;
+    }
 }
 
-// out[i] = sum over k of part[k * n + i]
-__global__ void k_sum_parts(const float *__restrict__ part, int nsplit, int n, float *__restrict__ out)
+// Pixels per bias-gradient split for c channels: 32 loads per thread.
+constexpr int bias_pps(int c) { return 32 * (2048 / c); }
+
+// out[i] = sum over k of part[k * n + i]: 32 outputs per workgroup, 8 lanes over the splits (k = lane,
+// lane + 8, ...), their sums added in lane order.
+__global__ __launch_bounds__(256) void k_sum_parts(const float *__restrict__ part, int nsplit, int n,
+                                                   float *__restrict__ out)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    __shared__ float red[8][32];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int i = blockIdx.x * 32 + tx;
     float s = 0.f;
-    for (int k = 0; k < nsplit; ++k) s += part[(size_t)k * n + i];
-    out[i] = s;
+    if (i < n)
+        for (int k = ty; k < nsplit; k += 8) s += part[(size_t)k * n + i];
+    red[ty][tx] = s;
+    __syncthreads();
+    if (ty == 0 && i < n) {
+        float t = red[0][tx];
+#pragma unroll
+        for (int l = 1; l < 8; ++l) t += red[l][tx];
+        out[i] = t;
+    }
+}
+
+// Sum of v over the 16 lanes of a wave that share lane % 4 (a butterfly: every such lane ends with the
+// same bits, since each step adds the same two values on both sides).
+__device__ __forceinline__ float sum16_of_4(float v)
+{
+    v += __shfl_xor(v, 4);
+    v += __shfl_xor(v, 8);
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    return v;
 }
 
 // Input layer (one channel, 32 outputs): out[p][co] = relu(b[co] + sum_tap W[co][tap] x[p + tap]).
@@ -455,25 +514,59 @@ __global__ __launch_bounds__(256) void k_conv_in(const float *__restrict__ x, co
     *reinterpret_cast<bf16x8 *>(out + p * 32 + 8 * q) = o;
 }
 
-// Input layer weight / bias gradient partials: thread t < 288 accumulates (co, tap) = (t / 9, t % 9),
-// threads 288..319 the bias of co = t - 288; part[split][320].
-__global__ __launch_bounds__(320) void k_conv_in_wgrad(const float *__restrict__ x, const bf16 *__restrict__ dz, int n,
+// Input layer weight / bias gradient partials part[split][320]: entries co * 9 + tap (co < 32, tap < 9)
+// sum dz[p][co] x[p + tap offset], entries 288 + co sum dz[p][co]. Thread (pixel lane tid / 4, channel
+// group tid % 4 of 8 channels) accumulates its pixels' 72 + 8 sums; the 16 pixel lanes of a wave are
+// added by a butterfly, the four waves in LDS, in a fixed order.
+__global__ __launch_bounds__(256) void k_conv_in_wgrad(const float *__restrict__ x, const bf16 *__restrict__ dz, int n,
                                                        int h, int w, int pps, float *__restrict__ part)
 {
-    const int t = threadIdx.x;
+    __shared__ float red[4][320];
+    const int cg = threadIdx.x & 3, pl = threadIdx.x >> 2, wave = threadIdx.x >> 6;
     const int hw = h * w, npix = n * hw;
     const int pb = blockIdx.x * pps, pe = min(pb + pps, npix);
-    const bool isb = t >= 288;
-    const int co = isb ? t - 288 : t / 9, tap = isb ? 4 : t % 9;
-    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-    float s = 0.f;
-    for (int p = pb; p < pe; ++p) {
-        const int pn = p / hw, rem = p - pn * hw, py = rem / w, px = rem - py * w;
-        const int yy = py + dy, xx = px + dx;
-        const float xv = isb ? 1.f : ((yy >= 0 && yy < h && xx >= 0 && xx < w) ? x[(size_t)pn * hw + yy * w + xx] : 0.f);
-        s = fmaf((float)dz[(size_t)p * 32 + co], xv, s);
+    float sw[8][9], sb[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        sb[i] = 0.f;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) sw[i][k] = 0.f;
     }
-    part[(size_t)blockIdx.x * 320 + t] = s;
+    for (int p = pb + pl; p < pe; p += 64) {
+        const int pn = p / hw, rem = p - pn * hw, py = rem / w, px = rem - py * w;
+        float v[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const int yy = py + k / 3 - 1, xx = px + k % 3 - 1;
+            v[k] = (yy >= 0 && yy < h && xx >= 0 && xx < w) ? x[(size_t)pn * hw + yy * w + xx] : 0.f;
+        }
+        const bf16x8 d = *reinterpret_cast<const bf16x8 *>(dz + (size_t)p * 32 + 8 * cg);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float di = (float)d[i];
+            sb[i] += di;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) sw[i][k] = fmaf(di, v[k], sw[i][k]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        sb[i] = sum16_of_4(sb[i]);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) sw[i][k] = sum16_of_4(sw[i][k]);
+    }
+    if ((threadIdx.x & 63) < 4) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int co = 8 * cg + i;
+            red[wave][288 + co] = sb[i];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) red[wave][co * 9 + k] = sw[i][k];
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < 320; t += 256)
+        part[(size_t)blockIdx.x * 320 + t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
 }
 
 // Output layer: out[p] = x[p] + b + sum_c W[c] a[p][c]. With a target: dy[p] = gscale (out - target)
@@ -531,14 +624,34 @@ __global__ void k_conv_out_back(const float *__restrict__ dy, const float *__res
     }
 }
 
-__global__ void k_conv_out_wgrad(const float *__restrict__ dy, const bf16 *__restrict__ a, int npix, int pps,
-                                 float *__restrict__ part)
+// Output layer gradient partials part[split][33]: entry c < 32 sums dy[p] a[p][c], entry 32 sums dy[p].
+// Thread (pixel lane tid / 4, channel group tid % 4) as in k_conv_in_wgrad.
+__global__ __launch_bounds__(256) void k_conv_out_wgrad(const float *__restrict__ dy, const bf16 *__restrict__ a,
+                                                        int npix, int pps, float *__restrict__ part)
 {
-    const int t = threadIdx.x;   // 0..32
+    __shared__ float red[4][33];
+    const int cg = threadIdx.x & 3, pl = threadIdx.x >> 2, wave = threadIdx.x >> 6;
     const int pb = blockIdx.x * pps, pe = min(pb + pps, npix);
-    float s = 0.f;
-    for (int p = pb; p < pe; ++p) s = fmaf(dy[p], t < 32 ? (float)a[(size_t)p * 32 + t] : 1.f, s);
-    part[(size_t)blockIdx.x * 33 + t] = s;
+    float sum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, sb = 0.f;
+    for (int p = pb + pl; p < pe; p += 64) {
+        const float d = dy[p];
+        const bf16x8 v = *reinterpret_cast<const bf16x8 *>(a + (size_t)p * 32 + 8 * cg);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) sum[i] = fmaf(d, (float)v[i], sum[i]);
+        sb += d;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) sum[i] = sum16_of_4(sum[i]);
+    sb = sum16_of_4(sb);
+    if ((threadIdx.x & 63) < 4) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) red[wave][8 * cg + i] = sum[i];
+        if (cg == 0) red[wave][32] = sb;
+    }
+    __syncthreads();
+    if (threadIdx.x < 33)
+        part[(size_t)blockIdx.x * 33 + threadIdx.x] =
+            ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
 }
 
 // 2x2 average pooling, NHWC bf16: one thread per (output pixel, 8 channels).
@@ -734,21 +847,22 @@ ct_status check_shape(const ct_unet *u, int n, int h, int w)
 
 int splits_for(size_t npix, size_t tiles)
 {
-    // enough workgroups to fill the chip, at least 1024 pixels per split
-    size_t sp = std::max<size_t>(1, std::min<size_t>(npix / 1024, (2048 + tiles - 1) / tiles));
-    return (int)std::min<size_t>(sp, 512);
+    // about 8192 single-wave workgroups (32 per CU: the chunk loop waits on its loads and barriers, so
+    // occupancy hides it), at least 512 pixels per split
+    size_t sp = std::max<size_t>(1, std::min<size_t>(npix / 512, (8192 + tiles - 1) / tiles));
+    return (int)std::min<size_t>(sp, 1024);
 }
 
-// Split geometry of a weight-gradient launch: pixels per split (multiple of 32) and split count.
+// Split geometry of a weight-gradient launch: pixels per split (multiple of 64) and split count.
 void wgrad_splits(size_t npix, int cin, int cout, int *pps, int *nsp)
 {
     const size_t tiles = (size_t)9 * (cout / 32) * (cin / 32);
     const int ns = splits_for(npix, tiles);
-    *pps = (int)(((npix + ns - 1) / ns + 31) / 32 * 32);
+    *pps = (int)(((npix + ns - 1) / ns + 63) / 64 * 64);
     *nsp = (int)((npix + *pps - 1) / *pps);
 }
 
-constexpr int kBiasPps = 512, kOutPps = 4096, kInPps = 2048;
+constexpr int kOutPps = 4096, kInPps = 2048;
 constexpr int kLevel[kLayers] = {0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0, 0};
 
 // Largest partial-sum request of any backward launch for batches up to max_n x max_h x max_w. Every
@@ -762,7 +876,7 @@ size_t part_need(const ct_unet *u)
         // the split count of any smaller batch is at most splits_for() at the maximum one
         const size_t ns = (size_t)splits_for(np, (size_t)9 * (kShape[l][1] / 32) * (kShape[l][0] / 32));
         need = std::max(need, ns * kShape[l][1] * 9 * kShape[l][0]);
-        need = std::max(need, ((np + kBiasPps - 1) / kBiasPps) * (size_t)kShape[l][1]);
+        need = std::max(need, ((np + bias_pps(kShape[l][1]) - 1) / bias_pps(kShape[l][1])) * (size_t)kShape[l][1]);
     }
     need = std::max(need, ((P1 + kOutPps - 1) / kOutPps) * 33);
     need = std::max(need, ((P1 + kInPps - 1) / kInPps) * 320);
@@ -900,15 +1014,15 @@ ct_status conv_wgrad(ct_unet *u, int l, const ConvSrc &S, const bf16 *dz, int n,
                        u->part);
     CT_HIP_CHECK(hipGetLastError());
     const size_t nw = (size_t)cout * cin * 9;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(nw, 256)), dim3(256), 0, s, u->part, nsp, cout, cin, u->grad + u->off[l]);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(nw, 32)), dim3(256), 0, s, u->part, nsp, cout, cin, u->grad + u->off[l]);
     CT_HIP_CHECK(hipGetLastError());
     // bias
-    const int bps = kBiasPps;
+    const int bps = bias_pps(cout);
     const int nb = (int)((npix + bps - 1) / bps);
     CT_TRY(ensure_part(u, (size_t)nb * cout));
-    hipLaunchKernelGGL(k_bias_part, dim3(nb), dim3(cout), 0, s, dz, cout, (int)npix, bps, u->part);
+    hipLaunchKernelGGL(k_bias_part, dim3(nb), dim3(256), 0, s, dz, cout, (int)npix, bps, u->part);
     CT_HIP_CHECK(hipGetLastError());
-    hipLaunchKernelGGL(k_sum_parts, dim3(blocks(cout, 256)), dim3(256), 0, s, u->part, nb, cout, u->grad + u->off[l] + nw);
+    hipLaunchKernelGGL(k_sum_parts, dim3(blocks(cout, 32)), dim3(256), 0, s, u->part, nb, cout, u->grad + u->off[l] + nw);
     CT_HIP_CHECK(hipGetLastError());
     return CT_OK;
 }
@@ -968,9 +1082,9 @@ ct_status run_backward(ct_unet *u, const float *x, int n, int h, int w, hipStrea
         const int pps = kOutPps;
         const int nsp = (int)((P1 + pps - 1) / pps);
         CT_TRY(ensure_part(u, (size_t)nsp * 33));
-        hipLaunchKernelGGL(k_conv_out_wgrad, dim3(nsp), dim3(33), 0, s, u->dy, u->d1b, (int)P1, pps, u->part);
+        hipLaunchKernelGGL(k_conv_out_wgrad, dim3(nsp), dim3(256), 0, s, u->dy, u->d1b, (int)P1, pps, u->part);
         CT_HIP_CHECK(hipGetLastError());
-        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, u->part, nsp, 33, u->grad + u->off[14]);
+        hipLaunchKernelGGL(k_sum_parts, dim3(blocks(33, 32)), dim3(256), 0, s, u->part, nsp, 33, u->grad + u->off[14]);
         CT_HIP_CHECK(hipGetLastError());
     }
     // decoder level 1
@@ -1028,10 +1142,10 @@ ct_status run_backward(ct_unet *u, const float *x, int n, int h, int w, hipStrea
         const int pps = kInPps;
         const int nsp = (int)((P1 + pps - 1) / pps);
         CT_TRY(ensure_part(u, (size_t)nsp * 320));
-        hipLaunchKernelGGL(k_conv_in_wgrad, dim3(nsp), dim3(320), 0, s, x, u->dzB[0], n, h, w, pps, u->part);
+        hipLaunchKernelGGL(k_conv_in_wgrad, dim3(nsp), dim3(256), 0, s, x, u->dzB[0], n, h, w, pps, u->part);
         CT_HIP_CHECK(hipGetLastError());
         // weights 0..287 (canonical [co][1][3][3] == [co][tap]), then biases 288..319
-        hipLaunchKernelGGL(k_sum_parts, dim3(2), dim3(256), 0, s, u->part, nsp, 320, u->grad + u->off[0]);
+        hipLaunchKernelGGL(k_sum_parts, dim3(blocks(320, 32)), dim3(256), 0, s, u->part, nsp, 320, u->grad + u->off[0]);
         CT_HIP_CHECK(hipGetLastError());
     }
     return CT_OK;
