@@ -2,9 +2,11 @@
 // 26-neighbour relaxed update and the solver driver.
 //
 // Kernels (per-thread arithmetic in ct_helix_body.hpp):
+//   k_hcum    cumulative form of the volume for the forward projector, in both layouts: per voxel the
+//             FP64 sum of its column's voxels below it (rounded once) and the voxel itself.
 //   k_hfp     forward projection of a view block: workgroup = (64 bins, HX_RB rows, view); its HX_FW waves
-//             take interleaved planes, lanes are bins; the waves' partial sums are added in LDS in a fixed
-//             order; the epilogue writes A x, the weighted residual M w (A x - y), or w (A 1), the last two
+//             take interleaved planes, lanes are bins; each row of a meeting column is one evaluation of the
+//             column's cumulative integral; the waves' partial sums are added in LDS in a fixed order; the epilogue writes A x, the weighted residual M w (A x - y), or w (A 1), the last two
 //             optionally prescaled for the back-projector (hx_prescale).
 //   k_hbp     gather back-projection, no atomics: a wave is an 8 x 8 tile of voxel columns, every lane the
 //             same HX_ZG voxels in z of its column, so that the lanes of a wave meet the same few detector
@@ -39,6 +41,7 @@ struct ct_helix {
     size_t nvox = 0;
     float *xa = nullptr, *xb = nullptr, *xta = nullptr, *xtb = nullptr;
     float *gv = nullptr, *h = nullptr, *dl = nullptr, *zeta = nullptr;
+    float2 *cz = nullptr, *czT = nullptr;   // cumulative forms of the projected volume (both layouts)
     float *r = nullptr;
     size_t r_cap = 0;
     double *red = nullptr;
@@ -59,8 +62,25 @@ constexpr int HUPD_T = 16;         // update tile edge
 
 // Forward projection of views vstart + vi * vstride (vi = blockIdx.z). Bins blockIdx.x * 64 + lane, rows
 // blockIdx.y * HX_RB + rr. Output block out[vi][r][k]; y, w indexed by the full view v.
-__global__ __launch_bounds__(HFP_THREADS) void k_hfp(HelixDev G, const float *__restrict__ x,
-                                                     const float *__restrict__ xT, size_t nvox, int vstart,
+// Cumulative form (blockIdx.y = 0: in0 -> out0, 1: in1 -> out1) of a volume [nz][ncol]: out[kz][c] =
+// (sum over k < kz of in[k][c], accumulated in FP64 and rounded once; in[kz][c]). One thread per column.
+__global__ __launch_bounds__(256) void k_hcum(const float *__restrict__ in0, const float *__restrict__ in1, int ncol,
+                                              int nz, float2 *__restrict__ out0, float2 *__restrict__ out1)
+{
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= ncol) return;
+    const float *__restrict__ in = blockIdx.y ? in1 : in0;
+    float2 *__restrict__ out = blockIdx.y ? out1 : out0;
+    double acc = 0.0;
+    for (int kz = 0; kz < nz; ++kz) {
+        const float v = in[(size_t)kz * ncol + c];
+        out[(size_t)kz * ncol + c] = make_float2((float)acc, v);
+        acc += (double)v;
+    }
+}
+
+__global__ __launch_bounds__(HFP_THREADS) void k_hfp(HelixDev G, const float2 *__restrict__ cz,
+                                                     const float2 *__restrict__ czT, size_t nvox, int vstart,
                                                      int vstride, int epi, int prescale,
                                                      const float *__restrict__ y, const float *__restrict__ w,
                                                      float mscale, float *__restrict__ out)
@@ -76,8 +96,8 @@ __global__ __launch_bounds__(HFP_THREADS) void k_hfp(HelixDev G, const float *__
 #pragma unroll
     for (int rr = 0; rr < HX_RB; ++rr) acc[rr] = 0.f;
     if (k < G.nb) {
-        const Ro<float> X{row ? x : xT, nvox};
-        hfp_lane(G, X, epi == HFP_WEIGHTED_ONES, v, k, r0, wave, HX_FW, acc);
+        const Ro<float2> C{row ? cz : czT, nvox};
+        hfp_lane(G, C, epi == HFP_WEIGHTED_ONES, v, k, r0, wave, HX_FW, acc);
     }
 #pragma unroll
     for (int rr = 0; rr < HX_RB; ++rr) part[wave][rr][lane] = acc[rr];
@@ -256,6 +276,8 @@ void free_helix(ct_helix *h)
     hx_free(&h->dl);
     hx_free(&h->zeta);
     hx_free(&h->r);
+    hx_free(&h->cz);
+    hx_free(&h->czT);
     hx_free(&h->red);
 }
 
@@ -269,6 +291,8 @@ ct_status ensure_views(ct_helix *h, int nv)
         h->r_cap = need;
     }
     CT_TRY(hx_alloc(&h->xta, h->nvox));
+    CT_TRY(hx_alloc(&h->cz, h->nvox));
+    CT_TRY(hx_alloc(&h->czT, h->nvox));
     CT_TRY(hx_alloc(&h->red, kRedSize));
     return CT_OK;
 }
@@ -289,14 +313,23 @@ ct_status subset_of(const ct_helix *h, int subset, int *vs, int *vst, int *nv)
     return CT_OK;
 }
 
-// prescale: write r' = scale secphi (epilogue value), the back-projector's input.
+// Forward projection of the volume x (xT its per-slice transpose): the cumulative forms of both layouts,
+// then the projection (the ones epilogue reads no volume and skips the first step). prescale: write
+// r' = scale secphi (epilogue value), the back-projector's input.
 hipError_t launch_hfp(const ct_helix *h, const float *x, const float *xT, int vs, int vst, int nv, int epi,
                       int prescale, const float *y, const float *w, float mscale, float *out, hipStream_t s)
 {
     const ct_helix_desc &d = h->desc;
+    if (epi != HFP_WEIGHTED_ONES) {
+        const int ncol = d.nx * d.ny;
+        hipLaunchKernelGGL(k_hcum, dim3((unsigned)((ncol + 255) / 256), 2), dim3(256), 0, s, x, xT, ncol, d.nz, h->cz,
+                           h->czT);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     const dim3 grid((unsigned)((d.nb + 63) / 64), (unsigned)((d.nr + HX_RB - 1) / HX_RB), (unsigned)nv);
-    hipLaunchKernelGGL(k_hfp, grid, dim3(HFP_THREADS), 0, s, h->dev, x, xT, h->nvox, vs, vst, epi, prescale, y, w,
-                       mscale, out);
+    hipLaunchKernelGGL(k_hfp, grid, dim3(HFP_THREADS), 0, s, h->dev, h->cz, h->czT, h->nvox, vs, vst, epi, prescale, y,
+                       w, mscale, out);
     return hipGetLastError();
 }
 

@@ -13,10 +13,12 @@
 // along the central ray and wr_r = w_r / (dsd dz). The weight is scale_k * secphi_rk * f_t * f_a.
 // Precision: overlaps are taken where FP32 rounding stays relative to a voxel, not to the volume. Along the
 // line the boundary crossings U_k reach hundreds of voxels, where FP32 would round them by 1e-5 voxel or
-// more; they are evaluated in FP64 from an FP64 table (the MI355X vector unit issues FP64 FMAs at the FP32
-// rate) and each overlap is formed in FP64 before it is rounded to FP32. Along z the view's source height is
-// split into an integer voxel index zai and a fraction zaf: voxel kz spans [kz - zai, kz - zai + 1] exactly,
-// and the row boundaries zaf + ell wr_r stay within a few tens of voxels.
+// more; they are evaluated in FP64 from an FP64 table, and the forward projector forms each overlap in
+// FP64, the back-projector each crossing relative to the column's edge, before rounding to FP32. Along z
+// the view's source height is split into an integer voxel index zai and a fraction zaf: voxel kz spans
+// [kz - zai, kz - zai + 1] exactly, and the row boundaries zaf + ell wr_r stay within a few tens of voxels.
+// The forward projector integrates a column along z from its cumulative form, whose partial sums are
+// accumulated in FP64 and rounded once.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -97,11 +99,32 @@ __host__ __device__ inline float column_depth(const HelixDev &G, bool row, float
     return fmaf(xc, cs.x, fmaf(yc, cs.y, G.dso));
 }
 
+// Point z of the view's z frame (voxel kz spans [kz - zai, kz - zai + 1]) as a voxel index and the fraction
+// above its lower face, clamped to the volume: below it (k, f) = (0, 0), above it (nz - 1, 1). The integer
+// part and the fraction are taken in the view's frame, where |z| stays within the cone, so f is exact.
+__host__ __device__ inline void hx_cum_point(float z, int zi, int nz, int &k, float &f)
+{
+    const float fl = floorf(z);
+    k = (int)fl + zi;
+    f = z - fl;
+    if (k < 0) {
+        k = 0;
+        f = 0.f;
+    } else if (k >= nz) {
+        k = nz - 1;
+        f = 1.f;
+    }
+}
+
 // Forward projection, one lane: bin k of view v, rows r0 .. r0 + HX_RB - 1 (rows >= nr are skipped),
-// lines l0, l0 + lstep, ... < NL. acc[rr] += f_t * sum_kz f_a * X(kz, line, q) over the lane's lines; the
-// caller multiplies by scale_k * secphi. X: the volume in the view's sweep layout [nz][NL][NQ] (x for row
-// sweep views, its per-slice transpose for the others); ones: every voxel is 1 (X is not read).
-__host__ __device__ inline void hfp_lane(const HelixDev &G, const Ro<float> &X, bool ones, int v, int k, int r0,
+// lines l0, l0 + lstep, ... < NL. acc[rr] += f_t * (integral of the column over the row's z interval) /
+// (row height) over the lane's lines; the caller multiplies by scale_k * secphi. Cz: the cumulative form of
+// the volume in the view's sweep layout [nz][NL][NQ] (x for row sweep views, its per-slice transpose for
+// the others): Cz[kz] = (sum of the column's voxels below kz, voxel kz), so that the column's integral from
+// the volume's lower face to height k + f is C = S_k + f X_k, and a row costs one evaluation of C at its
+// upper face (its lower face's value is the previous row's). ones: every voxel is 1 (C = k + f; Cz is not
+// read).
+__host__ __device__ inline void hfp_lane(const HelixDev &G, const Ro<float2> &Cz, bool ones, int v, int k, int r0,
                                          int l0, int lstep, float (&acc)[HX_RB])
 {
     const bool row = G.rowsweep[v] != 0;
@@ -109,9 +132,8 @@ __host__ __device__ inline void hfp_lane(const HelixDev &G, const Ro<float> &X, 
     const size_t bb = (size_t)v * (G.nb + 1) + k;
     const double2 b0 = G.bnd[bb], b1 = G.bnd[bb + 1];
     const float2 cs = G.cs[v];
-    const float zai = G.zai[v], zaf = G.zaf[v];
-    // the volume's voxels in the view's z coordinates: kz spans [kz - zai, kz - zai + 1]
-    const float zlo = -zai, zhi = (float)G.nz - zai;
+    const int zi = (int)G.zai[v];
+    const float zaf = G.zaf[v];
     float wr[HX_RB + 1];
 #pragma unroll
     for (int rr = 0; rr <= HX_RB; ++rr) wr[rr] = G.wr[(size_t)hx_min(r0 + rr, G.nr)];
@@ -131,24 +153,33 @@ __host__ __device__ inline void hfp_lane(const HelixDev &G, const Ro<float> &X, 
             const float ft = (float)(fmin(hi, e0 + 1.0) - fmax(lo, e0)) * invt;
             if (!(ft > 0.f)) continue;
             const float ell = column_depth(G, row, lc, q, cs);
-            const float inva = 1.f / (ell * G.dwn);
+            const float w = ft / (ell * G.dwn);
             const size_t col = (size_t)l * NQ + q;
-            float zp = fmaf(ell, wr[0], zaf);
+            int kp;
+            float fp;
+            hx_cum_point(fmaf(ell, wr[0], zaf), zi, G.nz, kp, fp);
+            float Cp = 0.f;
+            if (!ones) {
+                const float2 c = Cz[(size_t)kp * plane + col];
+                Cp = fmaf(fp, c.y, c.x);
+            }
 #pragma unroll
             for (int rr = 0; rr < HX_RB; ++rr) {
-                const float zn = fmaf(ell, wr[rr + 1], zaf);
-                if (r0 + rr < G.nr) {
-                    const int ka = (int)floorf(fmaxf(zp, zlo) + zai);
-                    const int kb = (int)ceilf(fminf(zn, zhi) + zai) - 1;
-                    float s = 0.f;
-                    for (int kz = ka; kz <= kb; ++kz) {
-                        const float z0 = (float)kz - zai;
-                        const float fa = fminf(zn, z0 + 1.f) - fmaxf(zp, z0);
-                        if (fa > 0.f) s = fmaf(fa, ones ? 1.f : X[(size_t)kz * plane + col], s);
-                    }
-                    acc[rr] = fmaf(ft * inva, s, acc[rr]);
+                int kn;
+                float fn;
+                hx_cum_point(fmaf(ell, wr[rr + 1], zaf), zi, G.nz, kn, fn);
+                float val;
+                if (ones) {
+                    val = (float)(kn - kp) + (fn - fp);
+                } else {
+                    const float2 c = Cz[(size_t)kn * plane + col];
+                    const float Cn = fmaf(fn, c.y, c.x);
+                    val = Cn - Cp;
+                    Cp = Cn;
                 }
-                zp = zn;
+                if (r0 + rr < G.nr) acc[rr] = fmaf(w, val, acc[rr]);
+                kp = kn;
+                fp = fn;
             }
         }
     }

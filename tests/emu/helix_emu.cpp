@@ -79,6 +79,21 @@ int hemu_forward(const ct_helix_desc *d, int vs, int vst, int nv, const float *x
         for (int i = 0; i < d->ny; ++i)
             for (int j = 0; j < d->nx; ++j)
                 xT[((size_t)kz * d->nx + j) * d->ny + i] = x[((size_t)kz * d->ny + i) * d->nx + j];
+    // the k_hcum pass: cumulative forms of both layouts (one thread per column)
+    const int ncol = d->nx * d->ny;
+    std::vector<float2> cz(nvox), czT(nvox);
+    for (int layout = 0; layout < 2; ++layout) {
+        const float *in = layout ? xT.data() : x;
+        float2 *out = layout ? czT.data() : cz.data();
+        for (int c = 0; c < ncol; ++c) {
+            double acc = 0.0;
+            for (int kz = 0; kz < d->nz; ++kz) {
+                const float v = in[(size_t)kz * ncol + c];
+                out[(size_t)kz * ncol + c] = make_float2((float)acc, v);
+                acc += (double)v;
+            }
+        }
+    }
     reset_oob();
     for (int vi = 0; vi < nv; ++vi) {
         const int v = vs + vi * vst;
@@ -87,7 +102,7 @@ int hemu_forward(const ct_helix_desc *d, int vs, int vst, int nv, const float *x
                 static float part[HX_FW][HX_RB][64];
                 const int r0 = by * HX_RB;
                 const bool row = G.rowsweep[v] != 0;
-                const Ro<float> X{row ? x : xT.data(), nvox};
+                const Ro<float2> X{row ? cz.data() : czT.data(), nvox};
                 for (int wave = 0; wave < HX_FW; ++wave)
                     for (int lane = 0; lane < 64; ++lane) {
                         const int k = bx * 64 + lane;
