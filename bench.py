@@ -443,6 +443,8 @@ def main():
     ap.add_argument("--niters", type=int, default=100)
     ap.add_argument("--t1hu-iters", type=int, default=500, help="iterations of the time-to-1-HU runs")
     ap.add_argument("--no-t1hu", action="store_true", help="skip the time-to-1-HU runs")
+    ap.add_argument("--no-held-out", action="store_true",
+                    help="skip the per-scan time-to-1-HU runs on every scan with an x* under tests/golden")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--cpu-iters-single", type=int, default=2, help="iterations of the one-thread oracle leg")
@@ -723,6 +725,52 @@ def main():
                 entry["seconds"] = round(timed(lambda: solve_m(M_, alpha, hit[0], start=start), 3), 5)
             t1hu[key] = entry
 
+    # Time to 1 HU on the held-out scans: every seed whose x* the oracle has written (all disjoint from the
+    # network's training seeds; seed 100 is the scan above), relaxed and unrelaxed at 12 subsets from the
+    # FBP-like and learned starts; per scan the iterations and seconds to 1 HU, and their median.
+    held_out = None
+    xfiles = sorted(f for f in os.listdir(os.path.dirname(XSTAR))
+                    if f.startswith("xstar_cfg2_seed") and f.endswith(".npz"))
+    if xfiles and not args.no_t1hu and not args.no_held_out:
+        held_out = {"scans": [], "median": {}}
+        starts_h = ("fbp", "learned") if net is not None else ("fbp",)
+        per_case = {}
+        for f in xfiles:
+            seed = int(f[len("xstar_cfg2_seed"):-len(".npz")])
+            sc = synth.noisy_scan(g, seed, truth=False)
+            yh, wh = torch.as_tensor(sc.y, device=dev), torch.as_tensor(sc.w, device=dev)
+            xref_h = torch.as_tensor(np.load(os.path.join(os.path.dirname(XSTAR), f))["x"], device=dev)
+            xh = torch.empty((g.ny, g.nx), device=dev)
+            row = {"seed": seed}
+            for alpha in (1.999, 1.0):
+                for start in starts_h:
+                    key = f"subsets=12,alpha={alpha},start={start}"
+                    p = api.Params(alpha=alpha, niters=args.t1hu_iters, subset_order=ORDER, start=start,
+                                   fov_radius=synth.fov_radius(g), unet=net if start == "learned" else None)
+                    try:
+                        rows = api.rlalm_solve(G12, p, yh, wh, xh, x_ref=xref_h, trace=True)
+                    except api.CtError as e:
+                        row[key] = {"iters": None, "diverged": str(e)[:120]}
+                        continue
+                    hit = [r["iter"] for r in rows if r["rmsd_hu"] <= 1.0]
+                    ent = {"iters": hit[0] if hit else None,
+                           "best_rmsd_hu": round(min(r["rmsd_hu"] for r in rows), 3)}
+                    if hit:
+                        ph = api.Params(alpha=alpha, niters=hit[0], subset_order=ORDER, start=start,
+                                        unet=net if start == "learned" else None)
+                        api.rlalm_solve(G12, ph, yh, wh, xh)
+                        ent["seconds"] = round(timed(lambda: api.rlalm_solve(G12, ph, yh, wh, xh), 3), 5)
+                    row[key] = ent
+                    per_case.setdefault(key, []).append(ent)
+            held_out["scans"].append(row)
+            print(f"held-out scan {seed}: {row}", flush=True)
+        for key, ents in per_case.items():
+            its = [e["iters"] for e in ents if e.get("iters") is not None]
+            secs = [e["seconds"] for e in ents if e.get("seconds") is not None]
+            held_out["median"][key] = {"scans": len(ents), "reached_1hu": len(its),
+                                       "iters": float(np.median(its)) if its else None,
+                                       "seconds": round(float(np.median(secs)), 5) if secs else None}
+
     # The paper's comparison of relaxations (Section IV): proposed (Algorithm 1) vs simple (Algorithm 2)
     # relaxation at alpha 1.999 vs unrelaxed, each with the continuation rho_k(alpha) and with a fixed
     # rho = 0.05, 12 subsets, FBP-like start: RMSD to x* by iteration.
@@ -806,6 +854,7 @@ def main():
         "unet": unet_line,
         "wall_s": round(wall, 3),
         "time_to_1hu": t1hu,
+        "time_to_1hu_held_out": held_out,
         "relaxation_rmsd_hu_12_subsets": relax,
         "ablations_rmsd_hu": ablate,
         "roofline": roofline,
