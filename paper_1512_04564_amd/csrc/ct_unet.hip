@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "ct_internal.hpp"
+#include "ct_unet_plan.hpp"
 #include "../../include/ct_unet.h"
 
 namespace ct {
@@ -33,11 +34,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kLayers = 15;
-// (c_in, c_out, kernel) in canonical order
-constexpr int kShape[kLayers][3] = {{1, 32, 3},    {32, 32, 3},   {32, 64, 3},   {64, 64, 3},   {64, 128, 3},
-                                    {128, 128, 3}, {128, 256, 3}, {256, 256, 3}, {384, 128, 3}, {128, 128, 3},
-                                    {192, 64, 3},  {64, 64, 3},   {96, 32, 3},   {32, 32, 3},   {32, 1, 1}};
+using unet_plan::kLayers;
+using unet_plan::kShape;
 
 // Input channels [0, c0) come from src0 (c0 channels; half resolution when up0), [c0, c0 + c1) from
 // src1 (c1 channels, full resolution).
@@ -391,31 +389,107 @@ __global__ __launch_bounds__(64) void k_conv3x3_wgrad(ConvSrc S, const bf16 *__r
             }
 }
 
+// Weight gradient partials of a 3x3 convolution, all nine taps per workgroup, for images whose width is a
+// multiple of 64: part[split][c_out][tap][c_in] over the split's 64-pixel row segments [split * cps,
+// min((split + 1) * cps, segments)). Workgroup = 4 waves = the 2 x 2 16 x 16 tiles of a 32 (c_out) x 32
+// (c_in) block, grid (splits, (c_out / 32) * (c_in / 32)). Per segment the output gradient (32 channels x
+// 64 pixels) and the input rows y - 1, y, y + 1 over the segment's pixels with one halo pixel on each side
+// are staged in LDS, transposed to pixel-contiguous rows (the matrix cores take 8 consecutive pixels of
+// one channel per lane). A wave reads its A operand once per 32-pixel K-step and, per input row, one
+// window of 10 pixels per lane, from which the three horizontal taps' B operands come: pixels 0-7 (dx = -1),
+// 1-8 (a 16-bit shift across the window's words, dx = 0) and 2-9 (dx = +1).
+__global__ __launch_bounds__(256) void k_conv3x3_wgrad9(ConvSrc S, const bf16 *__restrict__ dz, int cout, int n,
+                                                        int h, int w, int cps, float *__restrict__ part)
+{
+    constexpr int LD = 72;   // padded LDS row (bf16): 144 bytes keeps rows 16-byte aligned; 66 pixels used
+    __shared__ __attribute__((aligned(16))) bf16 sA[32 * LD];       // [c_out][pixel]
+    __shared__ __attribute__((aligned(16))) bf16 sB[3 * 32 * LD];   // [input row][c_in][halo pixel]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int cin = S.c0 + S.c1;
+    const int nci = cin / 32;
+    const int co0 = (blockIdx.y / nci) * 32, ci0 = (blockIdx.y % nci) * 32;
+    const int segs_row = w / 64, nseg = n * h * segs_row;
+    const int s0 = blockIdx.x * cps, s1 = min(s0 + cps, nseg);
+    const int g = lane >> 4, r = lane & 15;
+    const int mt = wave & 1, qt = wave >> 1;   // the wave's c_out and c_in 16-tiles
+    f32x4 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16x8 zero8 = {};
+    for (int sg = s0; sg < s1; ++sg) {
+        const int row = sg / segs_row, px0 = (sg - row * segs_row) * 64;
+        const int pn = row / h, py = row - pn * h;
+        {   // output gradient: thread -> (pixel tid / 4, channels 8 (tid % 4) ..), 64 x 4 pieces
+            const int q = tid >> 2, c8 = (tid & 3) * 8;
+            const bf16x8 v =
+                *reinterpret_cast<const bf16x8 *>(dz + (((size_t)pn * h + py) * w + px0 + q) * cout + co0 + c8);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) sA[(c8 + i) * LD + q] = v[i];
+        }
+        // input rows: 3 rows x 66 pixels x 4 channel groups
+        for (int idx = tid; idx < 3 * 66 * 4; idx += 256) {
+            const int c8 = (idx & 3) * 8, pr = idx >> 2;
+            const int ry = pr / 66, j = pr - ry * 66;
+            const int yy = py + ry - 1, xx = px0 + j - 1;
+            const bool ok = yy >= 0 && yy < h && xx >= 0 && xx < w;
+            const bf16x8 v = ok ? *reinterpret_cast<const bf16x8 *>(src_ptr(S, ci0, pn, yy, xx, h, w) + c8) : zero8;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) sB[(ry * 32 + c8 + i) * LD + j] = v[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(sA + (16 * mt + r) * LD + 32 * kk + 8 * g);
+#pragma unroll
+            for (int ry = 0; ry < 3; ++ry) {
+                const bf16 *wp = sB + (ry * 32 + 16 * qt + r) * LD + 32 * kk + 8 * g;
+                const uint4 w0 = *reinterpret_cast<const uint4 *>(wp);
+                const unsigned w4 = *reinterpret_cast<const unsigned *>(wp + 8);
+                const uint4 bc = {__builtin_amdgcn_alignbit(w0.y, w0.x, 16), __builtin_amdgcn_alignbit(w0.z, w0.y, 16),
+                                  __builtin_amdgcn_alignbit(w0.w, w0.z, 16), __builtin_amdgcn_alignbit(w4, w0.w, 16)};
+                const uint4 bp = {w0.y, w0.z, w0.w, w4};
+                acc[3 * ry] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, w0), acc[3 * ry], 0,
+                                                                      0, 0);
+                acc[3 * ry + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, bc),
+                                                                          acc[3 * ry + 1], 0, 0, 0);
+                acc[3 * ry + 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, bp),
+                                                                          acc[3 * ry + 2], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int co = co0 + 16 * mt + 4 * g + j, ci = ci0 + 16 * qt + r;
+            part[(((size_t)blockIdx.x * cout + co) * 9 + t) * cin + ci] = acc[t][j];
+        }
+}
+
 // grad[co][ci][dy][dx] (canonical) = sum over splits of part[split][co][tap][ci]: 32 outputs per workgroup,
-// 8 lanes over the splits (k = lane, lane + 8, ...), their sums added in lane order.
+// consecutive in the partials' layout (so that each split's reads are coalesced; the one write per output
+// goes to its canonical place), 8 lanes over the splits (k = lane, lane + 8, ...), added in lane order.
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float *__restrict__ part, int nsplit, int cout, int cin,
                                                       float *__restrict__ grad)
 {
     __shared__ float red[8][32];
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    const size_t i = (size_t)blockIdx.x * 32 + tx;   // canonical index
+    const size_t o = (size_t)blockIdx.x * 32 + tx;   // index in [c_out][tap][c_in]
     const size_t total = (size_t)cout * cin * 9;
     float s = 0.f;
-    if (i < total) {
-        const int tap = (int)(i % 9);
-        const int ci = (int)((i / 9) % cin);
-        const int co = (int)(i / (9 * (size_t)cin));
-        const size_t stride = (size_t)cout * 9 * cin;
-        const size_t o = ((size_t)co * 9 + tap) * cin + ci;
-        for (int k = ty; k < nsplit; k += 8) s += part[k * stride + o];
-    }
+    if (o < total)
+        for (int k = ty; k < nsplit; k += 8) s += part[(size_t)k * total + o];
     red[ty][tx] = s;
     __syncthreads();
-    if (ty == 0 && i < total) {
+    if (ty == 0 && o < total) {
         float t = red[0][tx];
 #pragma unroll
         for (int l = 1; l < 8; ++l) t += red[l][tx];
-        grad[i] = t;
+        const int ci = (int)(o % cin);
+        const int tap = (int)((o / cin) % 9);
+        const int co = (int)(o / (9 * (size_t)cin));
+        grad[((size_t)co * cin + ci) * 9 + tap] = t;
     }
 }
 
@@ -445,8 +519,7 @@ __global__ __launch_bounds__(256) void k_bias_part(const bf16 *__restrict__ dz, 
     }
 }
 
-// Pixels per bias-gradient split for c channels: 32 loads per thread.
-constexpr int bias_pps(int c) { return 32 * (2048 / c); }
+using unet_plan::bias_pps;
 
 // out[i] = sum over k of part[k * n + i]: 32 outputs per workgroup, 8 lanes over the splits (k = lane,
 // lane + 8, ...), their sums added in lane order.
@@ -845,43 +918,15 @@ ct_status check_shape(const ct_unet *u, int n, int h, int w)
     return CT_OK;
 }
 
-int splits_for(size_t npix, size_t tiles)
-{
-    // about 8192 single-wave workgroups (32 per CU: the chunk loop waits on its loads and barriers, so
-    // occupancy hides it), at least 512 pixels per split
-    size_t sp = std::max<size_t>(1, std::min<size_t>(npix / 512, (8192 + tiles - 1) / tiles));
-    return (int)std::min<size_t>(sp, 1024);
-}
-
-// Split geometry of a weight-gradient launch: pixels per split (multiple of 64) and split count.
-void wgrad_splits(size_t npix, int cin, int cout, int *pps, int *nsp)
-{
-    const size_t tiles = (size_t)9 * (cout / 32) * (cin / 32);
-    const int ns = splits_for(npix, tiles);
-    *pps = (int)(((npix + ns - 1) / ns + 63) / 64 * 64);
-    *nsp = (int)((npix + *pps - 1) / *pps);
-}
-
-constexpr int kOutPps = 4096, kInPps = 2048;
-constexpr int kLevel[kLayers] = {0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0, 0};
+using unet_plan::kInPps;
+using unet_plan::kLevel;
+using unet_plan::kOutPps;
+using unet_plan::wgrad9_splits;
+using unet_plan::wgrad_splits;
 
 // Largest partial-sum request of any backward launch for batches up to max_n x max_h x max_w. Every
 // request grows with the pixel count, so the maximum batch bounds all smaller ones.
-size_t part_need(const ct_unet *u)
-{
-    const size_t P1 = (size_t)u->max_n * u->max_h * u->max_w;
-    size_t need = 0;
-    for (int l = 1; l < kLayers - 1; ++l) {
-        const size_t np = P1 >> (2 * kLevel[l]);
-        // the split count of any smaller batch is at most splits_for() at the maximum one
-        const size_t ns = (size_t)splits_for(np, (size_t)9 * (kShape[l][1] / 32) * (kShape[l][0] / 32));
-        need = std::max(need, ns * kShape[l][1] * 9 * kShape[l][0]);
-        need = std::max(need, ((np + bias_pps(kShape[l][1]) - 1) / bias_pps(kShape[l][1])) * (size_t)kShape[l][1]);
-    }
-    need = std::max(need, ((P1 + kOutPps - 1) / kOutPps) * 33);
-    need = std::max(need, ((P1 + kInPps - 1) / kInPps) * 320);
-    return need;
-}
+size_t part_need(const ct_unet *u) { return unet_plan::part_need(u->max_n, u->max_h, u->max_w); }
 
 ct_status alloc_train(ct_unet *u)
 {
@@ -1007,11 +1052,20 @@ ct_status conv_wgrad(ct_unet *u, int l, const ConvSrc &S, const bf16 *dz, int n,
 {
     const int cin = kShape[l][0], cout = kShape[l][1];
     const size_t npix = (size_t)n * h * w;
-    int pps, nsp;
-    wgrad_splits(npix, cin, cout, &pps, &nsp);
-    CT_TRY(ensure_part(u, (size_t)nsp * cout * 9 * cin));
-    hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(nsp, 9, (cout / 32) * (cin / 32)), dim3(64), 0, s, S, dz, cout, n, h, w, pps,
-                       u->part);
+    int nsp;
+    if (w % 64 == 0) {   // whole 64-pixel row segments: the nine-tap form
+        int cps;
+        wgrad9_splits(npix, cin, cout, &cps, &nsp);
+        CT_TRY(ensure_part(u, (size_t)nsp * cout * 9 * cin));
+        hipLaunchKernelGGL(k_conv3x3_wgrad9, dim3(nsp, (cout / 32) * (cin / 32)), dim3(256), 0, s, S, dz, cout, n, h, w,
+                           cps, u->part);
+    } else {
+        int pps;
+        wgrad_splits(npix, cin, cout, &pps, &nsp);
+        CT_TRY(ensure_part(u, (size_t)nsp * cout * 9 * cin));
+        hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(nsp, 9, (cout / 32) * (cin / 32)), dim3(64), 0, s, S, dz, cout, n, h, w,
+                           pps, u->part);
+    }
     CT_HIP_CHECK(hipGetLastError());
     const size_t nw = (size_t)cout * cin * 9;
     hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(nw, 32)), dim3(256), 0, s, u->part, nsp, cout, cin, u->grad + u->off[l]);
