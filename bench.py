@@ -697,18 +697,26 @@ def main():
         t1hu = {}
         geoms = {41: G, 12: G12, 4: api.Geometry(g.replace(nsubsets=4))}
 
-        def solve_m(M_, alpha, niters, xref=None, trace=False, start="zero"):
+        def solve_m(M_, alpha, niters, xref=None, trace=False, start="zero", **kw):
             p = api.Params(alpha=alpha, niters=niters, subset_order=ORDER, start=start,
-                           fov_radius=synth.fov_radius(g), unet=net if start == "learned" else None)
+                           fov_radius=synth.fov_radius(g), unet=net if start == "learned" else None, **kw)
             return api.rlalm_solve(geoms[M_], p, y, w, x, x_ref=xref, trace=trace)
 
         starts = ("zero", "fbp", "learned") if net is not None else ("zero", "fbp")
-        cases = [(M_, a, st) for M_ in (12, 4) for a in (1.999, 1.0) for st in starts]
-        cases += [(41, 1.999, "fbp"), (41, 1.0, "fbp")]
-        for M_, alpha, start in cases:
+        cases = [(M_, a, st, {}) for M_ in (12, 4) for a in (1.999, 1.0) for st in starts]
+        cases += [(41, 1.999, "fbp", {}), (41, 1.0, "fbp", {})]
+        # the relaxed 12-subset method with the supplement's variants: the maximum-curvature D_R (omega = 1
+        # in place of the Huber curvature), the full-gradient initialisation, and both
+        cases += [(12, 1.999, "fbp", {"huber": False}), (12, 1.999, "fbp", {"init_full": True}),
+                  (12, 1.999, "fbp", {"huber": False, "init_full": True})]
+        for M_, alpha, start, kw in cases:
             key = f"subsets={M_},alpha={alpha},start={start}"
+            if kw.get("huber") is False:
+                key += ",D_R=maximum curvature"
+            if kw.get("init_full"):
+                key += ",init=full gradient"
             try:
-                rows = solve_m(M_, alpha, args.t1hu_iters, xref=xstar, trace=True, start=start)
+                rows = solve_m(M_, alpha, args.t1hu_iters, xref=xstar, trace=True, start=start, **kw)
             except api.CtError as e:   # the traced solve stopped: cost growth or non-finite values
                 rows = getattr(e, "rows", [])
                 t1hu[key] = {"iters": None, "diverged": str(e)[:160],
@@ -721,8 +729,8 @@ def main():
                      "rmsd_hu_at": {str(r["iter"]): round(r["rmsd_hu"], 2) for r in rows
                                     if r["iter"] in (1, 2, 5, 10, 20, 50, 100, 200, 300, 500)}}
             if hit:
-                solve_m(M_, alpha, hit[0], start=start)
-                entry["seconds"] = round(timed(lambda: solve_m(M_, alpha, hit[0], start=start), 3), 5)
+                solve_m(M_, alpha, hit[0], start=start, **kw)
+                entry["seconds"] = round(timed(lambda: solve_m(M_, alpha, hit[0], start=start, **kw), 3), 5)
             t1hu[key] = entry
 
     # Time to 1 HU on the held-out scans: every seed whose x* the oracle has written (all disjoint from the

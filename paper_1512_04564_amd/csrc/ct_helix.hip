@@ -41,7 +41,7 @@ struct ct_helix {
     size_t nvox = 0;
     float *xa = nullptr, *xb = nullptr, *xta = nullptr, *xtb = nullptr;
     float *gv = nullptr, *h = nullptr, *dl = nullptr, *zeta = nullptr;
-    float2 *cz = nullptr, *czT = nullptr;   // cumulative forms of the projected volume (both layouts)
+    float2 *cz = nullptr, *czT = nullptr;   // cumulative forms of the projected volume (both layouts, padded)
     float *r = nullptr;
     size_t r_cap = 0;
     double *red = nullptr;
@@ -62,8 +62,9 @@ constexpr int HUPD_T = 16;         // update tile edge
 
 // Forward projection of views vstart + vi * vstride (vi = blockIdx.z). Bins blockIdx.x * 64 + lane, rows
 // blockIdx.y * HX_RB + rr. Output block out[vi][r][k]; y, w indexed by the full view v.
-// Cumulative form (blockIdx.y = 0: in0 -> out0, 1: in1 -> out1) of a volume [nz][ncol]: out[kz][c] =
-// (sum over k < kz of in[k][c], accumulated in FP64 and rounded once; in[kz][c]). One thread per column.
+// Cumulative form (blockIdx.y = 0: in0 -> out0, 1: in1 -> out1) of a volume [nz][ncol], padded by one plane
+// on each side: out[kz + 1][c] = (sum over k < kz of in[k][c], accumulated in FP64 and rounded once;
+// in[kz][c]), out[0][c] = (0, 0), out[nz + 1][c] = (the column's sum, 0). One thread per column.
 __global__ __launch_bounds__(256) void k_hcum(const float *__restrict__ in0, const float *__restrict__ in1, int ncol,
                                               int nz, float2 *__restrict__ out0, float2 *__restrict__ out1)
 {
@@ -72,13 +73,16 @@ __global__ __launch_bounds__(256) void k_hcum(const float *__restrict__ in0, con
     const float *__restrict__ in = blockIdx.y ? in1 : in0;
     float2 *__restrict__ out = blockIdx.y ? out1 : out0;
     double acc = 0.0;
+    out[c] = make_float2(0.f, 0.f);
     for (int kz = 0; kz < nz; ++kz) {
         const float v = in[(size_t)kz * ncol + c];
-        out[(size_t)kz * ncol + c] = make_float2((float)acc, v);
+        out[(size_t)(kz + 1) * ncol + c] = make_float2((float)acc, v);
         acc += (double)v;
     }
+    out[(size_t)(nz + 1) * ncol + c] = make_float2((float)acc, 0.f);
 }
 
+template <bool ONES>
 __global__ __launch_bounds__(HFP_THREADS) void k_hfp(HelixDev G, const float2 *__restrict__ cz,
                                                      const float2 *__restrict__ czT, size_t nvox, int vstart,
                                                      int vstride, int epi, int prescale,
@@ -96,8 +100,8 @@ __global__ __launch_bounds__(HFP_THREADS) void k_hfp(HelixDev G, const float2 *_
 #pragma unroll
     for (int rr = 0; rr < HX_RB; ++rr) acc[rr] = 0.f;
     if (k < G.nb) {
-        const Ro<float2> C{row ? cz : czT, nvox};
-        hfp_lane(G, C, epi == HFP_WEIGHTED_ONES, v, k, r0, wave, HX_FW, acc);
+        const Ro<float2> C{row ? cz : czT, nvox + 2 * (size_t)G.nx * G.ny};   // padded by two planes
+        hfp_lane<ONES>(G, C, v, k, r0, wave, HX_FW, acc);
     }
 #pragma unroll
     for (int rr = 0; rr < HX_RB; ++rr) part[wave][rr][lane] = acc[rr];
@@ -291,8 +295,9 @@ ct_status ensure_views(ct_helix *h, int nv)
         h->r_cap = need;
     }
     CT_TRY(hx_alloc(&h->xta, h->nvox));
-    CT_TRY(hx_alloc(&h->cz, h->nvox));
-    CT_TRY(hx_alloc(&h->czT, h->nvox));
+    const size_t ncz = h->nvox + 2 * (size_t)h->desc.nx * h->desc.ny;   // two padding planes
+    CT_TRY(hx_alloc(&h->cz, ncz));
+    CT_TRY(hx_alloc(&h->czT, ncz));
     CT_TRY(hx_alloc(&h->red, kRedSize));
     return CT_OK;
 }
@@ -328,8 +333,12 @@ hipError_t launch_hfp(const ct_helix *h, const float *x, const float *xT, int vs
         if (e != hipSuccess) return e;
     }
     const dim3 grid((unsigned)((d.nb + 63) / 64), (unsigned)((d.nr + HX_RB - 1) / HX_RB), (unsigned)nv);
-    hipLaunchKernelGGL(k_hfp, grid, dim3(HFP_THREADS), 0, s, h->dev, h->cz, h->czT, h->nvox, vs, vst, epi, prescale, y,
-                       w, mscale, out);
+    if (epi == HFP_WEIGHTED_ONES)
+        hipLaunchKernelGGL(k_hfp<true>, grid, dim3(HFP_THREADS), 0, s, h->dev, h->cz, h->czT, h->nvox, vs, vst, epi,
+                           prescale, y, w, mscale, out);
+    else
+        hipLaunchKernelGGL(k_hfp<false>, grid, dim3(HFP_THREADS), 0, s, h->dev, h->cz, h->czT, h->nvox, vs, vst, epi,
+                           prescale, y, w, mscale, out);
     return hipGetLastError();
 }
 

@@ -85,6 +85,17 @@ struct HelixDev {
 
 __host__ __device__ inline int hx_min(int a, int b) { return a < b ? a : b; }
 
+// Approximate reciprocal (one ulp on the device), for weights and candidate ranges.
+__host__ __device__ inline float hx_rcp(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.f / x;
+#endif
+}
+
+
 // Rows per forward-projection workgroup and waves per forward workgroup; voxels per back-projection thread.
 constexpr int HX_RB = 8;
 constexpr int HX_FW = 4;
@@ -116,16 +127,21 @@ __host__ __device__ inline void hx_cum_point(float z, int zi, int nz, int &k, fl
     }
 }
 
+__host__ __device__ inline int hx_clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
 // Forward projection, one lane: bin k of view v, rows r0 .. r0 + HX_RB - 1 (rows >= nr are skipped),
 // lines l0, l0 + lstep, ... < NL. acc[rr] += f_t * (integral of the column over the row's z interval) /
 // (row height) over the lane's lines; the caller multiplies by scale_k * secphi. Cz: the cumulative form of
-// the volume in the view's sweep layout [nz][NL][NQ] (x for row sweep views, its per-slice transpose for
-// the others): Cz[kz] = (sum of the column's voxels below kz, voxel kz), so that the column's integral from
-// the volume's lower face to height k + f is C = S_k + f X_k, and a row costs one evaluation of C at its
-// upper face (its lower face's value is the previous row's). ones: every voxel is 1 (C = k + f; Cz is not
-// read).
-__host__ __device__ inline void hfp_lane(const HelixDev &G, const Ro<float2> &Cz, bool ones, int v, int k, int r0,
-                                         int l0, int lstep, float (&acc)[HX_RB])
+// the volume in the view's sweep layout (x for row sweep views, its per-slice transpose for the others),
+// padded by one plane on each side: Cz[kz + 1][col] = (sum of the column's voxels below kz, voxel kz) for
+// kz in [0, nz), Cz[0] = (0, 0) and Cz[nz + 1] = (column sum, 0). The column's integral from the volume's
+// lower face to height k + f is then C = S + f X at the index clamped to [-1, nz] (one integer clamp: the
+// padding planes give 0 below the volume and the column sum above it), and a row costs one evaluation of
+// C at its upper face (its lower face's value is the previous row's). ONES: every voxel is 1 (C = k + f
+// clamped to [0, nz]; Cz is not read).
+template <bool ONES>
+__host__ __device__ inline void hfp_lane(const HelixDev &G, const Ro<float2> &Cz, int v, int k, int r0, int l0,
+                                         int lstep, float (&acc)[HX_RB])
 {
     const bool row = G.rowsweep[v] != 0;
     const int NL = row ? G.ny : G.nx, NQ = row ? G.nx : G.ny;
@@ -139,13 +155,14 @@ __host__ __device__ inline void hfp_lane(const HelixDev &G, const Ro<float2> &Cz
     for (int rr = 0; rr <= HX_RB; ++rr) wr[rr] = G.wr[(size_t)hx_min(r0 + rr, G.nr)];
     const double halfq = 0.5 * (double)NQ, cl = 0.5 * (double)(NL - 1);
     const size_t plane = (size_t)NL * NQ;
+    const float rdwn = 1.f / G.dwn;
     for (int l = l0; l < NL; l += lstep) {
         const double lcd = (double)l - cl;
         const float lc = (float)lcd;
         const double ua = fma(lcd, b0.y, b0.x), ub = fma(lcd, b1.y, b1.x);
         const double lo = fmin(ua, ub), hi = fmax(ua, ub);
         if (!(hi > lo)) continue;
-        const float invt = 1.f / (float)(hi - lo);
+        const float invt = hx_rcp((float)(hi - lo));
         const int qa = (int)floor(fmax(lo + halfq, 0.0));
         const int qb = (int)ceil(fmin(hi + halfq, (double)NQ)) - 1;
         for (int q = qa; q <= qb; ++q) {
@@ -153,33 +170,35 @@ __host__ __device__ inline void hfp_lane(const HelixDev &G, const Ro<float2> &Cz
             const float ft = (float)(fmin(hi, e0 + 1.0) - fmax(lo, e0)) * invt;
             if (!(ft > 0.f)) continue;
             const float ell = column_depth(G, row, lc, q, cs);
-            const float w = ft / (ell * G.dwn);
+            const float w = ft * rdwn * hx_rcp(ell);
             const size_t col = (size_t)l * NQ + q;
-            int kp;
-            float fp;
-            hx_cum_point(fmaf(ell, wr[0], zaf), zi, G.nz, kp, fp);
-            float Cp = 0.f;
-            if (!ones) {
-                const float2 c = Cz[(size_t)kp * plane + col];
-                Cp = fmaf(fp, c.y, c.x);
-            }
+            if (ONES) {
+                int kp;
+                float fp;
+                hx_cum_point(fmaf(ell, wr[0], zaf), zi, G.nz, kp, fp);
 #pragma unroll
-            for (int rr = 0; rr < HX_RB; ++rr) {
-                int kn;
-                float fn;
-                hx_cum_point(fmaf(ell, wr[rr + 1], zaf), zi, G.nz, kn, fn);
-                float val;
-                if (ones) {
-                    val = (float)(kn - kp) + (fn - fp);
-                } else {
-                    const float2 c = Cz[(size_t)kn * plane + col];
-                    const float Cn = fmaf(fn, c.y, c.x);
-                    val = Cn - Cp;
+                for (int rr = 0; rr < HX_RB; ++rr) {
+                    int kn;
+                    float fn;
+                    hx_cum_point(fmaf(ell, wr[rr + 1], zaf), zi, G.nz, kn, fn);
+                    if (r0 + rr < G.nr) acc[rr] = fmaf(w, (float)(kn - kp) + (fn - fp), acc[rr]);
+                    kp = kn;
+                    fp = fn;
+                }
+            } else {
+                auto cum = [&](float z) {
+                    const float fl = floorf(z);
+                    const int kk = hx_clampi((int)fl + zi, -1, G.nz);
+                    const float2 c = Cz[(size_t)(kk + 1) * plane + col];
+                    return fmaf(z - fl, c.y, c.x);
+                };
+                float Cp = cum(fmaf(ell, wr[0], zaf));
+#pragma unroll
+                for (int rr = 0; rr < HX_RB; ++rr) {
+                    const float Cn = cum(fmaf(ell, wr[rr + 1], zaf));
+                    if (r0 + rr < G.nr) acc[rr] = fmaf(w, Cn - Cp, acc[rr]);
                     Cp = Cn;
                 }
-                if (r0 + rr < G.nr) acc[rr] = fmaf(w, val, acc[rr]);
-                kp = kn;
-                fp = fn;
             }
         }
     }
@@ -191,16 +210,6 @@ __host__ __device__ inline void hfp_lane(const HelixDev &G, const Ro<float2> &Cz
 __host__ __device__ inline float hx_prescale(const HelixDev &G, int v, int r, int k)
 {
     return G.scale[(size_t)v * G.nb + k] * G.secphi[(size_t)r * G.nb + k];
-}
-
-// Approximate reciprocal (one ulp on the device), for weights and candidate ranges.
-__host__ __device__ inline float hx_rcp(float x)
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    return __builtin_amdgcn_rcpf(x);
-#else
-    return 1.f / x;
-#endif
 }
 
 __host__ __device__ inline float hx_clamp01(float x) { return fminf(fmaxf(x, 0.f), 1.f); }

@@ -79,19 +79,22 @@ int hemu_forward(const ct_helix_desc *d, int vs, int vst, int nv, const float *x
         for (int i = 0; i < d->ny; ++i)
             for (int j = 0; j < d->nx; ++j)
                 xT[((size_t)kz * d->nx + j) * d->ny + i] = x[((size_t)kz * d->ny + i) * d->nx + j];
-    // the k_hcum pass: cumulative forms of both layouts (one thread per column)
+    // the k_hcum pass: padded cumulative forms of both layouts (one thread per column)
     const int ncol = d->nx * d->ny;
-    std::vector<float2> cz(nvox), czT(nvox);
+    const size_t ncz = nvox + 2 * (size_t)ncol;
+    std::vector<float2> cz(ncz), czT(ncz);
     for (int layout = 0; layout < 2; ++layout) {
         const float *in = layout ? xT.data() : x;
         float2 *out = layout ? czT.data() : cz.data();
         for (int c = 0; c < ncol; ++c) {
             double acc = 0.0;
+            out[c] = make_float2(0.f, 0.f);
             for (int kz = 0; kz < d->nz; ++kz) {
                 const float v = in[(size_t)kz * ncol + c];
-                out[(size_t)kz * ncol + c] = make_float2((float)acc, v);
+                out[(size_t)(kz + 1) * ncol + c] = make_float2((float)acc, v);
                 acc += (double)v;
             }
+            out[(size_t)(d->nz + 1) * ncol + c] = make_float2((float)acc, 0.f);
         }
     }
     reset_oob();
@@ -102,13 +105,13 @@ int hemu_forward(const ct_helix_desc *d, int vs, int vst, int nv, const float *x
                 static float part[HX_FW][HX_RB][64];
                 const int r0 = by * HX_RB;
                 const bool row = G.rowsweep[v] != 0;
-                const Ro<float2> X{row ? cz.data() : czT.data(), nvox};
+                const Ro<float2> X{row ? cz.data() : czT.data(), ncz};
                 for (int wave = 0; wave < HX_FW; ++wave)
                     for (int lane = 0; lane < 64; ++lane) {
                         const int k = bx * 64 + lane;
                         float acc[HX_RB];
                         for (int rr = 0; rr < HX_RB; ++rr) acc[rr] = 0.f;
-                        if (k < G.nb) hfp_lane(G, X, false, v, k, r0, wave, HX_FW, acc);
+                        if (k < G.nb) hfp_lane<false>(G, X, v, k, r0, wave, HX_FW, acc);
                         for (int rr = 0; rr < HX_RB; ++rr) part[wave][rr][lane] = acc[rr];
                     }
                 for (int idx = 0; idx < HX_RB * 64; ++idx) {
