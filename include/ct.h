@@ -224,8 +224,9 @@ ct_status ct_cost(ct_geom *g, const ct_rlalm_params *p, const void *y, const voi
  *     on exit). p applies to every slice; trace and time_kernels are not available here (CT_ERR_UNSUPPORTED).
  *   autotune: 0 = lockstep with the default shape (16-wave projection workgroups, slices in the given
  *     order; with n == 1 the result equals ct_rlalm_solve bit for bit); 1 = time the candidates on this
- *     set of slice shapes -- lockstep with 8 or 16 waves per projection workgroup, persistent with 1, 2 or
- *     4 resident workgroups per CU, each with the slices in the given order or largest first -- and keep
+ *     set of slice shapes -- lockstep with 8 or 16 waves per projection workgroup, each with the forward
+ *     split never and always (when p->forward_split is -1), persistent with 1, 2 or 4 resident workgroups
+ *     per CU, each with the slices in the given order or largest first -- and keep
  *     the fastest, cached per process and on disk (a text file per GPU architecture and shape set under
  *     $CTRLALM_TUNE_DIR, else $XDG_CACHE_HOME/ctrlalm/tune, else ~/.cache/ctrlalm/tune); 2 = persistent,
  *     its candidates (1, 2 or 4 workgroups per CU, either slice order) timed on this batch and the fastest
@@ -243,6 +244,8 @@ typedef struct {
     double ms_subiteration;/* timed cost of one batched subiteration (tuned shapes; else 0)           */
     int persistent;        /* 1: the persistent single-launch form                                   */
     int blocks_per_cu;     /* persistent form: resident workgroups per CU                            */
+    int forward_split;     /* lockstep forward launch: -1 automatic, 0 never, 1 always split each     */
+                           /* block's lines over two workgroups (a solve's own forward_split wins)     */
 } ct_batch_config;
 ct_status ct_rlalm_solve_batched(ct_geom *const *g, int n, const ct_rlalm_params *p, const void *const *y,
                                  const void *const *w, float *const *x, int autotune, ct_batch_config *chosen,

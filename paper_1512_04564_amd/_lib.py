@@ -60,7 +60,7 @@ class KernelTimes(ctypes.Structure):
 
 class BatchConfig(ctypes.Structure):
     _fields_ = [("fp_waves", ctypes.c_int), ("largest_first", ctypes.c_int), ("ms_subiteration", ctypes.c_double),
-                ("persistent", ctypes.c_int), ("blocks_per_cu", ctypes.c_int)]
+                ("persistent", ctypes.c_int), ("blocks_per_cu", ctypes.c_int), ("forward_split", ctypes.c_int)]
 
 
 class TraceRow(ctypes.Structure):

@@ -232,7 +232,7 @@ def rlalm_solve_batched(geoms, p: Params, ys, ws, xs, *, autotune=False, stream=
     ``autotune``: False / 0 lockstep default shape, True / 1 tuned (lockstep or persistent), 2 or
     "persistent" the single persistent launch at its fastest shape on this batch. Returns the launch
     shape used:
-    ``{"fp_waves", "largest_first", "ms_subiteration", "persistent", "blocks_per_cu"}``."""
+    ``{"fp_waves", "largest_first", "ms_subiteration", "persistent", "blocks_per_cu", "forward_split"}``."""
     autotune = 2 if autotune == "persistent" else int(autotune)
     n = len(geoms)
     if not (len(ys) == len(ws) == len(xs) == n) or n == 0:
@@ -247,7 +247,7 @@ def rlalm_solve_batched(geoms, p: Params, ys, ws, xs, *, autotune=False, stream=
     check(geoms[0]._lib.ct_rlalm_solve_batched(hs, n, ctypes.byref(cp), yp, wp, xp, autotune, ctypes.byref(cfg),
                                                _stream_handle(stream)))
     return dict(fp_waves=cfg.fp_waves, largest_first=bool(cfg.largest_first), ms_subiteration=cfg.ms_subiteration,
-                persistent=bool(cfg.persistent), blocks_per_cu=cfg.blocks_per_cu)
+                persistent=bool(cfg.persistent), blocks_per_cu=cfg.blocks_per_cu, forward_split=cfg.forward_split)
 
 
 def rlalm_prepare(g: Geometry, p: Params, w: torch.Tensor, dl: torch.Tensor, kappa: torch.Tensor | None = None,

@@ -598,15 +598,17 @@ ct_status do_init(const Ctx &c, const float *x_in, int zero_start, hipStream_t s
 
 // Slice table of a batch in a given slice order, with contiguous workgroup ranges. Buffer index 0 is
 // ping-pong buffer A, 1 is B.
+// split_mode: the forward launch's split of each block's lines over two workgroups, -1 automatic (decided
+// for the launch as a whole: when all of its unsplit forward workgroups would underfill the device), 0
+// never, 1 always (where eligible); a solve's own forward_split setting other than -1 overrides it.
 std::vector<SliceDev> slice_table(const std::vector<Ctx> &cs, const std::vector<int> &order, int fp_waves,
-                                  int *nwg_fp, int *nwg_bp)
+                                  int split_mode, int *nwg_fp, int *nwg_bp)
 {
     std::vector<SliceDev> tab;
     int fp = 0, bp = 0;
-    // the automatic split is decided for the launch as a whole: all of its unsplit forward workgroups
     int fp_all = 0;
     for (int i : order) fp_all += forward_workgroups(cs[(size_t)i].g->dev, cs[(size_t)i].nvm, fp_waves, false);
-    const int batch_split = launch_underfills(fp_all) ? 1 : 0;
+    const int batch_split = split_mode >= 0 ? split_mode : (launch_underfills(fp_all) ? 1 : 0);
     for (int i : order) {
         const Ctx &c = cs[(size_t)i];
         const Workspace &W = c.g->ws;
@@ -738,7 +740,7 @@ ct_status tune_batch(const std::vector<Ctx> &cs, hipStream_t s, ct_batch_config 
         for (int bpc : {1, 2, 4}) {
             if (!dorder || bpc > max_bpc || st != CT_OK) continue;
             int nfp = 0, nbp = 0;
-            std::vector<SliceDev> tab = slice_table(cs, lf ? largest : given, 8, &nfp, &nbp);
+            std::vector<SliceDev> tab = slice_table(cs, lf ? largest : given, 8, -1, &nfp, &nbp);
             SliceDev *dtab = nullptr;
             st = upload_table(tab, &dtab, s);
             if (st != CT_OK) break;
@@ -768,12 +770,17 @@ ct_status tune_batch(const std::vector<Ctx> &cs, hipStream_t s, ct_batch_config 
                 best->largest_first = lf;
                 best->persistent = 1;
                 best->blocks_per_cu = bpc;
+                best->forward_split = -1;
             }
         }
-        for (int waves : {16, 8}) {
-            if (!lockstep) break;
+        // lockstep: 16 or 8 forward waves per workgroup, each with the forward split never and always (when
+        // the solve leaves the split to the library; otherwise its own setting)
+        const bool tune_split = cs[0].p->forward_split == -1;
+        for (int cand = 0; cand < 4 && lockstep; ++cand) {
+            const int waves = cand < 2 ? 16 : 8, split = tune_split ? (cand & 1) : -1;
+            if (!tune_split && (cand & 1)) continue;
             int nfp = 0, nbp = 0;
-            std::vector<SliceDev> tab = slice_table(cs, lf ? largest : given, waves, &nfp, &nbp);
+            std::vector<SliceDev> tab = slice_table(cs, lf ? largest : given, waves, split, &nfp, &nbp);
             SliceDev *dtab = nullptr;
             st = upload_table(tab, &dtab, s);
             if (st != CT_OK) break;
@@ -802,6 +809,7 @@ ct_status tune_batch(const std::vector<Ctx> &cs, hipStream_t s, ct_batch_config 
                 best->largest_first = lf;
                 best->persistent = 0;
                 best->blocks_per_cu = 0;
+                best->forward_split = split;
             }
         }
     }
@@ -839,11 +847,13 @@ bool read_tuned(const std::string &path, ct_batch_config *cfg, int max_bpc)
     FILE *f = std::fopen(path.c_str(), "r");
     if (!f) return false;
     ct_batch_config c{};
-    const int got = std::fscanf(f, "fp_waves %d largest_first %d persistent %d blocks_per_cu %d ms %lf", &c.fp_waves,
-                                &c.largest_first, &c.persistent, &c.blocks_per_cu, &c.ms_subiteration);
+    const int got = std::fscanf(f, "fp_waves %d largest_first %d persistent %d blocks_per_cu %d forward_split %d ms %lf",
+                                &c.fp_waves, &c.largest_first, &c.persistent, &c.blocks_per_cu, &c.forward_split,
+                                &c.ms_subiteration);
     std::fclose(f);
-    const bool ok = got == 5 && (c.fp_waves == 8 || c.fp_waves == 16) && (c.largest_first == 0 || c.largest_first == 1) &&
-                    (c.persistent == 0 || (c.persistent == 1 && c.blocks_per_cu >= 1 && c.blocks_per_cu <= max_bpc));
+    const bool ok = got == 6 && (c.fp_waves == 8 || c.fp_waves == 16) && (c.largest_first == 0 || c.largest_first == 1) &&
+                    (c.persistent == 0 || (c.persistent == 1 && c.blocks_per_cu >= 1 && c.blocks_per_cu <= max_bpc)) &&
+                    c.forward_split >= -1 && c.forward_split <= 1;
     if (ok) *cfg = c;
     return ok;
 }
@@ -856,8 +866,8 @@ void write_tuned(const std::string &path, const ct_batch_config &c)
     const std::string tmp = path + ".tmp";
     FILE *f = std::fopen(tmp.c_str(), "w");
     if (!f) return;
-    std::fprintf(f, "fp_waves %d largest_first %d persistent %d blocks_per_cu %d ms %.6f\n", c.fp_waves,
-                 c.largest_first, c.persistent, c.blocks_per_cu, c.ms_subiteration);
+    std::fprintf(f, "fp_waves %d largest_first %d persistent %d blocks_per_cu %d forward_split %d ms %.6f\n",
+                 c.fp_waves, c.largest_first, c.persistent, c.blocks_per_cu, c.forward_split, c.ms_subiteration);
     std::fclose(f);
     (void)std::rename(tmp.c_str(), path.c_str());
 }
@@ -880,7 +890,7 @@ ct_status persistent_batched(ct_geom *const *gs, int n, const ct_rlalm_params *p
             return work(a) > work(b);
         });
     int nfp = 0, nbp = 0;
-    std::vector<SliceDev> tab = slice_table(cs, order, 8, &nfp, &nbp);
+    std::vector<SliceDev> tab = slice_table(cs, order, 8, -1, &nfp, &nbp);
     SliceDev *dtab = nullptr;
     CT_TRY(upload_table(tab, &dtab, s));
     int *dorder = nullptr;
@@ -1268,7 +1278,7 @@ ct_status ct_rlalm_solve_batched(ct_geom *const *gs, int n, const ct_rlalm_param
     // every slice reads the rho table and subiteration counter of slice 0
     const Workspace &W0 = gs[0]->ws;
 
-    ct_batch_config cfg{16, 0, 0.0, 0, 0};
+    ct_batch_config cfg{16, 0, 0.0, 0, 0, -1};
     int dev = 0, cus = 0;
     CT_HIP_CHECK(hipGetDevice(&dev));
     CT_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -1335,7 +1345,7 @@ ct_status ct_rlalm_solve_batched(ct_geom *const *gs, int n, const ct_rlalm_param
             return work(a) > work(b);
         });
     int nfp = 0, nbp = 0;
-    std::vector<SliceDev> tab = slice_table(cs, order, cfg.fp_waves, &nfp, &nbp);
+    std::vector<SliceDev> tab = slice_table(cs, order, cfg.fp_waves, cfg.forward_split, &nfp, &nbp);
     SliceDev *dtab = nullptr;
     CT_TRY(upload_table(tab, &dtab, s));
     struct Guard {

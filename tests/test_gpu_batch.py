@@ -205,3 +205,4 @@ def test_tuned_shape_is_cached_on_disk(api, tmp_path, monkeypatch):
     assert len(files) == 1 and files[0].parent.name.startswith("gfx")
     text = files[0].read_text()
     assert f"persistent {int(cfg['persistent'])}" in text and f"fp_waves {cfg['fp_waves']}" in text
+    assert f"forward_split {cfg['forward_split']}" in text
