@@ -127,7 +127,21 @@ __host__ __device__ inline void hx_cum_point(float z, int zi, int nz, int &k, fl
     }
 }
 
-__host__ __device__ inline int hx_clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+__host__ __device__ inline int hx_clampi(int v, int lo, int hi)
+{
+    const int a = v < hi ? v : hi;
+    return a > lo ? a : lo;
+}
+
+// a * b for a, b < 2^24 (the full-rate 24-bit multiply on the device); the product must fit 32 bits.
+__host__ __device__ inline unsigned hx_mul24(unsigned a, unsigned b)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __umul24(a, b);
+#else
+    return a * b;
+#endif
+}
 
 // Forward projection, one lane: bin k of view v, rows r0 .. r0 + HX_RB - 1 (rows >= nr are skipped),
 // lines l0, l0 + lstep, ... < NL. acc[rr] += f_t * (integral of the column over the row's z interval) /
@@ -186,10 +200,13 @@ __host__ __device__ inline void hfp_lane(const HelixDev &G, const Ro<float2> &Cz
                     fp = fn;
                 }
             } else {
+                // 32-bit element index (the descriptor check keeps the padded volume below 2^31 elements
+                // and a plane below 2^24)
+                const unsigned col32 = (unsigned)col, plane32 = (unsigned)plane;
                 auto cum = [&](float z) {
                     const float fl = floorf(z);
-                    const int kk = hx_clampi((int)fl + zi, -1, G.nz);
-                    const float2 c = Cz[(size_t)(kk + 1) * plane + col];
+                    const unsigned kk = (unsigned)(hx_clampi((int)fl + zi, -1, G.nz) + 1);
+                    const float2 c = Cz[hx_mul24(kk, plane32) + col32];
                     return fmaf(z - fl, c.y, c.x);
                 };
                 float Cp = cum(fmaf(ell, wr[0], zaf));
@@ -276,7 +293,6 @@ __host__ __device__ inline void hbp_lane(const HelixDev &G, const Ro<float> &Rp,
             fk[c] = (ka + c <= kb && ov > 0.f && wd > 0.f) ? ov * hx_rcp(wd) * inva : 0.f;
             up = un;
         }
-        const size_t rv = (size_t)vi * G.nr * G.nb;
         const float zoff = zaf - zg0;   // row boundaries in the group's coordinates: fmaf(ell, wr_r, zoff)
         float cl[HX_ZG];
         {
@@ -284,12 +300,17 @@ __host__ __device__ inline void hbp_lane(const HelixDev &G, const Ro<float> &Rp,
 #pragma unroll
             for (int b = 0; b < HX_ZG; ++b) cl[b] = hx_clamp01(zl - (float)b);
         }
-        for (int r = ra; r <= rb; ++r) {
+        // 32-bit element offsets into the residual block (the descriptor check keeps nviews * nr * nb below
+        // 2^31): the row's base advances by nb per row, the candidates' bins are fixed for the view
+        unsigned kcand[HX_KC];
+#pragma unroll
+        for (int c = 0; c < HX_KC; ++c) kcand[c] = (unsigned)hx_min(ka + c, kb);
+        unsigned rr = ((unsigned)vi * (unsigned)G.nr + (unsigned)ra) * (unsigned)G.nb;
+        for (int r = ra; r <= rb; ++r, rr += (unsigned)G.nb) {
             const float zh = fmaf(ell, G.wr[(size_t)r + 1], zoff);
-            const size_t rr = rv + (size_t)r * G.nb;
             float t = 0.f;
 #pragma unroll
-            for (int c = 0; c < HX_KC; ++c) t = fmaf(fk[c], Rp[rr + hx_min(ka + c, kb)], t);
+            for (int c = 0; c < HX_KC; ++c) t = fmaf(fk[c], Rp[rr + kcand[c]], t);
             for (int k = ka + HX_KC; k <= kb; ++k) {   // columns that meet more than HX_KC bins
                 const double2 b0 = G.bnd[vb + k], b1 = G.bnd[vb + k + 1];
                 const double ua = fma(lcd, b0.y, b0.x) - e0d, ub = fma(lcd, b1.y, b1.x) - e0d;

@@ -42,8 +42,13 @@ ct_status check_helix_desc(const ct_helix_desc *d)
         return fail(CT_ERR_INVALID_ARG, "nb must be in [1, 8192] and nr in [1, 1024]");
     if (d->nviews < 1 || d->views_per_turn < 1 || d->nviews > (1 << 20))
         return fail(CT_ERR_INVALID_ARG, "nviews and views_per_turn must be >= 1 (nviews <= 2^20)");
-    if ((long long)d->nviews * (d->nb + 1) >= (1ll << 31) || (long long)d->nviews * d->nr * d->nb >= (1ll << 40))
-        return fail(CT_ERR_INVALID_ARG, "sinogram too large");
+    // the back-projector indexes a residual block (up to all views) in 32 bits
+    if ((long long)d->nviews * (d->nb + 1) >= (1ll << 31) || (long long)d->nviews * d->nr * d->nb >= (1ll << 31))
+        return fail(CT_ERR_INVALID_ARG, "sinogram too large: nviews * nr * nb must be below 2^31");
+    // the forward projector indexes the padded cumulative volume ((nz + 2) planes) in 32 bits, a plane by a
+    // 24-bit multiply
+    if ((long long)d->nx * d->ny >= (1ll << 24) || (long long)(d->nz + 2) * d->nx * d->ny >= (1ll << 31))
+        return fail(CT_ERR_INVALID_ARG, "volume too large: nx * ny must be below 2^24 and (nz + 2) * nx * ny below 2^31");
     if (d->nsubsets < 1 || d->nviews % d->nsubsets != 0)
         return fail(CT_ERR_INVALID_ARG, "nsubsets must be >= 1 and divide nviews");
     if (!(d->dso > 0) || !(d->dsd > d->dso)) return fail(CT_ERR_INVALID_ARG, "need dsd > dso > 0");

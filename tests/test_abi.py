@@ -68,3 +68,34 @@ def test_network_parameter_count_is_host_only_and_matches_the_reference():
     from oracle import unet
     from paper_1512_04564_amd import _lib
     assert _lib.load().ct_unet_num_params() == unet.n_params() == 1946305
+
+
+def test_helical_descriptor_limits_are_checked_on_the_host():
+    """The 3-D projectors index the padded cumulative volume and the residual block in 32 bits; a
+    descriptor beyond those limits is rejected before any GPU call, as is an inconsistent one."""
+    import ctypes
+    from paper_1512_04564_amd import _lib, synth
+    L = _lib.load()
+    g = synth.HELICAL_SMALL
+
+    def desc(**kw):
+        f = dict(nx=g.nx, ny=g.ny, nz=g.nz, dx=g.dx, dy=g.dy, dz=g.dz, zc=g.zc, nb=g.nb, du=g.du,
+                 u_offset=g.u_offset, nr=g.nr, dw=g.dw, w_offset=g.w_offset, nviews=g.nviews,
+                 views_per_turn=g.views_per_turn, beta0=g.beta0, z0=g.z0, feed=g.feed, dso=g.dso, dsd=g.dsd,
+                 nsubsets=g.nsubsets)
+        f.update(kw)
+        return _lib.HelixDesc(*[f[n] for n, _ in _lib.HelixDesc._fields_])
+
+    h = ctypes.c_void_p()
+    # a plane of 4096 x 4096 voxels (2^24) exceeds the 24-bit plane multiply (pixel size keeps the volume
+    # inside the source circle, so the limit is what rejects it)
+    big = desc(nx=4096, ny=4096, dx=0.05, dy=0.05)
+    assert L.ct_helix_create(ctypes.byref(big), ctypes.byref(h)) == _lib.CT_ERR_INVALID_ARG
+    assert b"volume too large" in L.ct_last_error()
+    # nviews * nr * nb at 2^31 or more
+    many = desc(nviews=2 ** 17, views_per_turn=2 ** 15, nr=128, nb=256, nsubsets=1, dw=g.dw / 16)
+    assert L.ct_helix_create(ctypes.byref(many), ctypes.byref(h)) == _lib.CT_ERR_INVALID_ARG
+    assert b"sinogram too large" in L.ct_last_error()
+    bad = desc(nsubsets=7)   # 660 views, not a multiple of 7
+    assert L.ct_helix_create(ctypes.byref(bad), ctypes.byref(h)) == _lib.CT_ERR_INVALID_ARG
+    assert L.ct_helix_create(None, ctypes.byref(h)) == _lib.CT_ERR_INVALID_ARG
