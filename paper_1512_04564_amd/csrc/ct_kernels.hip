@@ -558,10 +558,11 @@ __device__ __forceinline__ T wave_shift_up(T v)
     return dpp_or_zero<0x138, 0xF>(v);   // wave_shr:1
 }
 
+// idelta = 1 / delta (one division per thread instead of one per neighbour).
 template <int POT>
-__device__ __forceinline__ void pot_terms(float delta, float t, float &dphi, float &omega)
+__device__ __forceinline__ void pot_terms(float idelta, float t, float &dphi, float &omega)
 {
-    const float z = t / delta;
+    const float z = t * idelta;
     if (POT == 0) {
         omega = rsqrtf(fmaf(z, z, 1.f));
     } else if (POT == 1) {
@@ -625,6 +626,7 @@ __device__ __forceinline__ void reg_stencil(const UpdateArgs &U, int i, int j, i
     gr = 0.f;
     dr = 0.f;
     const float kc = U.kappa ? U.kappa[idx] : 1.f;
+    const float idelta = 1.f / U.delta;
     const int di[8] = {0, 0, 1, -1, 1, -1, 1, -1};
     const int dj[8] = {1, -1, 0, 0, 1, -1, -1, 1};
 #pragma unroll
@@ -634,7 +636,7 @@ __device__ __forceinline__ void reg_stencil(const UpdateArgs &U, int i, int j, i
         const size_t i2x = (size_t)i2 * nx + j2;
         const float bt = (n < 4 ? U.beta_ax : U.beta_dg) * (U.kappa ? kc * U.kappa[i2x] : 1.f);
         float dphi, om;
-        pot_terms<POT>(U.delta, xc - U.x[i2x], dphi, om);
+        pot_terms<POT>(idelta, xc - U.x[i2x], dphi, om);
         gr = fmaf(bt, dphi, gr);
         dr = fmaf(bt, 2.f * (U.huber ? om : 1.f), dr);
     }
@@ -840,7 +842,7 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
             } else if (MODE == BP_FULL) {
                 const float rho = U.rho[t];
                 const float a = U.alpha;
-                const float inv1 = 1.f / (rho + 1.f);
+                const float inv1 = rcp_approx(rho + 1.f);
                 const float gn = rho * inv1 * (a * zeta + (1.f - a) * g) + g * inv1;
                 const float hn = U.algorithm == 1 ? a * fmaf(d, xc, -zeta) + (1.f - a) * hh : zeta;
                 g = gn;
@@ -877,7 +879,7 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
             gr += q.x;
             dr += q.y;
             const float den = fmaf(xs_rho1, xs_d, dr);
-            xn = den > 0.f ? fmaxf(xs_xc - (xs_s + gr) / den, 0.f) : xs_xc;
+            xn = den > 0.f ? fmaxf(xs_xc - (xs_s + gr) * rcp_approx(den), 0.f) : xs_xc;
             U.x_next[idx] = xn;
             if (!std::is_same<TXC, float>::value) st<TXC>(U.xc_next, idx, xn);
         }
