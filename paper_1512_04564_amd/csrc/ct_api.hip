@@ -200,8 +200,9 @@ bool key_equal(const GraphKey &a, const GraphKey &b)
 void drop_graph_cache(ct_geom *g)
 {
     GraphCache &c = g->graphs;
-    for (int i = 0; i < 2; ++i)
-        if (c.exec[i]) (void)hipGraphExecDestroy(c.exec[i]);
+    for (int k = 0; k < 2; ++k)
+        for (int i = 0; i < 2; ++i)
+            if (c.exec[k][i]) (void)hipGraphExecDestroy(c.exec[k][i]);
     if (c.cap) (void)hipStreamDestroy(c.cap);
     c = GraphCache();
 }
@@ -450,35 +451,40 @@ ct_status run_subiters(const Ctx &c, long long t0, long long nsub, int use_graph
         GraphCache &gc = g->graphs;
         if (!gc.cap) CT_HIP_CHECK(hipStreamCreateWithFlags(&gc.cap, hipStreamNonBlocking));
         const int chunk = traced ? M : L;  // traced runs replay per iteration, still needing parity graphs
+        // untraced runs replay runs of about 400 subiterations as one graph while enough remain (fewer
+        // replays, each with its counter reset), then single chunks
+        const int nlong = traced ? 1 : std::max(1, 400 / chunk);
         while (tend - t >= chunk) {
+            const int kind = nlong > 1 && tend - t >= (long long)chunk * nlong ? 1 : 0;
+            const int len = kind ? chunk * nlong : chunk;
             const int parity = cur_a;
-            GraphKey key{c.y, c.w, c.dl, c.kappa, c.gv, c.h, W.rho, W.r, (int)(t % M), parity, chunk, *p};
-            if (!gc.valid[parity] || !key_equal(gc.key[parity], key)) {
-                if (gc.exec[parity]) (void)hipGraphExecDestroy(gc.exec[parity]);
-                gc.exec[parity] = nullptr;
-                gc.valid[parity] = false;
+            GraphKey key{c.y, c.w, c.dl, c.kappa, c.gv, c.h, W.rho, W.r, (int)(t % M), parity, len, *p};
+            if (!gc.valid[kind][parity] || !key_equal(gc.key[kind][parity], key)) {
+                if (gc.exec[kind][parity]) (void)hipGraphExecDestroy(gc.exec[kind][parity]);
+                gc.exec[kind][parity] = nullptr;
+                gc.valid[kind][parity] = false;
                 hipGraph_t graph;
                 CT_HIP_CHECK(hipStreamBeginCapture(gc.cap, hipStreamCaptureModeThreadLocal));
                 int ca = parity;
                 hipError_t e = hipSuccess;
-                for (int j = 0; j < chunk && e == hipSuccess; ++j) {
+                for (int j = 0; j < len && e == hipSuccess; ++j) {
                     e = launch_subiter(c, t + j, j, ca, gc.cap);
                     ca ^= 1;
                 }
-                if (e == hipSuccess) e = launch_add_counter(W.tbase, chunk, gc.cap);
+                if (e == hipSuccess) e = launch_add_counter(W.tbase, len, gc.cap);
                 hipError_t e2 = hipStreamEndCapture(gc.cap, &graph);
                 if (e != hipSuccess) return fail(CT_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
                 if (e2 != hipSuccess) return fail(CT_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
-                hipError_t e3 = hipGraphInstantiate(&gc.exec[parity], graph, nullptr, nullptr, 0);
+                hipError_t e3 = hipGraphInstantiate(&gc.exec[kind][parity], graph, nullptr, nullptr, 0);
                 (void)hipGraphDestroy(graph);
                 if (e3 != hipSuccess) return fail(CT_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e3));
-                gc.key[parity] = key;
-                gc.valid[parity] = true;
+                gc.key[kind][parity] = key;
+                gc.valid[kind][parity] = true;
             }
             CT_HIP_CHECK(launch_set_counter(W.tbase, (int)t, s));
-            CT_HIP_CHECK(hipGraphLaunch(gc.exec[parity], s));
-            if (chunk % 2) cur_a ^= 1;
-            t += chunk;
+            CT_HIP_CHECK(hipGraphLaunch(gc.exec[kind][parity], s));
+            if (len % 2) cur_a ^= 1;
+            t += len;
             CT_TRY(trace_point(t));
         }
     }

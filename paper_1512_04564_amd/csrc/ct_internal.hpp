@@ -73,7 +73,8 @@ struct Workspace {
     float *tmp = nullptr;                   // scratch image
 };
 
-// Cached executable graphs of one outer iteration, one per ping-pong parity of the image buffers.
+// Cached executable graphs of a solve's subiterations, per kind (0: one iteration, doubled for an odd subset
+// count; 1: a run of such graphs as one, for untraced solves) and per ping-pong parity of the image buffers.
 struct GraphKey {
     const void *y, *w, *dl, *kappa, *gv, *h, *rho, *r;
     int t0mod, parity, len;
@@ -81,9 +82,9 @@ struct GraphKey {
 };
 
 struct GraphCache {
-    bool valid[2] = {false, false};
-    GraphKey key[2]{};
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    bool valid[2][2] = {{false, false}, {false, false}};
+    GraphKey key[2][2]{};
+    hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     hipStream_t cap = nullptr;
 };
 
