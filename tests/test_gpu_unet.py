@@ -78,8 +78,10 @@ def test_forward_parity(mods, n, h, w):
 
 # 2 x 256^2 runs the LDS-tiled convolution in both directions with 16-row tiles (with and without the
 # chunk prefetch) and 8-row tiles, and the pooling fused into its forward epilogue; the smaller images
-# run the untiled forms
-@pytest.mark.parametrize("n,h,w", [(2, 64, 64), (2, 24, 40), (2, 256, 256)])
+# run the untiled forms. The weight gradient takes its nine-tap form at levels whose width is a multiple
+# of 64 (256: four 64-pixel segments per row, 128: two, 64: one; 1 x 64 x 192: three, then 96 and 48 wide
+# levels in the single-tap form) and the single-tap form elsewhere (2 x 24 x 40 throughout).
+@pytest.mark.parametrize("n,h,w", [(2, 64, 64), (2, 24, 40), (2, 256, 256), (1, 64, 192)])
 def test_gradient_parity_every_layer(mods, n, h, w):
     import torch
     _, unet = mods
