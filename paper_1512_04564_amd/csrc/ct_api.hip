@@ -282,6 +282,7 @@ UpdateArgs make_update(const Ctx &c)
     U.algorithm = c.p->algorithm;
     U.potential = c.p->potential;
     U.delta = (float)c.p->delta;
+    U.idelta = 1.f / U.delta;   // the correctly rounded float32 quotient, as a device division would give
     U.beta_ax = (float)c.p->beta;
     U.beta_dg = (float)(c.p->beta / std::sqrt(2.0));
     U.huber = c.p->huber;
@@ -661,6 +662,7 @@ BatchUpdate batch_update(const Ctx &c, long long tofs)
     u.potential = U.potential;
     u.huber = U.huber;
     u.delta = U.delta;
+    u.idelta = U.idelta;
     u.beta_ax = U.beta_ax;
     u.beta_dg = U.beta_dg;
     return u;

@@ -186,6 +186,7 @@ struct UpdateArgs {
     int algorithm = 1;
     int potential = 0;
     float delta = 1e-4f;
+    float idelta = 1e4f;           // 1 / delta, rounded once on the host
     float beta_ax = 1024.f, beta_dg = 1024.f / 1.41421356f;
     int huber = 1;
 };
@@ -226,7 +227,7 @@ struct BatchUpdate {
     long long tofs = 0;
     float alpha = 1.999f;
     int algorithm = 1, potential = 0, huber = 1;
-    float delta = 1e-4f, beta_ax = 1024.f, beta_dg = 1024.f / 1.41421356f;
+    float delta = 1e-4f, idelta = 1e4f, beta_ax = 1024.f, beta_dg = 1024.f / 1.41421356f;
 };
 
 // dtype: ct_dtype of the storage-typed operands (y, w, residual, image copies).

@@ -469,6 +469,14 @@ __device__ __forceinline__ float bp_view(const GeomDev &G, const float4 im, floa
 // bin by a hair (FP32 error, far below one bin) the neighbouring entry is taken instead.
 // Entry of the bin of the edge at signed coordinate u (detector coordinate kf, window-relative), with
 // u's endpoints ua, ub on the line lc; returns whether the estimate missed that bin.
+// v clamped to [0, hi] (hi >= 0) in one instruction: the median of v, 0 and hi.
+__device__ __forceinline__ int clamp_entry(int v, int hi)
+{
+    int r;
+    asm("v_med3_i32 %0, %1, 0, %2" : "=v"(r) : "v"(v), "v"(hi));
+    return r;
+}
+
 struct CumBin {
     float4 q;       // s A_k, s B_k, P_e, r_e
     float ua, ub;   // s U_k, s U_k+1 on the pixel's line
@@ -522,11 +530,11 @@ __device__ __forceinline__ void bp_line(const GeomDev &G, const float4 im, float
             if (G.arc) t = atanf(t);
             kf = fmaf(G.c_kf, t, kofs);
         }
-        const int e = min(max((int)floorf(kf), 0), n - 1);
+        const int e = clamp_entry((int)floorf(kf), n - 1);
         const float u = POS ? em : -em;   // the edge in signed coordinates
         CumBin c = cum_bin(E, e, lc);
         if ((u < c.ua) | (u > c.ub))   // the estimate missed its edge's bin: the neighbouring entry
-            c = cum_bin(E, min(max(u < c.ua ? e - 1 : e + 1, 0), n - 1), lc);
+            c = cum_bin(E, clamp_entry(u < c.ua ? e - 1 : e + 1, n - 1), lc);
         const float F = cum_value(c, u);
         if (m > 0) val[m - 1] = POS ? F - Fp : Fp - F;
         Fp = F;
@@ -558,7 +566,7 @@ __device__ __forceinline__ T wave_shift_up(T v)
     return dpp_or_zero<0x138, 0xF>(v);   // wave_shr:1
 }
 
-// idelta = 1 / delta (one division per thread instead of one per neighbour).
+// idelta = 1 / delta (rounded once on the host: no division on the device).
 template <int POT>
 __device__ __forceinline__ void pot_terms(float idelta, float t, float &dphi, float &omega)
 {
@@ -617,39 +625,71 @@ constexpr int BP_SWIN = 125;    // widest window staged (bins); wider ones read 
 constexpr int BP_SLOT = 128;    // staged entries per view (n + 1 for a window of n bins)
 
 // Regularizer gradient and Huber curvature at pixel (i, j) of value xc: the pair terms of neighbours
-// N0 .. N1 - 1 of the 8 (4 directions, each pair seen from both sides; 0 .. 3 axial, 4 .. 7 diagonal) with
-// potential POT, weighted by beta and the kappa factors.
-template <int POT, int N0, int N1>
-__device__ __forceinline__ void reg_stencil(const UpdateArgs &U, int i, int j, int nx, int ny, size_t idx,
-                                            float xc, float &gr, float &dr)
+// 0 .. 3 (axial) or 4 .. 7 (diagonal) of the 8 (4 directions, each pair seen from both sides) with potential
+// POT, weighted by beta and the kappa factors. The neighbours' loads (nbr_load) are issued together
+// and ahead of the pixel's own stores (one memory latency, not one per neighbour): a neighbour outside the
+// image reads the pixel itself and enters with weight 0, so that its term (difference 0) leaves both sums
+// unchanged.
+// Four neighbours of a pixel: N0 = 0 the axial ones, N0 = 4 the diagonal ones.
+struct Nbrs4 {
+    float x[4], k[4];   // values and kappa factors (1 without kappa)
+    float kc;           // the pixel's own kappa factor
+    unsigned in;        // bit n: neighbour n lies in the image
+};
+template <int N0>
+__device__ __forceinline__ Nbrs4 nbr_load(const UpdateArgs &U, int i, int j, int nx, int ny, unsigned idx)
+{
+    constexpr int di[8] = {0, 0, 1, -1, 1, -1, 1, -1};
+    constexpr int dj[8] = {1, -1, 0, 0, 1, -1, -1, 1};
+    Nbrs4 q;
+    unsigned k[4];
+    q.in = 0u;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        bool in = true;
+        if (di[N0 + n] > 0) in = in && i + 1 < ny;
+        if (di[N0 + n] < 0) in = in && i > 0;
+        if (dj[N0 + n] > 0) in = in && j + 1 < nx;
+        if (dj[N0 + n] < 0) in = in && j > 0;
+        q.in |= in ? 1u << n : 0u;
+        k[n] = in ? idx + (unsigned)(di[N0 + n] * nx + dj[N0 + n]) : idx;
+    }
+#pragma unroll
+    for (int n = 0; n < 4; ++n) q.x[n] = U.x[k[n]];
+    q.kc = 1.f;
+    if (U.kappa) {   // uniform
+        q.kc = U.kappa[idx];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) q.k[n] = U.kappa[k[n]];
+    } else {
+#pragma unroll
+        for (int n = 0; n < 4; ++n) q.k[n] = 1.f;
+    }
+    return q;
+}
+// beta: the four neighbours' direction weight (beta_ax or beta_dg)
+template <int POT>
+__device__ __forceinline__ void reg_terms(const UpdateArgs &U, const Nbrs4 &q, float beta, float xc, float &gr,
+                                          float &dr)
 {
     gr = 0.f;
     dr = 0.f;
-    const float kc = U.kappa ? U.kappa[idx] : 1.f;
-    const float idelta = 1.f / U.delta;
-    const int di[8] = {0, 0, 1, -1, 1, -1, 1, -1};
-    const int dj[8] = {1, -1, 0, 0, 1, -1, -1, 1};
 #pragma unroll
-    for (int n = N0; n < N1; ++n) {
-        const int i2 = i + di[n], j2 = j + dj[n];
-        if (i2 < 0 || i2 >= ny || j2 < 0 || j2 >= nx) continue;
-        const size_t i2x = (size_t)i2 * nx + j2;
-        const float bt = (n < 4 ? U.beta_ax : U.beta_dg) * (U.kappa ? kc * U.kappa[i2x] : 1.f);
+    for (int n = 0; n < 4; ++n) {
+        const float bt = (q.in >> n) & 1u ? beta * (q.kc * q.k[n]) : 0.f;
         float dphi, om;
-        pot_terms<POT>(idelta, xc - U.x[i2x], dphi, om);
+        pot_terms<POT>(U.idelta, xc - q.x[n], dphi, om);
         gr = fmaf(bt, dphi, gr);
         dr = fmaf(bt, 2.f * (U.huber ? om : 1.f), dr);
     }
 }
-
-template <int N0, int N1>
-__device__ __forceinline__ void reg_stencil_pot(const UpdateArgs &U, int i, int j, int nx, int ny, size_t idx,
-                                                float xc, float &gr, float &dr)
+__device__ __forceinline__ void reg_stencil_pot(const UpdateArgs &U, const Nbrs4 &q, float beta, float xc, float &gr,
+                                                float &dr)
 {
     // one uniform branch on the potential per pixel, not one per neighbour
-    if (U.potential == 0) reg_stencil<0, N0, N1>(U, i, j, nx, ny, idx, xc, gr, dr);
-    else if (U.potential == 1) reg_stencil<1, N0, N1>(U, i, j, nx, ny, idx, xc, gr, dr);
-    else reg_stencil<2, N0, N1>(U, i, j, nx, ny, idx, xc, gr, dr);
+    if (U.potential == 0) reg_terms<0>(U, q, beta, xc, gr, dr);
+    else if (U.potential == 1) reg_terms<1>(U, q, beta, xc, gr, dr);
+    else reg_terms<2>(U, q, beta, xc, gr, dr);
 }
 
 struct BpShared {
@@ -826,13 +866,15 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
     // operands of the x-step, kept over the barrier below: s, rho1, d, xc and the axial regularizer terms
     float xs_s = 0.f, xs_rho1 = 0.f, xs_d = 0.f, xs_xc = 0.f, gr = 0.f, dr = 0.f;
     if (hv == 0 && inside) {   // half 1 only evaluates the diagonal regularizer terms from here on
-        const size_t idx = (size_t)i * nx + j;
+        const unsigned idx = (unsigned)i * (unsigned)nx + (unsigned)j;
         if (MODE == BP_BACK) {
             a.out_back[idx] = zeta;
         } else {
             const float xc = U.x[idx];
             const float d = U.dl[idx];
             float g = U.gv[idx], hh = U.h[idx];
+            Nbrs4 nb;   // the axial neighbours, loaded ahead of this pixel's stores
+            if (MODE == BP_FULL || MODE == BP_XSTEP) nb = nbr_load<0>(U, i, j, nx, ny, idx);
             const long long t = (U.tbase ? (long long)(*U.tbase) : 0ll) + U.tofs;
             if (MODE == BP_INIT) {
                 g = zeta;
@@ -857,7 +899,7 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
                                                  : rho1 * hh + (1.f - rho1) * g;
                 // regularizer gradient and Huber curvature at xc: the axial neighbours here, the diagonal
                 // ones by the second half of the workgroup (below), added after the barrier
-                reg_stencil_pot<0, 4>(U, i, j, nx, ny, idx, xc, gr, dr);
+                reg_stencil_pot(U, nb, U.beta_ax, xc, gr, dr);
                 xs_s = s;
                 xs_rho1 = rho1;
                 xs_d = d;
@@ -867,14 +909,14 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
     }
     if (MODE == BP_FULL || MODE == BP_XSTEP) {
         if (hv == 1 && inside) {
-            const size_t idx = (size_t)i * nx + j;
+            const unsigned idx = (unsigned)i * (unsigned)nx + (unsigned)j;
             float g2, d2;
-            reg_stencil_pot<4, 8>(U, i, j, nx, ny, idx, U.x[idx], g2, d2);
+            reg_stencil_pot(U, nbr_load<4>(U, i, j, nx, ny, idx), U.beta_dg, U.x[idx], g2, d2);
             sh.reg_part[tid] = make_float2(g2, d2);
         }
         __syncthreads();
         if (hv == 0 && inside) {
-            const size_t idx = (size_t)i * nx + j;
+            const unsigned idx = (unsigned)i * (unsigned)nx + (unsigned)j;
             const float2 q = sh.reg_part[tid];
             gr += q.x;
             dr += q.y;
@@ -888,7 +930,7 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
         __syncthreads();
         const int jj = bx * BP_TX + ty;   // swapped roles
         const int ii = by * BP_TY + tx;
-        if (hv == 0 && jj < nx && ii < ny) st<TXC>(U.xT_next, (size_t)jj * ny + ii, tile_t[ty][tx]);
+        if (hv == 0 && jj < nx && ii < ny) st<TXC>(U.xT_next, (unsigned)jj * (unsigned)ny + (unsigned)ii, tile_t[ty][tx]);
     }
 }
 
@@ -930,6 +972,7 @@ __device__ __forceinline__ void update_item(const SliceDev *__restrict__ tab, in
     a.U.algorithm = u.algorithm;
     a.U.potential = u.potential;
     a.U.delta = u.delta;
+    a.U.idelta = u.idelta;
     a.U.beta_ax = u.beta_ax;
     a.U.beta_dg = u.beta_dg;
     a.U.huber = u.huber;
