@@ -1002,6 +1002,19 @@ void ct_rlalm_params_default(ct_rlalm_params *p)
     p->diverge_window = 3;
 }
 
+// The update kernel's bin windows, once per geometry (7.9 MB for 512^2 pixels and 984 views); above
+// 256 MiB the kernel computes them itself, as it would without the table.
+static ct_status build_tile_windows(ct_geom *g)
+{
+    const size_t nwin = tile_windows_count(g->dev);
+    if (nwin * sizeof(int2) > (size_t(256) << 20)) return CT_OK;
+    CT_HIP_CHECK(hipMalloc(&g->win, nwin * sizeof(int2)));
+    CT_HIP_CHECK(launch_tile_windows(g->dev, g->win, nullptr));
+    CT_HIP_CHECK(hipStreamSynchronize(nullptr));
+    g->dev.win = g->win;
+    return CT_OK;
+}
+
 ct_status ct_geom_create(const ct_geom_desc *desc, ct_geom **out)
 {
     if (!out) return fail(CT_ERR_INVALID_ARG, "out is NULL");
@@ -1012,6 +1025,7 @@ ct_status ct_geom_create(const ct_geom_desc *desc, ct_geom **out)
     g->desc = *desc;
     (void)hipGetDevice(&g->device);
     ct_status st = build_geometry(g);
+    if (st == CT_OK) st = build_tile_windows(g);
     if (st != CT_OK) {
         free_geometry(g);
         delete g;

@@ -193,6 +193,7 @@ ct_status build_geometry(ct_geom *g)
     G.inv = g->inv;
     G.rowsweep = g->d_rowsweep;
     G.sgn = g->sgn;
+    G.win = nullptr;   // filled by the caller once the kernels are at hand (ct_geom_create)
     return CT_OK;
 }
 
@@ -204,6 +205,9 @@ void free_geometry(ct_geom *g)
     if (g->d_rowsweep) (void)hipFree(g->d_rowsweep);
     if (g->cs) (void)hipFree(g->cs);
     if (g->sgn) (void)hipFree(g->sgn);
+    if (g->win) (void)hipFree(g->win);
+    g->win = nullptr;
+    g->dev.win = nullptr;
     g->cs = nullptr;
     g->sgn = nullptr;
     g->bnd = nullptr;

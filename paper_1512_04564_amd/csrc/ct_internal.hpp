@@ -55,6 +55,10 @@ struct GeomDev {
     const float4 *inv;
     const int *rowsweep;
     const float *sgn;
+    // bin window [x, y] of every (view, 16 x 16 tile) pair of the fused back-projection, at
+    // win[view * tiles + tile] (tiles in row-major order), filled when the geometry is created; nullptr
+    // where the table would exceed its size limit (the kernel then computes each window itself)
+    const int2 *win;
 };
 
 struct Workspace {
@@ -102,6 +106,7 @@ struct ct_geom {
     int *d_rowsweep = nullptr;
     double2 *cs = nullptr;  // per view (cos beta, sin beta) in FP64, for the FBP-like start
     float *sgn = nullptr;   // per view boundary order (+1 increasing, -1 decreasing)
+    int2 *win = nullptr;    // the fused back-projection's per (view, tile) bin windows (GeomDev::win)
     ct::GeomDev dev{};
     ct::Workspace ws;
     ct::GraphCache graphs;
@@ -233,6 +238,10 @@ struct BatchUpdate {
 // dtype: ct_dtype of the storage-typed operands (y, w, residual, image copies).
 hipError_t launch_forward(const FpLaunch &a, int ones, int epi, int dtype, hipStream_t s);
 hipError_t launch_back_update(const BpLaunch &a, int mode, int rtype, int ctype, hipStream_t s);
+// The bin windows of the fused back-projection's tiles for every view of G into out (G.nviews x tiles
+// entries), by the function the kernel would evaluate; tile_windows_count gives the number of entries.
+size_t tile_windows_count(const GeomDev &G);
+hipError_t launch_tile_windows(const GeomDev &G, int2 *out, hipStream_t s);
 // Batched subiteration kernels over slices [0, ns) of the device table tab: the forward projection of
 // subset m (views m + vi * M) from image buffer par with the residual epilogue, and the fused
 // back-projection / relaxed update reading buffer par and writing buffer par ^ 1. nwg_*: grid sizes

@@ -724,6 +724,7 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
     if (MODE != BP_XSTEP) {
         const int ti0 = by * BP_TY, ti1 = min(ti0 + BP_TY, ny);
         const int tj0 = bx * BP_TX, tj1 = min(tj0 + BP_TX, nx);
+        const int tilesx = (nx + BP_TX - 1) / BP_TX, ntiles = tilesx * ((ny + BP_TY - 1) / BP_TY);
         const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // view group
         // The lane's pixels are four consecutive pixels of one line of the view, so that five edges give four
         // pixels: for row sweep views tile row r4 = lane % 16, columns q4 + {0..3} (q4 = 4 (lane / 16)), edges
@@ -745,7 +746,8 @@ __device__ __forceinline__ void bp_body(const BpLaunch &a, const int bx, const i
             int nq = 0;
             if (lane < cn) {
                 const int v = vstart + (wave + BP_GROUPS * (c0 + lane)) * vstride;
-                wq = tile_window(G, v, ti0, ti1, tj0, tj1);
+                wq = G.win ? G.win[(unsigned)v * (unsigned)ntiles + (unsigned)(by * tilesx + bx)]
+                           : tile_window(G, v, ti0, ti1, tj0, tj1);
                 const int n = wq.y - wq.x + 1;
                 nq = n > 0 && n <= BP_SWIN ? n + 1 : 0;
             }
@@ -940,6 +942,19 @@ __global__ __launch_bounds__(2 * BP_TX *BP_TY) __attribute__((amdgpu_waves_per_e
 {
     __shared__ BpShared sh;
     bp_body<MODE, TR, TXC, R2>(a, blockIdx.x, blockIdx.y, sh);
+}
+
+// The bin window of every (view, tile) pair, as bp_body would compute it: one thread per pair.
+__global__ __launch_bounds__(256) void k_tile_windows(GeomDev G, int2 *__restrict__ out)
+{
+    const int tilesx = (G.nx + BP_TX - 1) / BP_TX, ntiles = tilesx * ((G.ny + BP_TY - 1) / BP_TY);
+    const unsigned q = blockIdx.x * 256u + threadIdx.x;
+    if (q >= (unsigned)G.nviews * (unsigned)ntiles) return;
+    const int v = (int)(q / (unsigned)ntiles), tile = (int)(q % (unsigned)ntiles);
+    const int bx = tile % tilesx, by = tile / tilesx;
+    const int ti0 = by * BP_TY, ti1 = min(ti0 + BP_TY, G.ny);
+    const int tj0 = bx * BP_TX, tj1 = min(tj0 + BP_TX, G.nx);
+    out[q] = tile_window(G, v, ti0, ti1, tj0, tj1);
 }
 
 // Batched fused back-projection / relaxed update of subset m: every slice reads image buffer par and
@@ -1182,6 +1197,19 @@ hipError_t launch_forward(const FpLaunch &a, int ones, int epi, int dtype, hipSt
         return hipErrorInvalidValue;
     }
 #undef CT_FP
+    return hipGetLastError();
+}
+
+size_t tile_windows_count(const GeomDev &G)
+{
+    return (size_t)G.nviews * (size_t)((G.nx + BP_TX - 1) / BP_TX) * (size_t)((G.ny + BP_TY - 1) / BP_TY);
+}
+
+hipError_t launch_tile_windows(const GeomDev &G, int2 *out, hipStream_t s)
+{
+    const size_t n = tile_windows_count(G);
+    if (n == 0 || n >= (size_t(1) << 31)) return hipErrorInvalidValue;   // 32-bit entry index
+    hipLaunchKernelGGL(k_tile_windows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, G, out);
     return hipGetLastError();
 }
 
