@@ -72,7 +72,9 @@ typedef struct ct_geom ct_geom; /* opaque: device geometry tables + solver works
 
 /*
  * Build the per-view geometry tables (FP64 on the host, stored FP32 on the current device) and the
- * subset tables. The handle owns them until ct_geom_destroy. The solver workspace inside the handle
+ * subset tables, and the back-projection's bin window of every (view, 16 x 16 pixel tile) pair
+ * (8 bytes each: 7.9 MB for 512^2 pixels and 984 views; not built past 256 MiB, where the kernel derives
+ * the windows itself). The handle owns them until ct_geom_destroy. The solver workspace inside the handle
  * is allocated on first use; solves on one handle must not overlap in time.
  * Errors: CT_ERR_INVALID_ARG for an inconsistent descriptor (sizes, distances, nviews % M), CT_ERR_OOM,
  * CT_ERR_HIP.
