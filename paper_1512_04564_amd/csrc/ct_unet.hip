@@ -341,11 +341,12 @@ __global__ __launch_bounds__(64) void k_conv3x3_wgrad(ConvSrc S, const bf16 *__r
         for (int q = 0; q < 2; ++q) acc[m][q] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bf16x8 zero8 = {};
     for (int pc = pb; pc < pe; pc += KC) {
-        // 64 pixels x 32 channels of each operand: 256 16-byte pieces, four per lane
+        // 64 pixels x 32 channels of each operand: 256 16-byte pieces, four per lane; piece t of lane q is
+        // channel group t of pixel q, so that each transposing write covers 64 consecutive pixels of one
+        // channel (neighbouring LDS halves, no bank conflicts between the channel groups)
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const int idx = lane + 64 * t;
-            const int q = idx >> 2, c8 = (idx & 3) * 8;
+            const int q = lane, c8 = 8 * t;
             const bool in = pc + q < pe;
             const int p = in ? pc + q : pe - 1;
             const bf16x8 va0 = *reinterpret_cast<const bf16x8 *>(dz + (size_t)p * cout + co0 + c8);
@@ -419,8 +420,9 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad9(ConvSrc S, const bf16 *_
     for (int sg = s0; sg < s1; ++sg) {
         const int row = sg / segs_row, px0 = (sg - row * segs_row) * 64;
         const int pn = row / h, py = row - pn * h;
-        {   // output gradient: thread -> (pixel tid / 4, channels 8 (tid % 4) ..), 64 x 4 pieces
-            const int q = tid >> 2, c8 = (tid & 3) * 8;
+        {   // output gradient: thread -> (pixel tid % 64, channels 8 (tid / 64) ..), 64 x 4 pieces: each wave
+            // writes one channel group's rows over 64 consecutive pixels (neighbouring LDS halves)
+            const int q = tid & 63, c8 = (tid >> 6) * 8;
             const bf16x8 v =
                 *reinterpret_cast<const bf16x8 *>(dz + (((size_t)pn * h + py) * w + px0 + q) * cout + co0 + c8);
 #pragma unroll
@@ -428,7 +430,7 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad9(ConvSrc S, const bf16 *_
         }
         // input rows: 3 rows x 66 pixels x 4 channel groups
         for (int idx = tid; idx < 3 * 66 * 4; idx += 256) {
-            const int c8 = (idx & 3) * 8, pr = idx >> 2;
+            const int c8 = (idx / 198) * 8, pr = idx % 198;   // channel group major, as above
             const int ry = pr / 66, j = pr - ry * 66;
             const int yy = py + ry - 1, xx = px0 + j - 1;
             const bool ok = yy >= 0 && yy < h && xx >= 0 && xx < w;
