@@ -458,6 +458,14 @@ __device__ __forceinline__ float bp_view(const GeomDev &G, const float4 im, floa
     return zeta;
 }
 
+// v clamped to [0, hi] (hi >= 0) in one instruction: the median of v, 0 and hi.
+__device__ __forceinline__ int clamp_entry(int v, int hi)
+{
+    int r;
+    asm("v_med3_i32 %0, %1, 0, %2" : "=v"(r) : "v"(v), "v"(hi));
+    return r;
+}
+
 // Cumulative form of the same back-projection, from a view staged in LDS. For the tile's bin window
 // kw0 .. kw1 (n bins), entry e = k - kw0 (0 <= e <= n) holds s (A_k, B_k), the signed coefficients of
 // boundary k (s = +1 or -1 the view's boundary order, so that s U_k increases with k), P_e, the sum of
@@ -469,14 +477,6 @@ __device__ __forceinline__ float bp_view(const GeomDev &G, const float4 im, floa
 // bin by a hair (FP32 error, far below one bin) the neighbouring entry is taken instead.
 // Entry of the bin of the edge at signed coordinate u (detector coordinate kf, window-relative), with
 // u's endpoints ua, ub on the line lc; returns whether the estimate missed that bin.
-// v clamped to [0, hi] (hi >= 0) in one instruction: the median of v, 0 and hi.
-__device__ __forceinline__ int clamp_entry(int v, int hi)
-{
-    int r;
-    asm("v_med3_i32 %0, %1, 0, %2" : "=v"(r) : "v"(v), "v"(hi));
-    return r;
-}
-
 struct CumBin {
     float4 q;       // s A_k, s B_k, P_e, r_e
     float ua, ub;   // s U_k, s U_k+1 on the pixel's line
