@@ -480,8 +480,18 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float *__restrict__ 
     const size_t o = (size_t)blockIdx.x * 32 + tx;   // index in [c_out][tap][c_in]
     const size_t total = (size_t)cout * cin * 9;
     float s = 0.f;
-    if (o < total)
-        for (int k = ty; k < nsplit; k += 8) s += part[(size_t)k * total + o];
+    if (o < total) {
+        // eight of the lane's partials in flight at once, then added in split order
+        int k = ty;
+        for (; k + 56 < nsplit; k += 64) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(k + 8 * u) * total + o];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; k < nsplit; k += 8) s += part[(size_t)k * total + o];
+    }
     red[ty][tx] = s;
     __syncthreads();
     if (ty == 0 && o < total) {
@@ -506,7 +516,17 @@ __global__ __launch_bounds__(256) void k_bias_part(const bf16 *__restrict__ dz, 
     const int cg = threadIdx.x % ng, pl = threadIdx.x / ng;
     const int pb = blockIdx.x * pps, pe = min(pb + pps, npix);
     float sum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int p = pb + pl; p < pe; p += nl) {
+    int p = pb + pl;
+    for (; p + 3 * nl < pe; p += 4 * nl) {   // four of the lane's pixels in flight, added in pixel order
+        bf16x8 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = *reinterpret_cast<const bf16x8 *>(dz + (size_t)(p + u * nl) * c + 8 * cg);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) sum[i] += (float)v[u][i];
+    }
+    for (; p < pe; p += nl) {
         const bf16x8 v = *reinterpret_cast<const bf16x8 *>(dz + (size_t)p * c + 8 * cg);
 #pragma unroll
         for (int i = 0; i < 8; ++i) sum[i] += (float)v[i];
@@ -532,8 +552,18 @@ __global__ __launch_bounds__(256) void k_sum_parts(const float *__restrict__ par
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     const int i = blockIdx.x * 32 + tx;
     float s = 0.f;
-    if (i < n)
-        for (int k = ty; k < nsplit; k += 8) s += part[(size_t)k * n + i];
+    if (i < n) {
+        // eight of the lane's partials in flight at once, then added in split order
+        int k = ty;
+        for (; k + 56 < nsplit; k += 64) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(k + 8 * u) * n + i];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; k < nsplit; k += 8) s += part[(size_t)k * n + i];
+    }
     red[ty][tx] = s;
     __syncthreads();
     if (ty == 0 && i < n) {
