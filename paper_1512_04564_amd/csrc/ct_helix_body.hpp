@@ -345,18 +345,32 @@ __host__ __device__ inline void reg26(const HelixUpdate &U, const Ro<float> &X, 
     gr = 0.f;
     dr = 0.f;
     const float bnd[4] = {0.f, U.beta, U.beta * 0.70710678118654752f, U.beta * 0.57735026918962576f};
-    for (int dz = -1; dz <= 1; ++dz) {
-        const int k2 = kz + dz;
-        if (k2 < 0 || k2 >= U.nz) continue;
-        for (int di = -1; di <= 1; ++di) {
-            const int i2 = i + di;
-            if (i2 < 0 || i2 >= U.ny) continue;
+    // Every neighbour's value is loaded before the first term (one memory latency, not one per neighbour):
+    // a neighbour outside the volume reads the voxel itself and takes weight 0, so that its term
+    // (difference 0) leaves both sums unchanged; the terms are added in the same order as the loops.
+    const size_t idx = ((size_t)kz * U.ny + i) * U.nx + j;
+    float xn[26];
+    unsigned in = 0u;
+    int q = 0;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int di = -1; di <= 1; ++di)
             for (int dj = -1; dj <= 1; ++dj) {
-                const int j2 = j + dj;
-                if (j2 < 0 || j2 >= U.nx) continue;
+                if (dz == 0 && di == 0 && dj == 0) continue;
+                const int k2 = kz + dz, i2 = i + di, j2 = j + dj;
+                const bool ok = k2 >= 0 && k2 < U.nz && i2 >= 0 && i2 < U.ny && j2 >= 0 && j2 < U.nx;
+                xn[q] = X[ok ? ((size_t)k2 * U.ny + i2) * U.nx + j2 : idx];
+                in |= ok ? 1u << q : 0u;
+                ++q;
+            }
+    q = 0;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int di = -1; di <= 1; ++di)
+            for (int dj = -1; dj <= 1; ++dj) {
+                if (dz == 0 && di == 0 && dj == 0) continue;
                 const int n = dz * dz + di * di + dj * dj;
-                if (n == 0) continue;
-                const float t = xc - X[((size_t)k2 * U.ny + i2) * U.nx + j2];
+                const float b = (in >> q) & 1u ? bnd[n] : 0.f;
+                const float t = xc - xn[q];
+                ++q;
                 const float z = t / U.delta;
                 float om;
                 if (U.potential == 0) om = 1.f / sqrtf(fmaf(z, z, 1.f));
@@ -365,11 +379,9 @@ __host__ __device__ inline void reg26(const HelixUpdate &U, const Ro<float> &X, 
                     const float s = powf(fabsf(z), 0.8f);
                     om = fmaf(1.2f, s, 2.f) / (2.f * (1.f + s) * (1.f + s));
                 }
-                gr = fmaf(bnd[n] * om, t, gr);
-                dr = fmaf(bnd[n], 2.f * (U.huber ? om : 1.f), dr);
+                gr = fmaf(b * om, t, gr);
+                dr = fmaf(b, 2.f * (U.huber ? om : 1.f), dr);
             }
-        }
-    }
 }
 
 // Clipped x-step at one voxel: x+ = max(0, (gamma + D_R x - grad R) / (rho D_L + D_R)), gamma = (rho - 1) g + rho h.
