@@ -200,7 +200,8 @@ __global__ __launch_bounds__(HUPD_T * HUPD_T) void k_hupd(HelixUpdate U, int mod
             float rho = rho_a;
             if (mode == HUPD_FULL) {
                 const float z = zeta[idx];
-                const float gn = rho_a / (rho_a + 1.f) * fmaf(U.alpha, z, (1.f - U.alpha) * g) + g / (rho_a + 1.f);
+                const float inv1 = hx_rcp(rho_a + 1.f);
+                const float gn = rho_a * inv1 * fmaf(U.alpha, z, (1.f - U.alpha) * g) + g * inv1;
                 hh = fmaf(U.alpha, fmaf(d, xc, -z), (1.f - U.alpha) * hh);
                 g = gn;
                 gv[idx] = g;
@@ -505,6 +506,7 @@ ct_status ct_helix_solve(ct_helix *h, const ct_rlalm_params *p, const float *y, 
     U.potential = p->potential;
     U.huber = p->huber;
     U.delta = (float)p->delta;
+    U.idelta = 1.f / U.delta;
     U.beta = (float)p->beta;
     // D_L = dl_scale * sum_m A_m' (w_m .* A_m 1)
     for (int m = 0; m < M; ++m) {

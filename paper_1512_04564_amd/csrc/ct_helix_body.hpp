@@ -85,6 +85,16 @@ struct HelixDev {
 
 __host__ __device__ inline int hx_min(int a, int b) { return a < b ? a : b; }
 
+// Approximate reciprocal square root (one ulp on the device), for the potentials' weights.
+__host__ __device__ inline float hx_rsqrt(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rsqf(x);
+#else
+    return 1.f / sqrtf(x);
+#endif
+}
+
 // Approximate reciprocal (one ulp on the device), for weights and candidate ranges.
 __host__ __device__ inline float hx_rcp(float x)
 {
@@ -334,6 +344,7 @@ struct HelixUpdate {
     float alpha;
     int potential, huber;
     float delta, beta;
+    float idelta;   // 1 / delta, rounded once on the host
 };
 
 // The 26-neighbour regularizer at voxel (kz, i, j) of X (canonical [nz][ny][nx]): gradient and Huber
@@ -371,10 +382,10 @@ __host__ __device__ inline void reg26(const HelixUpdate &U, const Ro<float> &X, 
                 const float b = (in >> q) & 1u ? bnd[n] : 0.f;
                 const float t = xc - xn[q];
                 ++q;
-                const float z = t / U.delta;
+                const float z = t * U.idelta;
                 float om;
-                if (U.potential == 0) om = 1.f / sqrtf(fmaf(z, z, 1.f));
-                else if (U.potential == 1) om = 1.f / (1.f + fabsf(z));
+                if (U.potential == 0) om = hx_rsqrt(fmaf(z, z, 1.f));
+                else if (U.potential == 1) om = hx_rcp(1.f + fabsf(z));
                 else {
                     const float s = powf(fabsf(z), 0.8f);
                     om = fmaf(1.2f, s, 2.f) / (2.f * (1.f + s) * (1.f + s));
@@ -389,7 +400,7 @@ __host__ __device__ inline float xstep(float rho, float x, float gv, float h, fl
 {
     const float gamma = fmaf(rho - 1.f, gv, rho * h);
     const float curv = fmaf(rho, dl, dr);
-    const float xn = curv > 0.f ? (gamma + fmaf(dr, x, -gr)) / curv : x;
+    const float xn = curv > 0.f ? (gamma + fmaf(dr, x, -gr)) * hx_rcp(curv) : x;
     return fmaxf(xn, 0.f);
 }
 

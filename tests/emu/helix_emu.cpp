@@ -189,6 +189,7 @@ int hemu_reg(int nx, int ny, int nz, const float *x, int potential, double delta
     U.potential = potential;
     U.huber = huber;
     U.delta = (float)delta;
+    U.idelta = 1.f / U.delta;
     U.beta = (float)beta;
     const size_t nvox = (size_t)nx * ny * nz;
     reset_oob();
